@@ -1,0 +1,175 @@
+"""Pins for the oracle's Cholesky/CholeskyQR2 (O3) and priming loops (O4-O6)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ppca_oracle as O
+from synthdata import make_problem, gaussian_block
+
+
+def _householder_q(a):
+    q, r = np.linalg.qr(a)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1
+    return q * s[None, :], r * s[:, None]
+
+
+def test_cholesky_vs_numpy():
+    rng = np.random.default_rng(10)
+    a = rng.standard_normal((20, 20))
+    a = a @ a.T + 0.1 * np.eye(20)
+    r = O.cholesky_upper(a)
+    assert np.allclose(r, np.triu(r))
+    assert np.allclose(r.T, np.linalg.cholesky(a), rtol=1e-12, atol=1e-12)
+
+
+def test_cholesky_not_spd():
+    v = np.random.default_rng(11).standard_normal((10, 3))
+    v[:, 2] = v[:, 1]
+    with pytest.raises(O.NotSPD):
+        O.cholesky_upper(v.T @ v - 1e-12 * np.eye(3))
+    with pytest.raises(O.NotSPD):
+        O.cholesky_upper(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    with pytest.raises(O.NotSPD):
+        O.cholesky_upper(np.array([[np.nan]]))
+
+
+def test_solve_right_upper():
+    rng = np.random.default_rng(12)
+    r = np.triu(rng.standard_normal((6, 6))) + 4 * np.eye(6)
+    z = rng.standard_normal((15, 6))
+    q = O.solve_right_upper(z, r)
+    assert np.allclose(q @ r, z, atol=1e-13)
+
+
+def test_cholqr2_vs_householder():
+    rng = np.random.default_rng(13)
+    a = rng.standard_normal((200, 12)) @ np.diag(np.logspace(0, -6, 12))
+    q, r = O.cholqr2(a)
+    qh, rh = _householder_q(a)
+    assert np.linalg.norm(q.T @ q - np.eye(12)) < 1e-14 * 12
+    assert np.allclose(q @ r, a, atol=1e-13)
+    assert np.allclose(q, qh, atol=1e-9)
+    assert np.allclose(r, rh, rtol=1e-9, atol=1e-15)
+
+
+def test_power_equals_qr_of_matrix_power():
+    """V_t is the Q factor (positive diagonal) of (X^T X)^t V_0, column by
+    column, because products of upper-triangular factors stay triangular."""
+    p = make_problem(400, 10, "exp0.9", seed=3, mode="gaussian", dtype=np.float64)
+    x = p.x - p.x.mean(axis=0)
+    v0 = gaussian_block(10, 4, 99, np.float64)
+    m = x.T @ x
+    for t in (1, 2, 3):
+        vt, grams = O.prime_power(x, v0, t)
+        ref, _ = _householder_q(np.linalg.matrix_power(m, t) @ _householder_q(v0)[0])
+        assert np.allclose(vt, ref, atol=1e-10)
+        assert len(grams) == t
+
+
+def test_power_fixed_point_and_gram():
+    p = make_problem(500, 12, "exp0.9", seed=4, mode="exact", dtype=np.float64)
+    x = p.x - O.column_means(p.x)[None, :]
+    u = p.q[:, :3]
+    vt, grams = O.prime_power(x, u, 4)
+    assert np.allclose(np.abs(np.sum(vt * u, axis=0)), 1.0, atol=1e-12)
+    # G_{t-1} = V^T X^T X V: the Rayleigh quotients times n
+    assert np.allclose(np.diag(grams[-1]) / 500, p.lam[:3], rtol=1e-10)
+
+
+def test_power_rate_bound():
+    p = make_problem(800, 16, "exp0.9", seed=5, mode="exact", dtype=np.float64)
+    x = p.x - O.column_means(p.x)[None, :]
+    kk = 4
+    v0 = gaussian_block(16, kk, 5, np.float64)
+    u = p.q[:, :kk]
+    q0 = O.cholqr2(v0)[0]
+    c0 = np.linalg.svd(u.T @ q0, compute_uv=False).min()
+    tan0 = math.sqrt(1 - c0 ** 2) / c0
+    ratio = p.lam[kk] / p.lam[kk - 1]
+    for t in (1, 3, 6):
+        vt, _ = O.prime_power(x, v0, t)
+        assert O.sin_theta_max(vt, u) <= ratio ** t * tan0 * (1 + 1e-9) + 1e-13
+
+
+def test_sanger_matrix_form_equals_printed_rule():
+    rng = np.random.default_rng(14)
+    xb = rng.standard_normal((7, 5))
+    v = rng.standard_normal((5, 3))
+    z, g = O.stream_pass(xb, v)
+    assert np.allclose(O.sanger_direction(z, g, v, 7), O.sanger_per_sample(xb, v), atol=1e-13)
+
+
+def test_sanger_fixed_point_full_batch():
+    p = make_problem(300, 8, "exp0.9", seed=6, mode="exact", dtype=np.float64)
+    x = p.x - O.column_means(p.x)[None, :]
+    u = p.q[:, :3]
+    z, g = O.stream_pass(x, u)
+    assert np.max(np.abs(O.sanger_direction(z, g, u, 300))) < 1e-12
+
+
+def test_eigengame_grad_finite_differences():
+    rng = np.random.default_rng(15)
+    b, d, kk = 11, 6, 4
+    xb = rng.standard_normal((b, d))
+    v = rng.standard_normal((d, kk))
+    m = xb.T @ xb / b
+    z, g = O.stream_pass(xb, v)
+    grad = O.eigengame_grad(z, g, b)
+    h = 1e-6
+    for j in range(kk):
+        for i in range(d):
+            vp = v.copy(); vp[i, j] += h
+            vm = v.copy(); vm[i, j] -= h
+            fd = (O.eigengame_utility(m, vp, j) - O.eigengame_utility(m, vm, j)) / (2 * h)
+            assert fd == pytest.approx(grad[i, j], rel=1e-6, abs=1e-8)
+
+
+def test_eigengame_fixed_point():
+    p = make_problem(300, 8, "exp0.9", seed=7, mode="exact", dtype=np.float64)
+    x = p.x - O.column_means(p.x)[None, :]
+    u = p.q[:, :3]
+    z, g = O.stream_pass(x, u)
+    grad = O.eigengame_grad(z, g, 300)
+    riem = grad - u * np.sum(u * grad, axis=0)[None, :]
+    assert np.max(np.abs(riem)) < 1e-12
+    v, _ = O.prime_eigengame(x, u, batch=300, steps=3, eta0=0.5, orthonormalise_start=False)
+    assert np.allclose(np.abs(np.sum(v * u, axis=0)), 1.0, atol=1e-12)
+
+
+def test_momentum_matches_torch_sgd_nesterov():
+    """Sec. 5 trains with SGD + Nesterov momentum 0.9; the oracle's update is
+    pinned to torch.optim.SGD (ascent: the gradient handed to torch is -g)."""
+    rng = np.random.default_rng(16)
+    x = rng.standard_normal((64, 6))
+    v0 = rng.standard_normal((6, 3))
+    eta, mu = 0.01, 0.9
+    v_or, _ = O.prime_oja(x, v0, batch=16, steps=5, eta0=eta, t0=0.0, momentum=mu,
+                          nesterov=True, orthonormalise_start=False)
+    p = torch.tensor(v0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.SGD([p], lr=eta, momentum=mu, nesterov=True)
+    for t in range(5):
+        xb = x[O.minibatch_rows(64, 16, t)]
+        vv = p.detach().numpy()
+        z, g = O.stream_pass(xb, vv)
+        p.grad = torch.from_numpy(-O.sanger_direction(z, g, vv, 16))
+        opt.step()
+    assert np.allclose(v_or, p.detach().numpy(), atol=1e-13)
+
+
+def test_schedule_and_rows():
+    assert O.learning_rate(0.1, 1000, 0) == 0.1
+    assert O.learning_rate(0.1, 1000, 1000) == pytest.approx(0.05)
+    assert O.learning_rate(0.1, 0, 5000) == 0.1
+    assert list(O.minibatch_rows(10, 4, 2)) == [8, 9, 0, 1]
+
+
+def test_oja_converges_on_easy_problem():
+    p = make_problem(4000, 10, "paper-exp", seed=8, mode="exact", dtype=np.float64)
+    x = p.x - O.column_means(p.x)[None, :]
+    x = x / math.sqrt(p.lam[0])
+    v, _ = O.prime_oja(x, gaussian_block(10, 3, 1, np.float64), batch=100, steps=1500, eta0=0.2, t0=0)
+    ang = O.angles(v, p.q[:, :3])
+    assert np.all(ang < 0.05)
