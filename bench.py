@@ -1,0 +1,275 @@
+"""Benchmark of the pPCA hot path on one MI355X.
+
+Workload (default): bf16 storage, n = 2,000,000, d = 2048, lambda_i = 0.9^i,
+k = 64, l = 64 (K = 128); one step = block power priming for 15 iterations
+(each a full pass over X with CholeskyQR2) + the pPCA projection pass + the
+128 x 128 float64 Rayleigh-Ritz step.  Synthetic data, generated on the GPU.
+
+Prints one JSON line:
+  value        X-stream GB/s = passes * n * d * 2 bytes / step time
+  roofline     the dominant streaming kernel against the 8 TB/s HBM peak,
+               timed with HIP events inside the library on the launch stream
+  time_to_1e-3 wall time until the max relative eigenvalue error of the top
+               k is <= 1e-3: primed bf16 (power + pPCA step) vs plain float32
+               power iteration (K = k, Rayleigh quotients) on the same data
+  cpu_baseline the float64 oracle on a bounded row sample, on the host cores
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("X-stream GB/s + time to 1e-3 eigval err, primed BF16/FP8 vs plain FP32 power, 1 GPU")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--d", type=int, default=2048)
+    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--l", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=15)
+    ap.add_argument("--storage", choices=["bf16", "fp8", "f32"], default="bf16")
+    ap.add_argument("--spectrum", default="exp0.9")
+    ap.add_argument("--seed", type=int, default=1003)
+    ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=20000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2109_03709_amd as P
+    from synthdata import gaussian_block, make_problem_device
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, d, k, l, iters = a.n, a.d, a.k, a.l, a.iters
+    K = k + l
+    P.set_chunk_rows(a.chunk_rows)
+
+    log(f"generating X: n={n} d={d} spectrum={a.spectrum}")
+    t0 = time.perf_counter()
+    xraw, lam, q = make_problem_device(n, d, a.spectrum, a.seed, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f}s")
+
+    code = {"bf16": P.BF16, "fp8": P.FP8_E4M3, "f32": P.F32}[a.storage]
+    es = {"bf16": 2, "fp8": 1, "f32": 4}[a.storage]
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    X, _ = P.center_quantize(xraw, code)
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - tp) * 1e3
+    # float32 centred copy for the plain baseline (in place)
+    Xf, _ = P.center_quantize(xraw, P.F32, out=xraw)
+    torch.cuda.synchronize()
+    log(f"centred + stored as {a.storage} in {prep_ms:.1f} ms")
+
+    v0 = torch.from_numpy(gaussian_block(d, K, a.seed + 1000, np.float32)).to(dev)
+    ws_pow = torch.empty(P.workspace_bytes(P.OP_POWER, X, K), dtype=torch.uint8, device=dev)
+    ws_prj = torch.empty(P.workspace_bytes(P.OP_PROJECT, X, K), dtype=torch.uint8, device=dev)
+    ws_rr = torch.empty(P.workspace_bytes(P.OP_RR, X, K), dtype=torch.uint8, device=dev)
+    V = torch.empty_like(v0)
+
+    def step():
+        V.copy_(v0)
+        P.prime_power(X, k, l, iters, V, ws=ws_pow)
+        G, B = P.project_gram(X, K, V, ws=ws_prj)
+        return P.rayleigh_ritz(X, K, k, G, B, V, ws=ws_rr)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.set_kernel_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ev, E = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P_stats = [P.kernel_stats(0), P.kernel_stats(1)]
+    P.set_kernel_timing(False)
+    ms_per_step = dt * 1e3 / a.steps
+    passes = iters + 1
+    xbytes = n * d * es
+    value = passes * xbytes / (ms_per_step * 1e-3) / 1e9
+    log(f"{ms_per_step:.2f} ms/step, X-stream {value:.1f} GB/s")
+
+    # accuracy of the timed result against the exact spectrum of the data
+    evh = ev.cpu().numpy()
+    rel = float(np.max(np.abs(evh - lam[:k]) / lam[:k]))
+    Eh = E.cpu().numpy().astype(np.float64)
+    qe = np.linalg.qr(Eh)[0]
+    sin_t = float(np.linalg.norm(qe - q[:, :k] @ (q[:, :k].T @ qe), 2))
+
+    # roofline of the dominant streaming kernel
+    names = ["ppca_xv (Y = X V')", "ppca_xty ([X|Y]^T Y)"]
+    Kp = int(math.ceil(K / 16) * 16)
+    ybytes = n * Kp * (4 if a.storage == "f32" else 2)
+    alg = [xbytes + ybytes, xbytes + ybytes]  # X read + Y write / X read + Y read
+    avg = [s[1] / max(s[0], 1) for s in P_stats]
+    dom = int(np.argmax([s[1] for s in P_stats]))
+    achieved = alg[dom] / (avg[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": names[dom], "avg_ms": round(avg[dom], 4),
+                "launches": P_stats[dom][0],
+                "other_kernel": {"kernel": names[1 - dom], "avg_ms": round(avg[1 - dom], 4),
+                                 "achieved_GBs": round(alg[1 - dom] / max(avg[1 - dom], 1e-9)
+                                                       / 1e6, 1)}}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": a.storage, "data": "synthetic",
+           "config": {"workload": f"ppca-power-{a.storage}", "n": n, "d": d, "k": k, "l": l,
+                      "power_iters": iters, "spectrum": a.spectrum, "passes_per_step": passes,
+                      "chunk_rows": a.chunk_rows},
+           "accuracy": {"max_rel_eig_err": rel, "sin_theta_max": sin_t},
+           "prep_ms": round(prep_ms, 2),
+           "roofline": roofline}
+
+    if not a.no_tta:
+        out["time_to_1e-3"] = time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch)
+    if a.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel()
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(X, k, l, iters, a.cpu_rows, v0, es)
+    print(json.dumps(out), flush=True)
+
+
+def _timed(torch, fn, reps=3):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch, cap=80):
+    K = k + l
+    # primed path: evaluate the pPCA result of every iterate V_t (from G_t, B_t)
+    gh = torch.zeros((iters, K, K), dtype=torch.float64, device=dev)
+    bh = torch.zeros_like(gh)
+    V = v0.clone()
+    P.prime_power(X, k, l, iters, V, gram_hist=gh, b_hist=bh)
+    t_star = None
+    errs = []
+    for t in range(iters):
+        ev, _ = P.rayleigh_ritz(X, K, k, gh[t].contiguous(), bh[t].contiguous(), V, vectors=False)
+        e = float(np.max(np.abs(ev.cpu().numpy() - lam[:k]) / lam[:k]))
+        errs.append(e)
+        if e <= 1e-3 and t_star is None:
+            t_star = t
+    res = {"primed_errors": [float(f"{e:.3e}") for e in errs]}
+    if t_star is not None:
+        Vw = torch.empty_like(v0)
+
+        def primed():
+            Vw.copy_(v0)
+            P.prime_power(X, k, l, t_star, Vw)
+            G, B = P.project_gram(X, K, Vw)
+            P.rayleigh_ritz(X, K, k, G, B, Vw)
+        res["primed_ms"] = round(_timed(torch, primed), 3)
+        res["primed_iters"] = t_star
+    # plain float32 power iteration, K = k, Rayleigh quotients of V_t
+    v0k = v0[:, :k].contiguous()
+    ghp = torch.zeros((cap, k, k), dtype=torch.float64, device=dev)
+    Vp = v0k.clone()
+    P.prime_power(Xf, k, 0, cap, Vp, gram_hist=ghp)
+    n = X.n
+    tp = None
+    perr = []
+    for t in range(cap):
+        rq = np.diag(ghp[t].cpu().numpy()) / n
+        e = float(np.max(np.abs(rq - lam[:k]) / lam[:k]))
+        perr.append(e)
+        if e <= 1e-3:
+            tp = t
+            break
+    res["plain_errors_tail"] = [float(f"{e:.3e}") for e in perr[-3:]]
+    if tp is not None:
+        Vq = torch.empty_like(v0k)
+
+        def plain():
+            Vq.copy_(v0k)
+            P.prime_power(Xf, k, 0, tp + 1, Vq)
+        res["plain_fp32_ms"] = round(_timed(torch, plain), 3)
+        res["plain_iters"] = tp + 1
+    else:
+        res["plain_fp32_ms"] = None
+        res["plain_note"] = f"not reached within {cap} iterations"
+    if res.get("primed_ms") and res.get("plain_fp32_ms"):
+        res["speedup"] = round(res["plain_fp32_ms"] / res["primed_ms"], 2)
+    return res
+
+
+def cpu_baseline(X, k, l, iters, rows, v0, es):
+    """The float64 oracle (as it stands) on the first `rows` rows of the
+    stored data: the same priming iterations, projection and Rayleigh-Ritz."""
+    import torch
+    from oracle import ppca_oracle as O
+    rows = min(rows, X.n)
+    if X.dtype == 1:
+        xs = O.bf16_value(X.x[:rows].contiguous().view(torch.int16).cpu().numpy().view(np.uint16))
+    elif X.dtype == 2:
+        xs = O.e4m3_value(X.x[:rows].contiguous().cpu().numpy()) * \
+            X.col_scale.cpu().numpy().astype(np.float64)[None, :]
+    else:
+        xs = X.x[:rows].cpu().numpy().astype(np.float64)
+    vh = v0.cpu().numpy().astype(np.float64)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() \
+            else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    v, _ = O.prime_power(xs, vh, iters)
+    O.ppca(xs, v, k)
+    dt = time.perf_counter() - t0
+    passes = iters + 1
+    gbs = passes * rows * X.d * es / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "sample": f"first {rows} rows of the stored data (d={X.d}, K={k + l}); "
+                      f"{iters} power iterations + projection + Rayleigh-Ritz in float64 numpy; "
+                      f"GB/s counts {es}-byte stored elements per pass like the GPU value"}
+
+
+if __name__ == "__main__":
+    main()

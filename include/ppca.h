@@ -1,0 +1,221 @@
+/*
+ * ppca.h -- C ABI of the primed-PCA (pPCA) hot path for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Primed PCA ("Speeding up PCA with priming", Alg. 1): a cheap approximate
+ * PCA method (the priming) produces K = k + l directions V (Sec. 3.3), the
+ * data is projected on span(V) and an exact PCA of the projected data
+ * returns the first k principal components.  This library implements the
+ * data-parallel passes of that method on the GPU:
+ *
+ *   ppca_center_quantize   centre the data and store it as f32 / bf16 / fp8
+ *   ppca_prime_power       block power (subspace) iteration with CholeskyQR2
+ *   ppca_prime_oja         minibatch Oja / Sanger rule
+ *   ppca_prime_eigengame   minibatch EigenGame utility ascent
+ *   ppca_project_gram      Y = X V', G = Y^T Y, B = V'^T V'   (Alg. 1 steps 2-3)
+ *   ppca_rayleigh_ritz     full PCA of the projected data      (Alg. 1 step 4)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a device pointer (HIP global memory) that
+ * the caller owns; the library never allocates or frees memory and keeps no
+ * state between calls.  Scratch space is the caller-provided workspace
+ * `ws` of `ws_bytes` bytes (256-byte aligned); its required size is returned
+ * by ppca_workspace_bytes().  Workspace contents are undefined between calls.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the legacy default stream).
+ * Every call validates its arguments on the host, enqueues its kernels on
+ * `stream`, waits for the stream to drain and returns a status: device-side
+ * failures (non-positive Cholesky pivot, non-finite values, eigensolver sweep
+ * cap) are reported through a status word kept in the workspace.  Calls on
+ * different streams with different workspaces may run concurrently; two
+ * calls that share a workspace must not overlap.
+ *
+ * Layouts.  X is row-major n x d with row stride `ld` elements (ld >= d).
+ * The base pointer must be 16-byte aligned and ld * element_size must be a
+ * multiple of 16 bytes.  V, Z and E are row-major d x K float32 (V[j*K+c]).
+ * Gram matrices G and B are row-major K x K float64.
+ *
+ * Signs and order.  Eigenvalues are returned in descending order; each
+ * returned eigenvector column is flipped so that its largest-magnitude
+ * entry is positive (ties: lowest row index).  Eigenvectors of repeated
+ * eigenvalues are any orthonormal basis of their eigenspace.
+ *
+ * Errors.  No entry point throws or aborts; outputs are unspecified when the
+ * status is not PPCA_OK.
+ */
+#ifndef PPCA_H
+#define PPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PPCA_OK                  0
+#define PPCA_ERR_ARG            (-1)  /* invalid size, pointer, count or parameter */
+#define PPCA_ERR_DTYPE          (-2)  /* unknown dtype, or col_scale given/missing wrongly */
+#define PPCA_ERR_NOT_SPD        (-3)  /* a Cholesky pivot <= K*eps*a_jj: V (or Z) is rank deficient */
+#define PPCA_ERR_NONFINITE      (-4)  /* NaN/Inf met in a Gram matrix or in Z */
+#define PPCA_ERR_NO_CONVERGENCE (-5)  /* Jacobi eigensolver reached its sweep cap */
+#define PPCA_ERR_WORKSPACE      (-6)  /* ws is NULL, misaligned or smaller than required */
+#define PPCA_ERR_HIP            (-7)  /* a HIP runtime call failed */
+#define PPCA_ERR_ALIGN          (-8)  /* X base or row stride violates the 16-byte rule */
+
+/* ---- storage types of X ------------------------------------------------- */
+#define PPCA_F32       0   /* float32 */
+#define PPCA_BF16      1   /* bfloat16 (bits of the upper half of a float32) */
+#define PPCA_FP8_E4M3  2   /* OCP fp8 e4m3 "fn" (bias 7, max 448, no inf) with per-column
+                              float32 scales: the value of x_ij is code_ij * col_scale[j] */
+
+/* ---- workspace query operations ------------------------------------------ */
+#define PPCA_OP_CENTER      0
+#define PPCA_OP_POWER       1
+#define PPCA_OP_OJA         2
+#define PPCA_OP_EIGENGAME   3
+#define PPCA_OP_PROJECT     4
+#define PPCA_OP_RR          5
+#define PPCA_OP_STREAM      6
+
+/* Largest K = k + l supported by the kernels. */
+#define PPCA_MAX_K 128
+
+/* A centred data matrix as the GPU path sees it. */
+typedef struct {
+  const void*  x;          /* device, row-major n x d, row stride ld (elements) */
+  int64_t      n;          /* rows (data points), n >= 1 */
+  int64_t      d;          /* columns (dimension), d >= 1 */
+  int64_t      ld;         /* row stride in elements, ld >= d */
+  int32_t      dtype;      /* PPCA_F32, PPCA_BF16 or PPCA_FP8_E4M3 */
+  const float* col_scale;  /* device [d]; required for PPCA_FP8_E4M3, NULL otherwise */
+} ppca_matrix;
+
+/* Minibatch schedule and optimiser of the SGD-style primings (Sec. 2.2,
+ * Sec. 2.3 and the training setup of Sec. 5: SGD, optionally with
+ * (Nesterov) momentum).  Step t (counted from start_step) uses the rows
+ * (t*batch + i) mod n, i < batch, and the rate eta_t = eta0 / (1 + t/t0)
+ * (t0 <= 0: constant eta0).  With momentum mu > 0 the buffer follows
+ * buf <- mu*buf + g and the step is g + mu*buf (Nesterov) or buf. */
+typedef struct {
+  int32_t  batch;           /* b, 1 <= b <= n */
+  int64_t  steps;           /* number of minibatch steps T >= 0 */
+  double   eta0;            /* > 0 and finite */
+  double   t0;              /* decay constant of the rate; <= 0 for a constant rate */
+  double   momentum;        /* mu in [0, 1) */
+  int32_t  nesterov;        /* 0 or 1 */
+  int64_t  start_step;      /* global index of the first step (resume), >= 0 */
+  float*   mom_buf;         /* device d x K float32 in/out (zero to start); required iff mu > 0 */
+  int32_t  snapshot_every;  /* m > 0: copy V after every m-th step into snapshots */
+  float*   snapshots;       /* device [floor(steps/m)][d*K] or NULL */
+  int32_t  orthonormalise_start; /* 1: V <- CholQR2(V) before the first step */
+} ppca_sgd_params;
+
+/* Centre a float32 matrix and store it in the requested type (the paper
+ * assumes a centred dataset, Sec. 1).  mu_j = (sum_r x_rj) / n with the sum
+ * taken in double-double arithmetic and rounded once (order independent);
+ * c_rj = float32(double(x_rj) - mu_j).  PPCA_F32 stores c; PPCA_BF16 stores
+ * the nearest bf16 of c (ties to even); PPCA_FP8_E4M3 stores the nearest
+ * e4m3 of float32(c_rj / s_j) (ties to even, saturating at +-448) with
+ * s_j = float32(max_r |c_rj| / 448) (1 for an all-zero column) written to
+ * col_scale.  x: device float32 [n][ldx]; out: device [n][ldo] of out_dtype;
+ * mean: device double [d] (may be NULL); col_scale: device float [d],
+ * required iff out_dtype is fp8.  x and out must not overlap unless both
+ * are float32 with ldx == ldo (in-place centring). */
+int ppca_center_quantize(const float* x, int64_t n, int64_t d, int64_t ldx,
+                         int32_t out_dtype, void* out, int64_t ldo,
+                         float* col_scale, double* mean,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Block power priming (Sec. 2.1, block form of the cited simultaneous
+ * iteration): V_0 = CholQR2(V); for t = 1..iters: one pass over X gives
+ * Y = X V'_{t-1}, Z = X^T Y (float32 accumulation) and G_{t-1} = Y^T Y
+ * (float64 across row panels); V_t = CholQR2(Z) in float64.
+ * V: device d x K float32, in = starting directions (full rank), out = V_iters
+ * (orthonormal columns).  K = k + l with 1 <= k, 0 <= l, K <= min(d, n, 128).
+ * gram_hist / b_hist (optional, device [iters][K*K] float64): G_{t-1} and
+ * B_{t-1} = V'^T V' of the operand V' that multiplied X in pass t, so that
+ * the Ritz values of every iterate can be evaluated afterwards. */
+int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters,
+                     float* V, double* gram_hist, double* b_hist,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Minibatch Sanger / generalised Oja priming (Sec. 2.2): for each step the
+ * minibatch mean of dw_m = y_m (x - sum_{l<=m} y_l w_l), in matrix form
+ * g = (Z_b - V triu(G_b)) / b with Z_b = X_b^T X_b V', G_b = V'^T X_b^T X_b V';
+ * then V <- V + eta_t * step.  V: device d x K float32 in/out. */
+int ppca_prime_oja(const ppca_matrix* X, int32_t k, int32_t l,
+                   const ppca_sgd_params* p, float* V,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Minibatch EigenGame priming (Sec. 2.3, eqs. (1)-(3)) with
+ * M = X_b^T X_b / b: grad_j = dU_j/dv_j = (2/b)(Z_j - sum_{i<j} G_ij/G_ii Z_i),
+ * projected on the tangent space of the sphere (grad_j - (v_j.grad_j) v_j),
+ * stepped (with optional momentum) and every v_j renormalised to unit norm.
+ * All players update together from the same minibatch. */
+int ppca_prime_eigengame(const ppca_matrix* X, int32_t k, int32_t l,
+                         const ppca_sgd_params* p, float* V,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* One streaming pass over the rows r0, r0+1, ..., r0+nrows-1 (mod n) of X:
+ * the product every priming step is built from (power step of Sec. 2.1,
+ * minibatch steps of Sec. 2.2 and 2.3): Y = X V' (never stored in full),
+ * Z = X^T Y (d x K float32, float32 accumulation within a row split, float64
+ * across splits) and G = Y^T Y (K x K float64).  V' is the operand described
+ * at ppca_project_gram; Z and G are unnormalised sums over the rows.
+ * 0 <= r0 < n, 1 <= nrows.  Workspace: PPCA_OP_STREAM with batch = nrows. */
+int ppca_stream_pass(const ppca_matrix* X, int32_t K, const float* V, int64_t r0,
+                     int64_t nrows, float* Z, double* G,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Projection of the data on span(V) and its Gram matrix (Alg. 1 steps 2-3;
+ * Sec. 4.2: the variance of the projected data along v in S is v^T X^T X v).
+ * One pass over X: Y = X V' is never stored; G = Y^T Y (float64 across row
+ * panels), B = V_eff^T V_eff in float64, where V' is the operand that
+ * multiplied X (V itself for f32 data; bf16(V) for bf16 data;
+ * bf16(s_j V_jc) for fp8 data) and V_eff = V' (f32, bf16) or diag(1/s) V'
+ * (fp8), so that G = V_eff^T Xhat^T Xhat V_eff for the stored data Xhat.
+ * G, B: device K x K float64.  V: device d x K float32. */
+int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V,
+                      double* G, double* B, void* ws, size_t ws_bytes, void* stream);
+
+/* Rayleigh-Ritz: exact PCA of the projected data (Alg. 1 step 4).
+ * R = chol(B); H = R^-T G R^-1 / n; H = W Theta W^T (parallel Jacobi,
+ * float64); E = V_eff R^-1 W[:, :k].  X supplies n, d, dtype and col_scale
+ * (its data is not read), so that V_eff is rebuilt exactly as
+ * ppca_project_gram built it.  evals: device double [k] (descending);
+ * E: device d x k float32 (may be NULL to get the eigenvalues only). */
+int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k,
+                       const double* G, const double* B, const float* V,
+                       float* E, double* evals,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace needed by operation `op` (PPCA_OP_*) for data X with
+ * K directions and minibatch `batch` (rows of the pass for PPCA_OP_STREAM;
+ * ignored by the other non-minibatch operations).
+ * Returns 0 for invalid arguments. */
+size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch);
+
+/* Static description of a status code. */
+const char* ppca_strerror(int status);
+
+/* Optional per-kernel timing of the streaming kernels.  When enabled, the
+ * library records a pair of HIP events on the caller's stream around every
+ * launch of each streaming kernel and accumulates their elapsed times.
+ * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty).
+ * ppca_kernel_stats returns the number of launches and the total ms since
+ * the last reset.  Not thread safe; meant for benchmarks. */
+void ppca_set_kernel_timing(int32_t enable);
+int  ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Tuning knob of the streaming passes: rows per chunk (0 = whole pass in
+ * one launch pair).  Chunks bound the size of the Y staging buffer and keep
+ * a chunk of X resident in the last-level cache between the two kernels. */
+void ppca_set_chunk_rows(int64_t rows);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPCA_H */

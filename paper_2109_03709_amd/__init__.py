@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of the data-parallel hot path of primed PCA.
+
+The compute runs in the HIP library libppca.so (see include/ppca.h); this
+package is its thin Python binding.  Build with
+`python -m paper_2109_03709_amd.build`.
+"""
+from ._lib import (  # noqa: F401
+    BF16, F32, FP8_E4M3, MAX_K, OP_CENTER, OP_EIGENGAME, OP_OJA, OP_POWER, OP_PROJECT, OP_RR, OP_STREAM,
+    Data, PPCAError, center_quantize, kernel_stats, lib, ppca, prime_eigengame, prime_oja,
+    prime_power, project_gram, rayleigh_ritz, set_chunk_rows, set_kernel_timing, stream_pass, strerror,
+    workspace_bytes,
+)

@@ -1,0 +1,503 @@
+// Host orchestration and the C ABI of libppca (see include/ppca.h).
+//
+// Each entry point validates its arguments, carves the caller's workspace
+// into sub-buffers, enqueues the kernels of the step on the caller's stream,
+// waits for the stream and returns the device status word.
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "ppca_common.h"
+
+using namespace ppca;
+
+namespace {
+
+// ------------------------------------------------------------------ knobs
+std::atomic<int64_t> g_chunk_rows{0};
+std::mutex g_tmu;
+bool g_timing = false;
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+KStat g_stats[2];
+struct Pending {
+  hipEvent_t a, b;
+  int kernel;
+};
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t get_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void resolve_timings() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& p : g_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_stats[p.kernel].launches += 1;
+      g_stats[p.kernel].ms += ms;
+    }
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+}
+
+// Launch `f` bracketed by timing events when timing is on.
+template <typename F>
+hipError_t timed(int kernel, hipStream_t s, F&& f) {
+  if (!g_timing) return f();
+  hipEvent_t a, b;
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    a = get_event();
+    b = get_event();
+  }
+  if (!a || !b) return f();
+  hipEventRecord(a, s);
+  hipError_t e = f();
+  hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_pending.push_back({a, b, kernel});
+  return e;
+}
+
+// --------------------------------------------------------------- workspace
+constexpr size_t kAlign = 256;
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + kAlign - 1) / kAlign * kAlign;
+    return o;
+  }
+};
+
+int elem_size(int32_t dtype) { return dtype == PPCA_F32 ? 4 : dtype == PPCA_BF16 ? 2 : 1; }
+
+struct Plan {
+  // dimensions
+  int64_t n = 0, d = 0;
+  int K = 0, Kp = 0;
+  int64_t dp = 0;
+  int64_t rows_cap = 0;   // rows of the Y staging buffer
+  int ntiles = 0, nsplit = 0;
+  // offsets
+  size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, z = 0, g = 0, b = 0, gparts = 0,
+         a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
+         sums = 0, cmax = 0, mean = 0;
+  size_t total = 0;
+};
+
+int nsplit_for(int ntiles, int64_t rows) {
+  int64_t ns = 512 / ntiles;
+  if (ns < 8) ns = 8;
+  const int64_t by_rows = round_up(cdiv(rows, 64), 8);
+  if (ns > by_rows) ns = by_rows;
+  if (ns < 8) ns = 8;
+  return (int)round_up(ns, 8);
+}
+
+Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t batch) {
+  Plan p;
+  p.n = n;
+  p.d = d;
+  p.K = K;
+  p.Kp = (int)round_up(K, 16);
+  p.dp = round_up(d, 32);
+  Carve c;
+  p.status = c.take(256);
+  if (op == PPCA_OP_CENTER) {
+    const int nrb = prep_row_blocks(n);
+    p.sums = c.take((size_t)nrb * d * 2 * sizeof(double));
+    p.cmax = c.take((size_t)nrb * d * sizeof(float));
+    p.mean = c.take((size_t)d * sizeof(double));
+    p.total = c.off;
+    return p;
+  }
+  const int es_op = dtype == PPCA_F32 ? 4 : 2;
+  p.vop = c.take((size_t)p.Kp * p.dp * es_op);
+  p.veff = c.take((size_t)d * p.Kp * sizeof(double));
+  const size_t kk = (size_t)K * K * sizeof(double);
+  if (op == PPCA_OP_RR) {
+    p.r = c.take(kk);
+    p.rinv = c.take(kk);
+    p.t = c.take(kk);
+    p.h = c.take(kk);
+    p.w = c.take(kk);
+    p.ev = c.take((size_t)K * sizeof(double));
+    p.m = c.take(kk);
+    p.total = c.off;
+    return p;
+  }
+  int64_t pass_rows = n;
+  if (op == PPCA_OP_OJA || op == PPCA_OP_EIGENGAME || op == PPCA_OP_STREAM) pass_rows = batch;
+  const int64_t chunk = g_chunk_rows.load();
+  if (chunk > 0 && chunk < pass_rows) pass_rows = round_up(chunk, 256);
+  p.rows_cap = round_up(pass_rows, 256);
+  const int es_y = dtype == PPCA_F32 ? 4 : 2;
+  p.yb = c.take((size_t)p.rows_cap * p.Kp * es_y);
+  p.ntiles = xty_tiles(d, p.Kp);
+  p.nsplit = nsplit_for(p.ntiles, p.rows_cap);
+  p.part = c.take((size_t)p.ntiles * p.nsplit * p.Kp * 256 * sizeof(float));
+  p.z = c.take((size_t)d * K * sizeof(float));
+  p.g = c.take(kk);
+  p.b = c.take(kk);
+  p.gparts = c.take((size_t)gram_parts(d) * K * K * sizeof(double));
+  p.a = c.take(kk);
+  p.r = c.take(kk);
+  p.rinv = c.take(kk);
+  p.q1 = c.take((size_t)d * K * sizeof(double));
+  if (op == PPCA_OP_EIGENGAME) {
+    const int64_t nblk = cdiv(d, 16);
+    p.egs = c.take((size_t)(2 * d * K + 2 * nblk * K) * sizeof(double));
+  }
+  p.total = c.off;
+  return p;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+// ------------------------------------------------------------- validation
+int check_matrix(const ppca_matrix* X) {
+  if (!X || !X->x) return PPCA_ERR_ARG;
+  if (X->n < 1 || X->d < 1 || X->ld < X->d) return PPCA_ERR_ARG;
+  if (X->dtype != PPCA_F32 && X->dtype != PPCA_BF16 && X->dtype != PPCA_FP8_E4M3)
+    return PPCA_ERR_DTYPE;
+  if ((X->dtype == PPCA_FP8_E4M3) != (X->col_scale != nullptr)) return PPCA_ERR_DTYPE;
+  const int es = elem_size(X->dtype);
+  if ((reinterpret_cast<uintptr_t>(X->x) % 16) != 0 || ((X->ld * es) % 16) != 0)
+    return PPCA_ERR_ALIGN;
+  return PPCA_OK;
+}
+
+int check_k(const ppca_matrix* X, int K) {
+  if (K < 1 || K > PPCA_MAX_K || K > X->d || K > X->n) return PPCA_ERR_ARG;
+  return PPCA_OK;
+}
+
+int check_ws(void* ws, size_t ws_bytes, const Plan& p) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < p.total)
+    return PPCA_ERR_WORKSPACE;
+  return PPCA_OK;
+}
+
+#define HIP_TRY(expr)                          \
+  do {                                         \
+    if ((expr) != hipSuccess) return PPCA_ERR_HIP; \
+  } while (0)
+
+int finish(const Plan& p, void* ws, hipStream_t s) {
+  int h = 0;
+  if (hipMemcpyAsync(&h, at<int>(ws, p.status), sizeof(int), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return PPCA_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return PPCA_ERR_HIP;
+  if (g_timing) resolve_timings();
+  return h;
+}
+
+// ------------------------------------------------------------ building blocks
+StreamBufs bufs_of(const Plan& p, void* ws) {
+  StreamBufs b;
+  b.vop = at<void>(ws, p.vop);
+  b.dp = p.dp;
+  b.yb = at<void>(ws, p.yb);
+  b.part = at<float>(ws, p.part);
+  b.nsplit = p.nsplit;
+  b.Kp = p.Kp;
+  return b;
+}
+
+// One streaming pass over rows r0 .. r0+nrows-1 (mod n): Z (unless gram_only), G.
+int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t nrows, float* Z,
+             double* G, double* Gcopy, bool gram_only, hipStream_t s) {
+  PassDesc pd;
+  pd.x = X->x;
+  pd.n = X->n;
+  pd.d = X->d;
+  pd.ld = X->ld;
+  pd.dtype = X->dtype;
+  pd.col_scale = X->col_scale;
+  pd.r0 = r0;
+  pd.nrows = nrows;
+  StreamBufs b = bufs_of(p, ws);
+  const int64_t chunk = (p.rows_cap < nrows) ? p.rows_cap : nrows;
+  for (int64_t i0 = 0; i0 < nrows; i0 += chunk) {
+    const int64_t rows = (nrows - i0) < chunk ? (nrows - i0) : chunk;
+    HIP_TRY(timed(0, s, [&] { return launch_xv(pd, b, i0, rows, s); }));
+    HIP_TRY(timed(1, s, [&] { return launch_xty(pd, b, i0, rows, i0 > 0, gram_only, s); }));
+  }
+  HIP_TRY(launch_reduce_zg(b, X->d, p.K, X->dtype == PPCA_FP8_E4M3 ? X->col_scale : nullptr, Z, G,
+                           Gcopy, gram_only, at<int>(ws, p.status), s));
+  return PPCA_OK;
+}
+
+// V (d x K f32) <- CholQR2(A) for A (d x K f32); A and V may alias.
+int cholqr2(const float* A, float* V, int64_t d, int K, const Plan& p, void* ws, hipStream_t s) {
+  int* st = at<int>(ws, p.status);
+  double* gp = at<double>(ws, p.gparts);
+  double* Am = at<double>(ws, p.a);
+  double* R = at<double>(ws, p.r);
+  double* Ri = at<double>(ws, p.rinv);
+  double* Q1 = at<double>(ws, p.q1);
+  HIP_TRY(launch_gram(A, false, d, K, K, gp, Am, st, s));
+  HIP_TRY(launch_chol_inv(Am, K, R, Ri, st, s));
+  HIP_TRY(launch_trmm(A, false, d, K, K, Ri, Q1, true, K, st, s));
+  HIP_TRY(launch_gram(Q1, true, d, K, K, gp, Am, st, s));
+  HIP_TRY(launch_chol_inv(Am, K, R, Ri, st, s));
+  HIP_TRY(launch_trmm(Q1, true, d, K, K, Ri, V, false, K, st, s));
+  return PPCA_OK;
+}
+
+int make_operand(const ppca_matrix* X, const float* V, const Plan& p, void* ws, hipStream_t s) {
+  HIP_TRY(launch_make_operand(V, X->d, p.K, p.Kp, p.dp, X->dtype, X->col_scale,
+                              at<void>(ws, p.vop), at<double>(ws, p.veff), s));
+  return PPCA_OK;
+}
+
+// B = V_eff^T V_eff (K x K f64)
+int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipStream_t s) {
+  HIP_TRY(launch_gram(at<double>(ws, p.veff), true, X->d, p.K, p.Kp, at<double>(ws, p.gparts), B,
+                      at<int>(ws, p.status), s));
+  return PPCA_OK;
+}
+
+#define RET_IF(expr)            \
+  do {                          \
+    const int _rc = (expr);     \
+    if (_rc != PPCA_OK) return _rc; \
+  } while (0)
+
+int check_sgd(const ppca_matrix* X, const ppca_sgd_params* q) {
+  if (!q) return PPCA_ERR_ARG;
+  if (q->batch < 1 || q->batch > X->n || q->steps < 0 || q->start_step < 0) return PPCA_ERR_ARG;
+  if (!(q->eta0 > 0.0) || !isfinite(q->eta0) || !isfinite(q->t0)) return PPCA_ERR_ARG;
+  if (!(q->momentum >= 0.0 && q->momentum < 1.0)) return PPCA_ERR_ARG;
+  if (q->momentum > 0.0 && !q->mom_buf) return PPCA_ERR_ARG;
+  if (q->nesterov != 0 && q->nesterov != 1) return PPCA_ERR_ARG;
+  if (q->snapshot_every < 0) return PPCA_ERR_ARG;
+  if (q->snapshot_every > 0 && !q->snapshots) return PPCA_ERR_ARG;
+  return PPCA_OK;
+}
+
+int prime_sgd(bool eigengame, const ppca_matrix* X, int32_t k, int32_t l, const ppca_sgd_params* q,
+              float* V, void* ws, size_t ws_bytes, void* stream) {
+  RET_IF(check_matrix(X));
+  if (k < 1 || l < 0 || !V) return PPCA_ERR_ARG;
+  const int K = k + l;
+  RET_IF(check_k(X, K));
+  RET_IF(check_sgd(X, q));
+  const Plan p = make_plan(eigengame ? PPCA_OP_EIGENGAME : PPCA_OP_OJA, X->n, X->d, X->dtype, K,
+                           q->batch);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  if (q->orthonormalise_start) RET_IF(cholqr2(V, V, X->d, K, p, ws, s));
+  float* Z = at<float>(ws, p.z);
+  double* G = at<double>(ws, p.g);
+  const int64_t b = q->batch;
+  for (int64_t t = 0; t < q->steps; ++t) {
+    const int64_t gstep = q->start_step + t;
+    const int64_t r0 = (int64_t)(((__int128)gstep * b) % X->n);
+    RET_IF(make_operand(X, V, p, ws, s));
+    RET_IF(run_pass(X, p, ws, r0, b, Z, G, nullptr, false, s));
+    const double eta = q->t0 > 0.0 ? q->eta0 / (1.0 + (double)gstep / q->t0) : q->eta0;
+    if (eigengame) {
+      HIP_TRY(launch_eigengame_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
+                                      q->mom_buf, at<double>(ws, p.egs), st, s));
+    } else {
+      HIP_TRY(launch_sanger_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
+                                   q->mom_buf, st, s));
+    }
+    if (q->snapshot_every > 0 && (t + 1) % q->snapshot_every == 0) {
+      const int64_t slot = (t + 1) / q->snapshot_every - 1;
+      HIP_TRY(launch_copy_f32(V, q->snapshots + slot * X->d * K, X->d * K, s));
+    }
+  }
+  return finish(p, ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppca_center_quantize(const float* x, int64_t n, int64_t d, int64_t ldx, int32_t out_dtype,
+                         void* out, int64_t ldo, float* col_scale, double* mean, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!x || !out || n < 1 || d < 1 || ldx < d || ldo < d) return PPCA_ERR_ARG;
+  if (out_dtype != PPCA_F32 && out_dtype != PPCA_BF16 && out_dtype != PPCA_FP8_E4M3)
+    return PPCA_ERR_DTYPE;
+  if ((out_dtype == PPCA_FP8_E4M3) != (col_scale != nullptr)) return PPCA_ERR_DTYPE;
+  const bool same = (const void*)x == (const void*)out;
+  if (same && !(out_dtype == PPCA_F32 && ldx == ldo)) return PPCA_ERR_ARG;
+  const Plan p = make_plan(PPCA_OP_CENTER, n, d, out_dtype, 1, 0);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
+  HIP_TRY(launch_center_quantize(x, n, d, ldx, out_dtype, out, ldo, col_scale, mean,
+                                 at<double>(ws, p.sums), at<float>(ws, p.cmax),
+                                 at<double>(ws, p.mean), s));
+  return finish(p, ws, s);
+}
+
+int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters, float* V,
+                     double* gram_hist, double* b_hist, void* ws, size_t ws_bytes, void* stream) {
+  RET_IF(check_matrix(X));
+  if (k < 1 || l < 0 || iters < 0 || !V) return PPCA_ERR_ARG;
+  const int K = k + l;
+  RET_IF(check_k(X, K));
+  const Plan p = make_plan(PPCA_OP_POWER, X->n, X->d, X->dtype, K, 0);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  RET_IF(cholqr2(V, V, X->d, K, p, ws, s));
+  float* Z = at<float>(ws, p.z);
+  double* G = at<double>(ws, p.g);
+  const int64_t kk = (int64_t)K * K;
+  for (int t = 0; t < iters; ++t) {
+    RET_IF(make_operand(X, V, p, ws, s));
+    if (b_hist) RET_IF(operand_gram(X, p, ws, b_hist + t * kk, s));
+    RET_IF(run_pass(X, p, ws, 0, X->n, Z, G, gram_hist ? gram_hist + t * kk : nullptr, false, s));
+    RET_IF(cholqr2(Z, V, X->d, K, p, ws, s));
+  }
+  return finish(p, ws, s);
+}
+
+int ppca_prime_oja(const ppca_matrix* X, int32_t k, int32_t l, const ppca_sgd_params* p, float* V,
+                   void* ws, size_t ws_bytes, void* stream) {
+  return prime_sgd(false, X, k, l, p, V, ws, ws_bytes, stream);
+}
+
+int ppca_prime_eigengame(const ppca_matrix* X, int32_t k, int32_t l, const ppca_sgd_params* p,
+                         float* V, void* ws, size_t ws_bytes, void* stream) {
+  return prime_sgd(true, X, k, l, p, V, ws, ws_bytes, stream);
+}
+
+int ppca_stream_pass(const ppca_matrix* X, int32_t K, const float* V, int64_t r0, int64_t nrows,
+                     float* Z, double* G, void* ws, size_t ws_bytes, void* stream) {
+  RET_IF(check_matrix(X));
+  if (!V || !Z || !G || r0 < 0 || r0 >= X->n || nrows < 1) return PPCA_ERR_ARG;
+  RET_IF(check_k(X, K));
+  const Plan p = make_plan(PPCA_OP_STREAM, X->n, X->d, X->dtype, K, nrows);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
+  RET_IF(make_operand(X, V, p, ws, s));
+  RET_IF(run_pass(X, p, ws, r0, nrows, Z, G, nullptr, false, s));
+  return finish(p, ws, s);
+}
+
+int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V, double* G, double* B,
+                      void* ws, size_t ws_bytes, void* stream) {
+  RET_IF(check_matrix(X));
+  if (!V || !G || !B) return PPCA_ERR_ARG;
+  RET_IF(check_k(X, K));
+  const Plan p = make_plan(PPCA_OP_PROJECT, X->n, X->d, X->dtype, K, 0);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
+  RET_IF(make_operand(X, V, p, ws, s));
+  RET_IF(operand_gram(X, p, ws, B, s));
+  RET_IF(run_pass(X, p, ws, 0, X->n, nullptr, G, nullptr, true, s));
+  return finish(p, ws, s);
+}
+
+int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k, const double* G,
+                       const double* B, const float* V, float* E, double* evals, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!X || X->n < 1 || X->d < 1) return PPCA_ERR_ARG;
+  if (X->dtype != PPCA_F32 && X->dtype != PPCA_BF16 && X->dtype != PPCA_FP8_E4M3)
+    return PPCA_ERR_DTYPE;
+  if ((X->dtype == PPCA_FP8_E4M3) != (X->col_scale != nullptr)) return PPCA_ERR_DTYPE;
+  if (K < 1 || K > PPCA_MAX_K || K > X->d || k < 1 || k > K) return PPCA_ERR_ARG;
+  if (!G || !B || !evals || (E && !V)) return PPCA_ERR_ARG;
+  const Plan p = make_plan(PPCA_OP_RR, X->n, X->d, X->dtype, K, 0);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  double* R = at<double>(ws, p.r);
+  double* Ri = at<double>(ws, p.rinv);
+  double* T = at<double>(ws, p.t);
+  double* H = at<double>(ws, p.h);
+  double* W = at<double>(ws, p.w);
+  double* ev = at<double>(ws, p.ev);
+  double* M = at<double>(ws, p.m);
+  HIP_TRY(launch_chol_inv(B, K, R, Ri, st, s));
+  HIP_TRY(launch_small_gemm(G, false, Ri, T, K, K, K, K, K, K, 1.0, st, s));
+  HIP_TRY(launch_small_gemm(Ri, true, T, H, K, K, K, K, K, K, 1.0 / (double)X->n, st, s));
+  HIP_TRY(launch_jacobi(H, K, W, ev, 60, st, s));
+  HIP_TRY(launch_copy_f64(ev, evals, k, s));
+  if (E) {
+    RET_IF(make_operand(X, V, p, ws, s));
+    HIP_TRY(launch_small_gemm(Ri, false, W, M, K, k, K, K, K, k, 1.0, st, s));
+    HIP_TRY(launch_rotate(at<double>(ws, p.veff), X->d, p.Kp, K, M, k, E, st, s));
+    HIP_TRY(launch_sign_fix(E, X->d, k, st, s));
+  }
+  return finish(p, ws, s);
+}
+
+size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch) {
+  if (!X || X->n < 1 || X->d < 1) return 0;
+  if (op < PPCA_OP_CENTER || op > PPCA_OP_STREAM) return 0;
+  if (op != PPCA_OP_CENTER && (K < 1 || K > PPCA_MAX_K)) return 0;
+  if ((op == PPCA_OP_OJA || op == PPCA_OP_EIGENGAME) && (batch < 1 || batch > X->n)) return 0;
+  if (op == PPCA_OP_STREAM && batch < 1) return 0;
+  const Plan p = make_plan(op, X->n, X->d, X->dtype, op == PPCA_OP_CENTER ? 1 : K, batch);
+  return p.total;
+}
+
+const char* ppca_strerror(int status) {
+  switch (status) {
+    case PPCA_OK: return "success";
+    case PPCA_ERR_ARG: return "invalid argument";
+    case PPCA_ERR_DTYPE: return "invalid dtype or col_scale";
+    case PPCA_ERR_NOT_SPD: return "Cholesky pivot not positive: directions are rank deficient";
+    case PPCA_ERR_NONFINITE: return "non-finite value in Z or a Gram matrix";
+    case PPCA_ERR_NO_CONVERGENCE: return "Jacobi eigensolver reached its sweep cap";
+    case PPCA_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case PPCA_ERR_HIP: return "HIP runtime error";
+    case PPCA_ERR_ALIGN: return "X base pointer or row stride not 16-byte aligned";
+    default: return "unknown status";
+  }
+}
+
+void ppca_set_kernel_timing(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = enable != 0;
+  g_stats[0] = KStat();
+  g_stats[1] = KStat();
+}
+
+int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
+  if (kernel < 0 || kernel > 1) return PPCA_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (launches) *launches = g_stats[kernel].launches;
+  if (total_ms) *total_ms = g_stats[kernel].ms;
+  return PPCA_OK;
+}
+
+void ppca_set_chunk_rows(int64_t rows) { g_chunk_rows.store(rows < 0 ? 0 : rows); }
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP sources of libppca (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ppca.h"
+
+namespace ppca {
+
+// ---------------------------------------------------------------- constants
+constexpr int kMaxK = PPCA_MAX_K;          // largest K = k + l
+constexpr int kXvRows = 256;               // rows of X per workgroup in the X V' kernel
+constexpr int kXtyCols = 256;              // columns of [X | Y] per workgroup in the X^T Y kernel
+constexpr int kXtyStep = 32;               // rows per k-step of the X^T Y kernel
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ device helpers
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Report a device-side failure: the first error code written wins.
+__device__ inline void set_status(int* status, int code) {
+  atomicCAS(status, 0, code);
+}
+
+// bf16 bits of the nearest bf16 to a finite float (ties to even).
+__device__ inline uint32_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ inline float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Exact fp8-e4m3fn -> bf16 bit conversion of one code (every e4m3 value is a
+// bf16 value: 3 mantissa bits, exponents 2^-9 .. 2^8).
+__device__ inline uint32_t e4m3_to_bf16_bits(uint32_t c) {
+  const uint32_t sign = (c & 0x80u) << 8;
+  const uint32_t e = (c >> 3) & 0xFu;
+  const uint32_t m = c & 0x7u;
+  uint32_t mag;
+  if (e != 0) {
+    mag = ((e + 120u) << 7) | (m << 4);
+  } else {
+    // subnormal: m * 2^-9, exact in float32
+    mag = __float_as_uint((float)m * 0.001953125f) >> 16;
+  }
+  return sign | mag;
+}
+
+// --------------------------------------------------------- host-side launch
+// Streaming pass description: rows i = 0 .. nrows-1 of the pass are the data
+// rows (r0 + i) mod n.
+struct PassDesc {
+  const void* x;
+  int64_t n, d, ld;
+  int32_t dtype;
+  const float* col_scale;   // fp8 only
+  int64_t r0, nrows;
+};
+
+struct StreamBufs {
+  const void* vop;      // operand V'^T: [Kp][dp] bf16 (bf16/fp8 data) or f32 (f32 data)
+  int64_t dp;           // padded d of the operand
+  void* yb;             // Y staging buffer (blocked rows), sized for chunk rows
+  float* part;          // partials [ntiles][nsplit][Kp][256]
+  int nsplit;           // row splits of the X^T Y kernel (multiple of 8)
+  int Kp;               // K padded to 16
+};
+
+// stream kernels (k_stream.hip)
+int xty_tiles(int64_t d, int Kp);  // tiles of [X | Y] columns (last one = Y)
+hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
+                     hipStream_t s);
+hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
+                      bool accumulate, bool gram_only, hipStream_t s);
+hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* col_scale,
+                            float* Z, double* G, double* G_copy, bool gram_only, int* status,
+                            hipStream_t s);
+
+// dense float64 kernels (k_dense.hip)
+hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp,
+                               int32_t dtype, const float* col_scale, void* vop,
+                               double* veff, hipStream_t s);
+// partial Grams of a (rows x K) matrix A (row stride lda); in_f64 selects the type
+int gram_parts(int64_t rows);
+hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,
+                       double* parts, double* out, int* status, hipStream_t s);
+hipError_t launch_chol_inv(const double* A, int K, double* R, double* Rinv, int* status,
+                           hipStream_t s);
+hipError_t launch_trmm(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,
+                       const double* Rinv, void* out, bool out_f64, int64_t ldo, int* status,
+                       hipStream_t s);
+// C = alpha * op(A) * B for small K x K / K x k matrices (row-major, float64)
+hipError_t launch_small_gemm(const double* A, bool transA, const double* B, double* C, int M,
+                             int N, int Kd, int lda, int ldb, int ldc, double alpha,
+                             int* status, hipStream_t s);
+hipError_t launch_jacobi(const double* H, int K, double* W, double* evals, int max_sweeps,
+                         int* status, hipStream_t s);
+hipError_t launch_rotate(const double* veff, int64_t d, int Kp, int K, const double* M, int k,
+                         float* E, int* status, hipStream_t s);
+hipError_t launch_sign_fix(float* E, int64_t d, int k, int* status, hipStream_t s);
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// minibatch updates (k_update.hip)
+hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K,
+                                int b, double eta, double mu, int nesterov, float* mom,
+                                int* status, hipStream_t s);
+hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
+                                   int b, double eta, double mu, int nesterov, float* mom,
+                                   double* scratch, int* status, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t count, hipStream_t s);
+
+// data preparation (k_prep.hip)
+int prep_row_blocks(int64_t n);
+hipError_t launch_center_quantize(const float* x, int64_t n, int64_t d, int64_t ldx,
+                                  int32_t out_dtype, void* out, int64_t ldo, float* col_scale,
+                                  double* mean_out, double* ws_sums, float* ws_max,
+                                  double* ws_mean, hipStream_t s);
+
+}  // namespace ppca

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol declared in include/ppca.h
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppca.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppca_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("ppca_prime_power", "ppca_prime_oja", "ppca_prime_eigengame",
+                 "ppca_project_gram", "ppca_rayleigh_ritz", "ppca_center_quantize",
+                 "ppca_workspace_bytes", "ppca_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2109_03709_amd import _lib
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert sorted(_declared()) == sorted(_lib.EXPORTS)
+
+
+def test_host_only_calls():
+    """Calls that touch no device memory: status strings, workspace sizes and
+    argument validation (which returns before anything is enqueued)."""
+    from paper_2109_03709_amd import _lib
+    L = _lib.lib()
+    assert _lib.strerror(0) == "success"
+    assert "rank deficient" in _lib.strerror(-3)
+    m = _lib._Matrix(16, 10000, 256, 256, _lib.F32, 0)
+    ws_power = L.ppca_workspace_bytes(_lib.OP_POWER, ctypes.byref(m), 32, 0)
+    assert ws_power > 10000 * 32 * 4          # at least the Y staging buffer
+    assert L.ppca_workspace_bytes(_lib.OP_POWER, ctypes.byref(m), 0, 0) == 0
+    assert L.ppca_workspace_bytes(_lib.OP_POWER, ctypes.byref(m), 129, 0) == 0
+    assert L.ppca_workspace_bytes(_lib.OP_OJA, ctypes.byref(m), 32, 0) == 0
+    assert L.ppca_workspace_bytes(_lib.OP_OJA, ctypes.byref(m), 32, 1000) > 0
+    # invalid arguments are rejected on the host
+    bad = _lib._Matrix(16, 100, 64, 32, _lib.F32, 0)          # ld < d
+    assert L.ppca_prime_power(ctypes.byref(bad), 4, 4, 1, ctypes.c_void_p(16), None, None,
+                              ctypes.c_void_p(256), 1 << 20, None) == -1
+    fp8_no_scale = _lib._Matrix(16, 100, 64, 64, _lib.FP8_E4M3, 0)
+    assert L.ppca_prime_power(ctypes.byref(fp8_no_scale), 4, 4, 1, ctypes.c_void_p(16), None,
+                              None, ctypes.c_void_p(256), 1 << 20, None) == -2
+    misaligned = _lib._Matrix(8, 100, 64, 64, _lib.F32, 0)
+    assert L.ppca_prime_power(ctypes.byref(misaligned), 4, 4, 1, ctypes.c_void_p(16), None,
+                              None, ctypes.c_void_p(256), 1 << 20, None) == -8
+    odd_ld = _lib._Matrix(16, 100, 63, 63, _lib.F32, 0)
+    assert L.ppca_prime_power(ctypes.byref(odd_ld), 4, 4, 1, ctypes.c_void_p(16), None,
+                              None, ctypes.c_void_p(256), 1 << 20, None) == -8
+    ok = _lib._Matrix(16, 100, 64, 64, _lib.F32, 0)
+    assert L.ppca_prime_power(ctypes.byref(ok), 4, 4, 1, ctypes.c_void_p(16), None, None,
+                              ctypes.c_void_p(256), 16, None) == -6    # workspace too small
+    assert L.ppca_prime_power(ctypes.byref(ok), 0, 4, 1, ctypes.c_void_p(16), None, None,
+                              ctypes.c_void_p(256), 1 << 30, None) == -1   # k = 0
+    assert L.ppca_prime_power(ctypes.byref(ok), 64, 1, 1, ctypes.c_void_p(16), None, None,
+                              ctypes.c_void_p(256), 1 << 30, None) == -1   # K > d

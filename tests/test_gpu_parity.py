@@ -1,0 +1,375 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle on
+the same seeded inputs.  Sizes span several tiles and ragged tails.
+
+Tolerances (derived in the design doc):
+* centring / storage codes: bit-exact (integer results);
+* Gram of the projected data: f32 data 2e-5, bf16/fp8 data 4e-3 of
+  sqrt(G_ii G_jj) (the bf16 rounding of Y before the Gram bounds it by 2^-8);
+  the operand Gram B: 1e-12;
+* pPCA results: 1e-4 (f32 path) and 2e-3 (bf16/fp8 path after
+  Rayleigh-Ritz) in eigenvalue relative error and largest principal-angle sine.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ppca_oracle as O
+from synthdata import gaussian_block, make_problem
+
+from ._gpu_util import (BF16, F32, FP8, col_cos, device_data, gram_err, host, operand_basis,
+                        sin_theta)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03709_amd as P
+    P.lib()        # fails loudly if the library is missing
+    P.set_chunk_rows(0)
+    yield
+
+
+def P():
+    import paper_2109_03709_amd as mod
+    return mod
+
+
+# ----------------------------------------------------------------- a0 parity
+@pytest.mark.parametrize("dtype", [F32, BF16, FP8])
+@pytest.mark.parametrize("shape", [(3001, 77), (64, 16), (1, 5)])
+def test_center_quantize_bit_exact(dtype, shape):
+    n, d = shape
+    rng = np.random.default_rng(n + d)
+    x = (rng.standard_normal((n, d)) * rng.uniform(0.01, 100, d) + rng.uniform(-5, 5, d))
+    x = x.astype(np.float32)
+    x[:, -1] = 0.0 if d > 1 else x[:, -1]          # an all-zero column
+    xd = torch.from_numpy(x).cuda()
+    data, mean = P().center_quantize(xd, dtype)
+    torch.cuda.synchronize()
+    mu = O.column_means(x)
+    assert np.array_equal(mean.cpu().numpy(), mu)
+    c = O.center_fp32(x, mu)
+    if dtype == F32:
+        assert np.array_equal(data.x.cpu().numpy().view(np.uint32), c.view(np.uint32))
+    elif dtype == BF16:
+        assert np.array_equal(host(data.x), O.bf16_round(c))
+    else:
+        s = O.fp8_column_scales(c)
+        assert np.array_equal(data.col_scale.cpu().numpy(), s)
+        assert np.array_equal(data.x.cpu().numpy(), O.fp8_quantize(c, s))
+
+
+# --------------------------------------------------------- projection + Gram
+@pytest.mark.parametrize("dtype", [F32, BF16, FP8])
+@pytest.mark.parametrize("n,d,K,pad", [(5003, 200, 24, 0), (3000, 256, 128, 0),
+                                        (777, 64, 1, 16), (4096, 600, 40, 32), (9, 33, 3, 15)])
+def test_project_gram(dtype, n, d, K, pad):
+    p = make_problem(n, d, "exp0.9", seed=n + K, mode="gaussian")
+    ld = d + pad
+    data, xs, scale = device_data(p.x, dtype, ld)
+    v = gaussian_block(d, K, 7, np.float32)
+    G, B = P().project_gram(data, K, torch.from_numpy(v).cuda())
+    torch.cuda.synchronize()
+    veff = operand_basis(v, dtype, scale)
+    g_ref, b_ref = O.project_gram(xs, veff)
+    tol = 2e-5 if dtype == F32 else 4e-3
+    assert gram_err(G.cpu().numpy(), g_ref) < tol
+    assert np.allclose(B.cpu().numpy(), b_ref, rtol=1e-12, atol=1e-12 * np.abs(b_ref).max())
+    assert np.array_equal(G.cpu().numpy(), G.cpu().numpy().T)
+
+
+# ------------------------------------------------------- the streaming pass
+@pytest.mark.parametrize("dtype", [F32, BF16, FP8])
+@pytest.mark.parametrize("n,d,K,r0,rows", [(5003, 300, 64, 0, 5003), (4000, 1024, 128, 3900, 1024),
+                                            (1500, 77, 5, 17, 999), (20000, 512, 32, 123, 20000)])
+def test_stream_pass_elementwise_bound(dtype, n, d, K, r0, rows):
+    """Z = X^T (X V') and G on a (wrapping) row range.  Elementwise bound:
+    |Z - Z_ref| <= c |X|^T |Y| with c = 2^-8 when Y is rounded to bf16 before
+    the second product (bf16 / fp8 data) and c = 1e-5 for float32 data."""
+    p = make_problem(n, d, "pow1.5", seed=n + d + K, mode="gaussian")
+    data, xs, scale = device_data(p.x, dtype)
+    v = gaussian_block(d, K, 17, np.float32)
+    Z, G = P().stream_pass(data, K, torch.from_numpy(v).cuda(), r0=r0, nrows=rows)
+    torch.cuda.synchronize()
+    xb = xs[(r0 + np.arange(rows)) % n]
+    veff = operand_basis(v, dtype, scale)
+    y = xb @ veff
+    z_ref, g_ref = xb.T @ y, y.T @ y
+    bound = np.abs(xb).T @ np.abs(y)
+    c = 1e-5 if dtype == F32 else 2.0 ** -8
+    assert np.all(np.abs(Z.cpu().numpy() - z_ref) <= c * bound + 1e-30)
+    assert gram_err(G.cpu().numpy(), g_ref) < (2e-5 if dtype == F32 else 4e-3)
+
+
+# ---------------------------------------------------------------- power pass
+@pytest.mark.parametrize("dtype", [F32, BF16, FP8])
+@pytest.mark.parametrize("n,d,k,l,spec", [(6007, 300, 8, 8, "exp0.9"),
+                                           (2048, 512, 16, 16, "exp0.97+1e-5"),
+                                           (500, 40, 3, 0, "exp0.9")])
+def test_power_iterates(dtype, n, d, k, l, spec):
+    """V_t of block power (CholeskyQR2 of Z = X^T X V') against the oracle's
+    iteration on the stored data, for t = 1 and 3."""
+    K = k + l
+    p = make_problem(n, d, spec, seed=3 * n + d, mode="exact")
+    data, xs, scale = device_data(p.x, dtype)
+    v0 = gaussian_block(d, K, 11, np.float32)
+    for iters in (1, 3):
+        V = torch.from_numpy(v0.copy()).cuda()
+        gh = torch.zeros((iters, K, K), dtype=torch.float64, device="cuda")
+        P().prime_power(data, k, l, iters, V, gram_hist=gh)
+        torch.cuda.synchronize()
+        v_gpu = V.cpu().numpy().astype(np.float64)
+        # oracle: same loop, operand of every pass built from the current V
+        v = O.cholqr2(v0.astype(np.float64))[0]
+        for t in range(iters):
+            veff = operand_basis(v.astype(np.float32), dtype, scale)
+            z, g = O.stream_pass(xs, veff)
+            v = O.cholqr2(z)[0]
+        tol = 1e-4 if dtype == F32 else 2e-2
+        assert np.linalg.norm(v_gpu.T @ v_gpu - np.eye(K)) < 1e-5 * K
+        assert sin_theta(v_gpu, v) < tol
+        if dtype == F32:     # columns match one by one (CholeskyQR keeps the nested spans)
+            assert np.min(col_cos(v_gpu, v)) > 1 - 1e-6
+        assert gram_err(gh[iters - 1].cpu().numpy(), g) < (2e-5 if dtype == F32 else 4e-3)
+
+
+def test_power_deterministic():
+    p = make_problem(5000, 256, "exp0.9", seed=5, mode="exact")
+    data, _, _ = device_data(p.x, BF16)
+    v0 = torch.from_numpy(gaussian_block(256, 32, 1, np.float32)).cuda()
+    a = P().prime_power(data, 16, 16, 4, v0.clone())
+    b = P().prime_power(data, 16, 16, 4, v0.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_chunked_pass_matches_single_pass():
+    p = make_problem(9000, 128, "exp0.9", seed=6, mode="exact")
+    data, _, _ = device_data(p.x, BF16)
+    v = torch.from_numpy(gaussian_block(128, 32, 2, np.float32)).cuda()
+    g1, _ = P().project_gram(data, 32, v)
+    P().set_chunk_rows(1000)
+    try:
+        g2, _ = P().project_gram(data, 32, v)
+    finally:
+        P().set_chunk_rows(0)
+    torch.cuda.synchronize()
+    assert gram_err(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6
+
+
+# ------------------------------------------------------------- Rayleigh-Ritz
+@pytest.mark.parametrize("K,k", [(32, 16), (128, 64), (7, 7), (1, 1), (65, 20)])
+def test_rayleigh_ritz_vs_oracle(K, k):
+    d = max(200, K)
+    p = make_problem(4000, d, "exp0.9", seed=K, mode="exact")
+    data, xs, _ = device_data(p.x, F32)
+    v = gaussian_block(d, K, 3, np.float32) + p.q[:, :K].astype(np.float32)
+    vd = torch.from_numpy(v).cuda()
+    G, B = P().project_gram(data, K, vd)
+    ev, E = P().rayleigh_ritz(data, K, k, G, B, vd)
+    torch.cuda.synchronize()
+    th, e_ref, _ = O.rayleigh_ritz(G.cpu().numpy(), B.cpu().numpy(), v.astype(np.float64),
+                                   data.n, k)
+    assert np.max(O.rel_eig_error(ev.cpu().numpy(), th)) < 1e-8
+    e = E.cpu().numpy().astype(np.float64)
+    assert np.min(col_cos(e, e_ref)) > 1 - 1e-9
+    # sign rule: largest-magnitude entry of each column positive
+    piv = np.argmax(np.abs(e), axis=0)
+    assert np.all(e[piv, np.arange(k)] > 0)
+    assert np.linalg.norm(e.T @ e - np.eye(k)) < 1e-5
+
+
+def test_counterexample_on_gpu():
+    """Sec. 4.1 worked example through the GPU Rayleigh-Ritz: the order swap."""
+    eps = 0.1
+    pts = np.array([[3, 0, 0], [-3, 0, 0], [0, 2, 0], [0, -2, 0], [0, 0, 1], [0, 0, -1]],
+                   np.float32)
+    x = np.zeros((6, 4), np.float32)       # pad d to a multiple of 4 with a zero column
+    x[:, :3] = pts
+    data, _ = P().center_quantize(torch.from_numpy(x).cuda(), F32)
+    v = np.zeros((4, 2), np.float32)
+    v[:3, 0] = [eps, 0, math.sqrt(1 - eps ** 2)]
+    v[:3, 1] = [0, 1, 0]
+    vd = torch.from_numpy(v).cuda()
+    G, B = P().project_gram(data, 2, vd)
+    ev, E = P().rayleigh_ritz(data, 2, 2, G, B, vd)
+    torch.cuda.synchronize()
+    assert ev.cpu().numpy() == pytest.approx([4.0 / 3.0, (1 + 8 * eps ** 2) / 3], rel=1e-6)
+    assert abs(E.cpu().numpy()[0, 0]) < 1e-7          # e1_pPCA is orthogonal to e1
+
+
+# --------------------------------------------------- end-to-end pPCA results
+def _ppca_gpu(data, k, l, iters, v0):
+    V = torch.from_numpy(v0.copy()).cuda()
+    P().prime_power(data, k, l, iters, V)
+    ev, E = P().ppca(data, V, k)
+    torch.cuda.synchronize()
+    return ev.cpu().numpy(), E.cpu().numpy().astype(np.float64)
+
+
+def test_small_config_full_size_f32():
+    """n=10,000, d=256, lambda_i = 0.9^i, k=16, l=16, 10 power iterations,
+    pPCA with a 32 x 32 eigensolve; f32 path tolerance 1e-4."""
+    n, d, k, l = 10000, 256, 16, 16
+    p = make_problem(n, d, "exp0.9", seed=1001, mode="exact")
+    data, xs, _ = device_data(p.x, F32)
+    v0 = gaussian_block(d, k + l, 2001, np.float32)
+    ev, E = _ppca_gpu(data, k, l, 10, v0)
+    v_or, _ = O.prime_power(xs, v0.astype(np.float64), 10)
+    th, e_or = O.ppca(xs, v_or, k)
+    assert np.max(O.rel_eig_error(ev, th)) < 1e-4
+    assert sin_theta(E, e_or) < 1e-4
+    # against the exact spectrum (priming has converged: rate 0.9^(17*10))
+    assert np.max(O.rel_eig_error(ev, p.lam[:k])) < 1e-4
+    assert sin_theta(E, p.q[:, :k]) < 1e-4
+    # Ky Fan: the pPCA Rayleigh-quotient sum is at least the priming one
+    vq = O.cholqr2(v_or)[0]
+    rq = np.sort(np.diag(vq.T @ O.covariance(xs) @ vq))[::-1]
+    assert ev.sum() >= rq[:k].sum() * (1 - 1e-6)
+
+
+@pytest.mark.parametrize("dtype,spec,k,iters", [(BF16, "exp0.9", 64, 6),
+                                                 (FP8, "exp0.97+1e-5", 32, 15)])
+def test_low_precision_ppca_scaled(dtype, spec, k, iters):
+    """bf16 (K = 128) and fp8 (K = 64) storage on d = 2048 with a ragged row
+    count.  Parity: after Rayleigh-Ritz the GPU result matches the oracle's
+    own run on the same stored data within 2e-3 (eigenvalue relative error
+    and largest principal-angle sine).  Against the exact spectrum of the
+    float32 data the eigenvalues stay within 2e-3; the subspace of the stored
+    data itself differs from the exact one by quantisation noise whose effect
+    shrinks like 1/sqrt(n) (about 2e-3 for bf16 and 4e-3 for fp8 at this n,
+    ten to twenty times less at the full row counts), hence the 1e-2 bound."""
+    n, d, l = 20011, 2048, k
+    p = make_problem(n, d, spec, seed=1003, mode="exact")
+    data, xs, scale = device_data(p.x, dtype)
+    v0 = gaussian_block(d, k + l, 2003, np.float32)
+    ev, E = _ppca_gpu(data, k, l, iters, v0)
+    v_or, _ = O.prime_power(xs, v0.astype(np.float64), iters)
+    th, e_or = O.ppca(xs, v_or, k)
+    assert np.max(O.rel_eig_error(ev, th)) < 2e-3
+    assert sin_theta(E, e_or) < 2e-3
+    assert np.max(O.rel_eig_error(ev, p.lam[:k])) < 2e-3
+    assert sin_theta(E, p.q[:, :k]) < 1e-2
+
+
+# ----------------------------------------------------- minibatch primings
+@pytest.mark.parametrize("dtype", [F32, BF16])
+def test_oja_trajectory(dtype):
+    n, d, k, l, b = 20000, 256, 16, 16, 1024
+    p = make_problem(n, d, "pow1.2+1e-4", seed=1002, mode="exact")
+    data, xs, scale = device_data(p.x, dtype)
+    v0 = gaussian_block(d, k + l, 2002, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    steps, eta0 = 5, 0.5
+    P().prime_oja(data, k, l, V, batch=b, steps=steps, eta0=eta0, t0=1000.0)
+    torch.cuda.synchronize()
+    v = O.cholqr2(v0.astype(np.float64))[0]
+    for t in range(steps):
+        veff = operand_basis(v.astype(np.float32), dtype, scale)
+        xb = xs[O.minibatch_rows(n, b, t)]
+        z, g = O.stream_pass(xb, veff)
+        v = v + O.learning_rate(eta0, 1000.0, t) * O.sanger_direction(z, g, v, b)
+    err = np.max(np.abs(V.cpu().numpy() - v)) / np.max(np.abs(v))
+    assert err < (1e-4 if dtype == F32 else 2e-2)
+
+
+@pytest.mark.parametrize("dtype", [F32, FP8])
+def test_eigengame_trajectory(dtype):
+    n, d, k, l, b = 12000, 512, 8, 8, 4096
+    p = make_problem(n, d, "exp0.97+1e-5", seed=1004, mode="exact")
+    data, xs, scale = device_data(p.x, dtype)
+    v0 = gaussian_block(d, k + l, 2004, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    steps, eta0 = 4, 0.5
+    P().prime_eigengame(data, k, l, V, batch=b, steps=steps, eta0=eta0)
+    torch.cuda.synchronize()
+    v = O.cholqr2(v0.astype(np.float64))[0]
+    for t in range(steps):
+        veff = operand_basis(v.astype(np.float32), dtype, scale)
+        xb = xs[O.minibatch_rows(n, b, t)]
+        z, g = O.stream_pass(xb, veff)
+        grad = O.eigengame_grad(z, g, b)
+        grad = grad - v * np.sum(v * grad, axis=0)[None, :]
+        v = v + eta0 * grad
+        v = v / np.linalg.norm(v, axis=0)[None, :]
+    err = np.max(np.abs(V.cpu().numpy() - v))
+    assert err < (1e-4 if dtype == F32 else 3e-2)
+
+
+def test_momentum_and_resume():
+    """Nesterov momentum 0.9 (Sec. 5) and resuming from (V, step, buffer):
+    two calls of 3 steps equal one call of 6."""
+    n, d, k, l, b = 8000, 128, 8, 0, 1000
+    p = make_problem(n, d, "paper-exp", seed=9, mode="exact")
+    data, xs, _ = device_data((p.x / math.sqrt(1000.0)).astype(np.float32), F32)
+    v0 = torch.from_numpy(gaussian_block(d, k, 3, np.float32)).cuda()
+    kw = dict(batch=b, eta0=1e-3, t0=0.0, momentum=0.9, nesterov=True)
+    va, ma = v0.clone(), torch.zeros_like(v0)
+    P().prime_oja(data, k, l, va, steps=6, mom_buf=ma, **kw)
+    vb, mb = v0.clone(), torch.zeros_like(v0)
+    P().prime_oja(data, k, l, vb, steps=3, mom_buf=mb, **kw)
+    P().prime_oja(data, k, l, vb, steps=3, mom_buf=mb, start_step=3, orthonormalise_start=False,
+                  **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb) and torch.equal(ma, mb)
+    v_or, _ = O.prime_oja(xs, v0.cpu().numpy().astype(np.float64), batch=b, steps=6, eta0=1e-3,
+                          t0=0.0, momentum=0.9, nesterov=True)
+    assert np.max(np.abs(va.cpu().numpy() - v_or)) < 1e-4 * np.max(np.abs(v_or))
+
+
+def test_snapshots():
+    n, d, K, b = 4000, 64, 8, 500
+    p = make_problem(n, d, "exp0.9", seed=10, mode="exact")
+    data, _, _ = device_data(p.x, F32)
+    v = torch.from_numpy(gaussian_block(d, K, 4, np.float32)).cuda()
+    snaps = torch.zeros((3, d, K), dtype=torch.float32, device="cuda")
+    P().prime_eigengame(data, 4, 4, v, batch=b, steps=7, eta0=0.1, snapshot_every=2,
+                        snapshots=snaps)
+    v6 = torch.from_numpy(gaussian_block(d, K, 4, np.float32)).cuda()
+    P().prime_eigengame(data, 4, 4, v6, batch=b, steps=6, eta0=0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(snaps[2], v6)
+
+
+# ------------------------------------------------------------- error paths
+def test_error_not_spd():
+    p = make_problem(1000, 64, "exp0.9", seed=12, mode="exact")
+    data, _, _ = device_data(p.x, F32)
+    v = gaussian_block(64, 6, 5, np.float32)
+    v[:, 5] = v[:, 1]
+    with pytest.raises(P().PPCAError) as ei:
+        P().prime_power(data, 3, 3, 2, torch.from_numpy(v).cuda())
+    assert ei.value.code == -3
+    vd = torch.from_numpy(v).cuda()
+    G, B = P().project_gram(data, 6, vd)
+    with pytest.raises(P().PPCAError) as ei:
+        P().rayleigh_ritz(data, 6, 3, G, B, vd)
+    assert ei.value.code == -3
+
+
+def test_error_nonfinite():
+    p = make_problem(1000, 64, "exp0.9", seed=13, mode="exact")
+    data, _, _ = device_data(p.x, F32)
+    data.x[17, 5] = float("nan")
+    with pytest.raises(P().PPCAError) as ei:
+        P().project_gram(data, 4, torch.from_numpy(gaussian_block(64, 4, 6, np.float32)).cuda())
+    assert ei.value.code == -4
+
+
+def test_error_workspace_and_args():
+    p = make_problem(1000, 64, "exp0.9", seed=14, mode="exact")
+    data, _, _ = device_data(p.x, F32)
+    v = torch.from_numpy(gaussian_block(64, 8, 6, np.float32)).cuda()
+    need = P().workspace_bytes(P().OP_POWER, data, 8)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P().PPCAError) as ei:
+        P().prime_power(data, 4, 4, 1, v, ws=ws)
+    assert ei.value.code == -6
+    with pytest.raises(P().PPCAError) as ei:
+        P().prime_oja(data, 4, 4, v, batch=2000, steps=1, eta0=0.1)
+    assert ei.value.code == -1
