@@ -108,86 +108,152 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
 }
 
 // --------------------------------------------------------------------------
-// Cholesky A = R^T R (upper R) and R^-1, one workgroup, K <= 128.
-// A pivot not above K * eps * a_jj (or not finite) means the columns behind A
-// are numerically dependent: PPCA_ERR_NOT_SPD.
+// Upper Cholesky factor R (R^T R = A) and its inverse, K <= 128, one
+// workgroup of 1024 threads.  Thread (ty, tx) = (tid / 32, tid % 32) keeps the
+// 4 x 4 elements (ty + 32p, tx + 32q) of the working matrix in registers.
+// Right-looking factorisation, two barriers per column j:
+//   (a) the owner of (j, j) checks the pivot (finite, > K * eps * |a_jj|,
+//       > 0; else NOT_SPD) and publishes r_jj = sqrt(pivot);
+//   (b) the owners of row j scale it, u_c = m_jc / r_jj, and publish u;
+//   (c) every thread updates its trailing elements, m_ic -= u_i u_c.
+// Then R goes to LDS and X = R^-1 follows from R X = I by right-looking back
+// substitution (row i of X = row i of B / r_ii, then B_p -= r_pi X_i for
+// p < i), one barrier per row.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A, int K,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv, int* status) {
-  __shared__ double M[kMaxK * kMaxK];
-  __shared__ double dg[kMaxK];     // original diagonal, later diag(R)
-  __shared__ double xd[kMaxK];     // diag(R^-1)
+  constexpr int KM = kMaxK;          // 128
+  __shared__ double Rs[KM * KM];     // R (row-major) for the inverse
+  __shared__ double ub[KM];          // published row of the current step
+  __shared__ double xb[2][KM];       // published rows of X (double buffered)
+  __shared__ double dg[KM];          // diagonal of A
+  __shared__ double rd[KM];          // diagonal of R
   __shared__ int fail;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
   if (status_set(status)) return;
   if (tid == 0) fail = 0;
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    M[e] = c >= i ? A[e] : 0.0;
-    if (i == c) dg[i] = A[e];
-  }
+  double m[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 32 * p, c = tx + 32 * q;
+      m[p][q] = (i < K && c < K) ? A[i * K + c] : 0.0;
+      if (i == c && i < K) dg[i] = m[p][q];
+    }
   __syncthreads();
   for (int j = 0; j < K; ++j) {
-    if (tid == 0) {
-      const double piv = M[j * K + j];
-      if (!(isfinite(piv) && piv > (double)K * kEps * fabs(dg[j]) && piv > 0.0)) {
-        fail = 1;
-      } else {
-        M[j * K + j] = sqrt(piv);
-      }
+    const int pj = j >> 5, oj = j & 31;
+    // (a) pivot
+    if (ty == oj && tx == oj) {
+      double piv = 0.0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (p == pj && q == pj) piv = m[p][q];
+      if (!(isfinite(piv) && piv > (double)K * kEps * fabs(dg[j]) && piv > 0.0)) fail = 1;
+      else rd[j] = sqrt(piv);
     }
     __syncthreads();
     if (fail) {
       if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
       return;
     }
-    const double rjj = M[j * K + j];
-    for (int c = j + 1 + tid; c < K; c += blockDim.x) M[j * K + c] /= rjj;
-    __syncthreads();
-    const int m = K - j - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, c = j + 1 + e % m;
-      if (c >= i) M[i * K + c] -= M[j * K + i] * M[j * K + c];
-    }
-    __syncthreads();
-  }
-  // R out; move the strict upper part of R to the strict lower part of M
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    R[e] = c >= i ? M[e] : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    if (c > i) M[c * K + i] = M[i * K + c];
-    if (c == i) {
-      dg[i] = M[e];
-      xd[i] = 1.0 / M[e];
-    }
-  }
-  __syncthreads();
-  // X = R^-1, row by row from the bottom: X[i][c] = -(sum_{p=i+1..c} R[i][p] X[p][c]) / R[i][i]
-  // (X strictly upper kept in M's upper part, R strictly upper transposed in M's lower part)
-  for (int i = K - 2; i >= 0; --i) {
-    const int c = i + 1 + (tid >> 3), part = tid & 7;
-    double s = 0.0;
-    if (c < K) {
-      for (int p = i + 1 + part; p <= c; p += 8) {
-        const double xp = (p == c) ? xd[c] : M[p * K + c];
-        s = fma(M[p * K + i], xp, s);
+    const double rjj = rd[j];
+    // (b) row j of R
+    if (ty == oj) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (p != pj) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tx + 32 * q;
+          double v = 0.0;
+          if (c == j) v = rjj;
+          else if (c > j && c < K) v = m[p][q] / rjj;
+          m[p][q] = v;
+          if (c < K) ub[c] = v;
+        }
       }
     }
-    s += __shfl_xor(s, 1, 8);
-    s += __shfl_xor(s, 2, 8);
-    s += __shfl_xor(s, 4, 8);
-    if (c < K && part == 0) M[i * K + c] = -s / dg[i];
     __syncthreads();
+    // (c) trailing update of the elements (i, c) with i, c > j
+    double ui[4], uc[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = ty + 32 * p;
+      ui[p] = (i > j && i < K) ? ub[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tx + 32 * q;
+      uc[q] = (c > j && c < K) ? ub[c] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m[p][q] = fma(-ui[p], uc[q], m[p][q]);
   }
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    Rinv[e] = c > i ? M[e] : (c == i ? xd[i] : 0.0);
+  // R out (upper part; rows below their diagonal hold zeros from step (b))
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 32 * p, c = tx + 32 * q;
+      if (i < K && c < K) {
+        const double v = c >= i ? m[p][q] : 0.0;
+        R[i * K + c] = v;
+        Rs[i * KM + c] = v;
+      }
+    }
+  // X = R^-1: B starts as the identity
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[p][q] = (ty + 32 * p == tx + 32 * q) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int i = K - 1; i >= 0; --i) {
+    const int pi = i >> 5, oi = i & 31, buf = i & 1;
+    if (ty == oi) {
+      const double rii = rd[i];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (p != pi) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tx + 32 * q;
+          const double v = (c >= i && c < K) ? m[p][q] / rii : 0.0;
+          m[p][q] = v;
+          if (c < K) xb[buf][c] = v;
+        }
+      }
+    }
+    __syncthreads();
+    double xc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tx + 32 * q;
+      xc[q] = (c >= i && c < K) ? xb[buf][c] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int r = ty + 32 * p;
+      if (r < i) {
+        const double rpi = Rs[r * KM + i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[p][q] = fma(-rpi, xc[q], m[p][q]);
+      }
+    }
   }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 32 * p, c = tx + 32 * q;
+      if (i < K && c < K) Rinv[i * K + c] = c >= i ? m[p][q] : 0.0;
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -1,30 +1,41 @@
 // Streaming kernels of one pass over X (block power step, minibatch step and
 // pPCA projection, Alg. 1 steps 2-3 and Sec. 2.1):
 //
-//   ppca_xv   : Y = X V'           (row panels of X, full d per workgroup)
-//   ppca_xty  : [Z ; G] = [X | Y]^T Y over row splits (partial per split)
+//   k_xv      : Y = X V' and the partial Grams G_w = Y^T Y of workgroup w
+//               (persistent over row tiles of 64/128/256 rows, full d per tile)
+//   k_xty     : Z = X^T Y over (256-column tile, row split) pairs
 //   reduce_zg : fixed-order float64 sum of the partials -> Z (f32), G (f64)
 //
-// bf16 and fp8 data run on v_mfma_f32_16x16x32_bf16 (fp8 codes are widened
-// to bf16 exactly); float32 data runs on v_mfma_f32_16x16x4_f32.  All
-// accumulation inside a workgroup is float32; partials of different row
-// splits are summed in float64 in a fixed order, so results are bitwise
+// The projection pass only needs G, so it runs k_xv alone (one read of X, no
+// Y written).  bf16 and fp8 data run on v_mfma_f32_16x16x32_bf16 (fp8 codes
+// are widened to bf16 exactly when read from LDS); float32 data runs on
+// v_mfma_f32_16x16x4_f32.  Accumulation inside a workgroup is float32;
+// partials are summed in float64 in a fixed order, so results are bitwise
 // reproducible run to run.
+//
+// Pipeline (both kernels): each k-step's tiles of X and of the second operand
+// are loaded into registers several steps ahead, written to one of two LDS
+// buffers one step ahead, and consumed from LDS by the MFMA loop; one barrier
+// per k-step.  LDS rows are XOR-swizzled at 16-byte granularity so that the
+// fragment reads of a wavefront hit distinct banks.
 //
 // Layouts
 //   X     row-major [n][ld] (element type per dtype); pass row i is data row
 //         (r0 + i) mod n.
 //   V'^T  operand [Kp][dp] (bf16 or f32), zero padded in both directions.
-//   Y     "blocked" staging buffer so that the X^T Y kernel can read 8 (bf16)
-//         or 4 (f32) consecutive rows of one Y column as a single 16-byte load:
+//   Y     "blocked" staging buffer so that the X^T Y kernel reads 8 (bf16) or
+//         4 (f32) consecutive rows of one Y column as one 16-byte chunk:
 //         bf16: yb[row/8][Kp][8], f32: yb[row/4][Kp][4].
 //   part  [tile][split][Kp][256] float32: column c of tile t is column
-//         t*256 + c of X (tiles 0..T-2) or column c of Y (last tile).
+//         t*256 + c of X.
+//   gpart [workgroup of k_xv][Kp][Kp] float32.
 #include "ppca_common.h"
 
 namespace ppca {
 
 namespace {
+
+constexpr int DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2;
 
 __device__ inline bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
 
@@ -36,295 +47,552 @@ __device__ inline uint2 fp8x4_to_bf16x4(uint32_t w) {
   return r;
 }
 
-// 8 consecutive bf16 of a row starting at column `col` (zero beyond d).
-template <bool FP8>
-__device__ inline uint4 load_row8(const uint8_t* rowp, int64_t col, int64_t d) {
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (col + 8 <= d) {
-    if (FP8) {
-      const uint2 w = *reinterpret_cast<const uint2*>(rowp + col);
-      const uint2 lo = fp8x4_to_bf16x4(w.x), hi = fp8x4_to_bf16x4(w.y);
-      v = make_uint4(lo.x, lo.y, hi.x, hi.y);
-    } else {
-      v = *reinterpret_cast<const uint4*>(rowp + col * 2);
-    }
-  } else if (col < d) {
-    uint32_t h[8];
+// Mask of the elements of a 16-byte chunk (EB bytes per element) whose
+// column index col + e is below d: whole words are kept or cleared, a word
+// holding a valid and an invalid element keeps its low half.
+template <int EB>
+__device__ inline uint4 chunk_mask(int64_t col, int64_t d) {
+  constexpr int NE = 16 / EB;
+  int64_t nv = d - col;
+  nv = nv < 0 ? 0 : (nv > NE ? NE : nv);
+  const int v = (int)nv * EB;              // valid bytes in the chunk
+  uint32_t w[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      uint32_t b = 0;
-      if (col + e < d) {
-        b = FP8 ? e4m3_to_bf16_bits(rowp[col + e])
-                : (uint32_t)reinterpret_cast<const uint16_t*>(rowp)[col + e];
-      }
-      h[e] = b;
-    }
-    v = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                   h[6] | (h[7] << 16));
+  for (int i = 0; i < 4; ++i) {
+    const int b = v - 4 * i;               // valid bytes in word i
+    w[i] = b >= 4 ? 0xFFFFFFFFu : (b <= 0 ? 0u : (0xFFFFFFFFu >> (8 * (4 - b))));
   }
-  return v;
+  return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// 4 consecutive bf16 of a row starting at column `col` (zero beyond d).
-template <bool FP8>
-__device__ inline uint2 load_row4(const uint8_t* rowp, int64_t col, int64_t d) {
-  uint2 v = make_uint2(0, 0);
-  if (col + 4 <= d) {
-    if (FP8) {
-      v = fp8x4_to_bf16x4(*reinterpret_cast<const uint32_t*>(rowp + col));
-    } else {
-      v = *reinterpret_cast<const uint2*>(rowp + col * 2);
-    }
-  } else if (col < d) {
-    uint32_t h[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      uint32_t b = 0;
-      if (col + e < d) {
-        b = FP8 ? e4m3_to_bf16_bits(rowp[col + e])
-                : (uint32_t)reinterpret_cast<const uint16_t*>(rowp)[col + e];
-      }
-      h[e] = b;
-    }
-    v = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-  }
-  return v;
+__device__ inline uint4 and4(uint4 a, uint4 m) {
+  return make_uint4(a.x & m.x, a.y & m.y, a.z & m.z, a.w & m.w);
 }
 
-__device__ inline float4 load_row4_f32(const float* rowp, int64_t col, int64_t d) {
-  if (col + 4 <= d) return *reinterpret_cast<const float4*>(rowp + col);
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (col + 0 < d) v.x = rowp[col + 0];
-  if (col + 1 < d) v.y = rowp[col + 1];
-  if (col + 2 < d) v.z = rowp[col + 2];
-  return v;
-}
-
-__device__ inline int64_t wrap_row(int64_t r, int64_t n) { return r < n ? r : r % n; }
+// LDS swizzles of the k_xv stages (LDS: 128 bytes per cycle over 32 banks;
+// a 16-byte read serves 8 lanes per pass, an 8-byte read 16 lanes).
+// 64-byte rows (bf16 X, V', f32 X): chunk c of row r sits at c ^ sw64(r), so
+// that the 8 consecutive rows read by one pass (and the 16 of a 256-byte
+// pass) land on distinct 16-byte bank groups.
+__device__ inline int sw64(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+// 32-byte rows (fp8 X): 8-byte piece p of row r sits at p ^ sw32(r), so that
+// the 16 rows read by one 8-byte pass land on distinct 8-byte bank groups.
+__device__ inline int sw32(int r) { return (r >> 2) & 3; }
 
 // ---------------------------------------------------------------------------
-// Y = X V'   (bf16 / fp8 data).  Workgroup: 4 waves x (MW x 16) rows.
+// Y = X V' and G = Y^T Y.  Persistent: workgroup w takes the row tiles
+// w, w + gridDim.x, ... (WGR = 4 waves x MW x 16 rows each).  Per tile, the
+// k-loop (32 columns per step, 16 for f32) runs a software pipeline: the X and
+// V' tiles of a step are loaded into registers PSX-1 steps ahead (PSX register
+// stages), written to one of two LDS buffers one step ahead and consumed by
+// the MFMAs; one barrier per step.  After the k-loop the tile of Y goes to
+// LDS (over the pipeline buffers, blocked layout below), is copied to global
+// memory when the pass needs it (WANT_Y) and feeds G += Y^T Y.  The G
+// accumulators of a lane live in LDS slots private to that lane between
+// tiles (they are only needed in the tile epilogue), which leaves the
+// register file to the Y accumulators and the in-flight stages; the G
+// partial of the workgroup is written once at the end.
 // ---------------------------------------------------------------------------
-template <int NB, int MW, bool FP8>
-__global__ __launch_bounds__(256) void k_xv_b16(const uint8_t* __restrict__ x, int64_t n,
-                                                int64_t d, int64_t ld, int64_t rstart,
-                                                int64_t rows, const uint16_t* __restrict__ vop,
-                                                int64_t dp, uint16_t* __restrict__ yb) {
-  constexpr int ES = FP8 ? 1 : 2;
+template <int... I, typename F>
+__device__ __attribute__((always_inline)) inline void unroll_seq(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
+// The streamed pointers are deliberately not __restrict__: loads through
+// restrict-qualified read-only kernel arguments may be moved down to their
+// use, which would collapse the pipeline.
+template <int NB, int DT, int MW, int PSX, bool WANT_Y, bool WANT_G>
+__global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                               int64_t rstart, int64_t rows, const uint8_t* vop,
+                                               int64_t dp, uint8_t* yb, float* gpart,
+                                               int accumulate) {
   constexpr int Kp = NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NBG = (NB + 3) / 4;                               // G column blocks per wave
+  constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
+  constexpr int OB = DT == DT_F32 ? 4 : 2;                        // bytes per operand element
+  constexpr int YB = OB;                                          // bytes per Y element
+  constexpr int YR = 16 / YB;                                     // rows per Y chunk (8 or 4)
+  constexpr int KS = DT == DT_F32 ? 16 : 32;                      // columns per k-step
+  constexpr int WGR = 4 * MW * 16;                                // rows per tile
+  constexpr int XCPR = KS * EB / 16;                              // 16-B chunks per X row (4 or 2)
+  constexpr int XSTB = WGR * XCPR * 16;                           // X bytes per stage
+  constexpr int XCHT = XSTB / 16;                                 // X chunks per stage
+  constexpr int XCH = (XCHT + 255) / 256;                         // X chunks per thread
+  constexpr int VSTB = Kp * 64;                                   // V' bytes per stage (4 chunks/row)
+  constexpr int VCH = (Kp * 4 + 255) / 256;                       // V' chunks per thread
+  constexpr int YTB = WGR * Kp * YB;                              // Y tile bytes
+  constexpr int YTCHT = YTB / 16;                                 // Y tile chunks
+  constexpr int PIPEB = 2 * (XSTB + VSTB);
+  constexpr int REGA = PIPEB > YTB ? PIPEB : YTB;                 // pipeline buffers / Y tile
+  constexpr int GSLOT = WANT_G ? NB * NBG * 4 * 64 * 16 : 16;    // G accumulator slots
+  static_assert(PSX % 2 == 0, "the LDS buffer of a step is its parity");
+  __shared__ __attribute__((aligned(16))) uint8_t lds[REGA + GSLOT];
+  uint8_t* const ylds = lds;
+  f32x4_t* const gslot = reinterpret_cast<f32x4_t*>(lds + REGA);
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = lane & 15, g = lane >> 4;
-  const int64_t li0 = (int64_t)blockIdx.x * (4 * MW * 16) + wave * (MW * 16);
+  const uint32_t keep = dp > 0 ? 0xFFFFFFFFu : 0u;   // all ones, opaque to the compiler
+  const int64_t ntile = (rows + WGR - 1) / WGR;
 
-  const uint8_t* rowp[MW];
-  bool rv[MW];
+  // lane-private G slot of block (mb, q): ((mb * NBG + q) * 4 + wave) * 64 + lane
+  auto gs = [&](int mb, int q) __attribute__((always_inline)) -> f32x4_t& { return gslot[((mb * NBG + q) * 4 + wave) * 64 + lane]; };
+  if (WANT_G) {
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb) {
-    const int64_t li = li0 + mb * 16 + a;
-    rv[mb] = li < rows;
-    const int64_t r = rv[mb] ? (rstart + li) % n : 0;
-    rowp[mb] = x + r * ld * ES;
+    for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+      for (int q = 0; q < NBG; ++q) gs(mb, q) = f32x4_t{0.f, 0.f, 0.f, 0.f};
   }
-  const uint16_t* vp = vop + (int64_t)a * dp + 8 * g;
 
+  // X chunk s of a stage = (row s / XCPR, chunk s % XCPR), swizzled in LDS;
+  // threads past the last chunk repeat an earlier one (identical writes)
+  // (fp8: the two 8-byte halves of a chunk go to xdst and xdst2)
+  int xrow[XCH], xdst[XCH], xdst2[XCH], xcol[XCH];
+#pragma unroll
+  for (int j = 0; j < XCH; ++j) {
+    const int s = (t + 256 * j) % XCHT, r = s / XCPR, c = s % XCPR;
+    xrow[j] = r;
+    xcol[j] = c * (16 / EB);
+    if (XCPR == 4) {
+      xdst[j] = (r * 4 + (c ^ sw64(r))) * 16;
+      xdst2[j] = 0;
+    } else {
+      xdst[j] = r * 32 + ((2 * c) ^ sw32(r)) * 8;
+      xdst2[j] = r * 32 + ((2 * c + 1) ^ sw32(r)) * 8;
+    }
+  }
+  // V' chunks: threads past the last chunk repeat an earlier one
+  const uint8_t* vsrc[VCH];
+  int vdst[VCH];
+#pragma unroll
+  for (int j = 0; j < VCH; ++j) {
+    const int s = (t + 256 * j) % (Kp * 4), r = s >> 2, c = s & 3;
+    vsrc[j] = vop + ((int64_t)r * dp) * OB + c * 16;
+    vdst[j] = (r * 4 + (c ^ sw64(r))) * 16;
+  }
+
+  // Y accumulators: zeroed once here and cleared after each tile's epilogue
+  // (zeroing them at the top of every tile makes the register allocator
+  // rotate them through extra registers inside the k-loop)
   f32x4_t acc[MW][NB];
 #pragma unroll
   for (int mb = 0; mb < MW; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  uint4 an[MW], bn[NB];
+  for (int64_t tl = blockIdx.x; tl < ntile; tl += gridDim.x) {
+    const int64_t row0 = tl * WGR;
+    // per-tile row sources: rows past the pass read a valid row, masked at the LDS write
+    const uint8_t* xsrc[XCH];
+    uint32_t xrowm[XCH];
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb)
-    an[mb] = rv[mb] ? load_row8<FP8>(rowp[mb], 8 * g, d) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-    bn[nb] = *reinterpret_cast<const uint4*>(vp + (int64_t)nb * 16 * dp);
-
-  for (int64_t k0 = 0; k0 < d; k0 += 32) {
-    uint4 ac[MW], bc[NB];
-#pragma unroll
-    for (int mb = 0; mb < MW; ++mb) ac[mb] = an[mb];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) bc[nb] = bn[nb];
-    const int64_t kn = k0 + 32;
-    if (kn < d) {
-#pragma unroll
-      for (int mb = 0; mb < MW; ++mb)
-        an[mb] = rv[mb] ? load_row8<FP8>(rowp[mb], kn + 8 * g, d) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bn[nb] = *reinterpret_cast<const uint4*>(vp + (int64_t)nb * 16 * dp + kn);
+    for (int j = 0; j < XCH; ++j) {
+      const int64_t li = row0 + xrow[j];
+      const bool ok = li < rows;
+      xrowm[j] = ok ? 0xFFFFFFFFu : 0u;
+      xsrc[j] = x + ((rstart + (ok ? li : 0)) % n) * ld * EB;
     }
-#pragma unroll
-    for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ac[mb]),
-                                                              as_bf16x8(bc[nb]),
-                                                              acc[mb][nb], 0, 0, 0);
-  }
 
-  // D[i][j]: lane (j = a, g) holds rows 4g..4g+3 of each 16-row block.
+    uint4 xr[PSX][XCH], vr[PSX][VCH];
+    auto gload = [&](int64_t k0, uint4 (&xo)[XCH], uint4 (&vo)[VCH]) __attribute__((always_inline)) {
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb) {
-    const int64_t li = li0 + mb * 16 + 4 * g;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      uint2 w;
-      w.x = f32_to_bf16_bits(acc[mb][nb][0]) | (f32_to_bf16_bits(acc[mb][nb][1]) << 16);
-      w.y = f32_to_bf16_bits(acc[mb][nb][2]) | (f32_to_bf16_bits(acc[mb][nb][3]) << 16);
-      uint16_t* dst = yb + (((li >> 3) * Kp + nb * 16 + a) << 3) + (li & 7);
-      *reinterpret_cast<uint2*>(dst) = w;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Y = X V'   (float32 data), v_mfma_f32_16x16x4_f32.
-// ---------------------------------------------------------------------------
-template <int NB, int MW>
-__global__ __launch_bounds__(256) void k_xv_f32(const float* __restrict__ x, int64_t n,
-                                                int64_t d, int64_t ld, int64_t rstart,
-                                                int64_t rows, const float* __restrict__ vop,
-                                                int64_t dp, float* __restrict__ yb) {
-  constexpr int Kp = NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int a = lane & 15, g = lane >> 4;
-  const int64_t li0 = (int64_t)blockIdx.x * (4 * MW * 16) + wave * (MW * 16);
-
-  const float* rowp[MW];
-  bool rv[MW];
-#pragma unroll
-  for (int mb = 0; mb < MW; ++mb) {
-    const int64_t li = li0 + mb * 16 + a;
-    rv[mb] = li < rows;
-    const int64_t r = rv[mb] ? (rstart + li) % n : 0;
-    rowp[mb] = x + r * ld;
-  }
-  const float* vp = vop + (int64_t)a * dp + 4 * g;
-
-  f32x4_t acc[MW][NB];
-#pragma unroll
-  for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-  float4 an[MW], bn[NB];
-  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-  for (int mb = 0; mb < MW; ++mb) an[mb] = rv[mb] ? load_row4_f32(rowp[mb], 4 * g, d) : z4;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-    bn[nb] = *reinterpret_cast<const float4*>(vp + (int64_t)nb * 16 * dp);
-
-  for (int64_t k0 = 0; k0 < d; k0 += 16) {
-    float4 ac[MW], bc[NB];
-#pragma unroll
-    for (int mb = 0; mb < MW; ++mb) ac[mb] = an[mb];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) bc[nb] = bn[nb];
-    const int64_t kn = k0 + 16;
-    if (kn < d) {
-#pragma unroll
-      for (int mb = 0; mb < MW; ++mb)
-        an[mb] = rv[mb] ? load_row4_f32(rowp[mb], kn + 4 * g, d) : z4;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bn[nb] = *reinterpret_cast<const float4*>(vp + (int64_t)nb * 16 * dp + kn);
-    }
-#pragma unroll
-    for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[mb].x, bc[nb].x, acc[mb][nb], 0, 0, 0);
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[mb].y, bc[nb].y, acc[mb][nb], 0, 0, 0);
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[mb].z, bc[nb].z, acc[mb][nb], 0, 0, 0);
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[mb].w, bc[nb].w, acc[mb][nb], 0, 0, 0);
+      for (int j = 0; j < XCH; ++j) {
+        const int64_t col = k0 + xcol[j];
+        const int64_t ce = col < d ? col : 0;
+        xo[j] = *reinterpret_cast<const uint4*>(xsrc[j] + ce * EB);
       }
-  }
-
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb) {
-    const int64_t li = li0 + mb * 16 + 4 * g;
+      for (int j = 0; j < VCH; ++j) vo[j] = *reinterpret_cast<const uint4*>(vsrc[j] + k0 * OB);
+    };
+    // mask (rows past the pass, columns past d) and write one stage to LDS;
+    // the AND on V' also keeps the compiler from fusing load and store into a
+    // memcpy placed here (which would move the load down to this point)
+    auto lwrite = [&](int buf, int64_t k0, const uint4 (&xi)[XCH], const uint4 (&vi)[VCH]) __attribute__((always_inline)) {
+      uint8_t* xs = lds + buf * (XSTB + VSTB);
+      uint8_t* vs = xs + XSTB;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      float* dst = yb + (((li >> 2) * Kp + nb * 16 + a) << 2);
-      *reinterpret_cast<float4*>(dst) =
-          make_float4(acc[mb][nb][0], acc[mb][nb][1], acc[mb][nb][2], acc[mb][nb][3]);
-    }
-  }
-}
-
-// block id -> (tile, split) so that all tiles of one row split run on the
-// same XCD (block b is dispatched to XCD b mod 8) and share Y through its L2.
-__device__ inline void xty_tile_split(int ntiles, int& tile, int& split) {
-  const int b = blockIdx.x;
-  const int xcd = b & 7, slot = b >> 3;
-  tile = slot % ntiles;
-  split = (slot / ntiles) * 8 + xcd;
-}
-
-__device__ inline void store_part(float* dst, const float4 v, bool acc) {
-  if (acc) {
-    const float4 o = *reinterpret_cast<const float4*>(dst);
-    *reinterpret_cast<float4*>(dst) = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
-  } else {
-    *reinterpret_cast<float4*>(dst) = v;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// [Z ; G] partials, bf16 / fp8 data.  Tile t < ntiles-1: 256 columns of X
-// (64 per wave); tile ntiles-1: the Kp columns of Y (Gram).  Rows of split s:
-// [s*rps, min(rows, (s+1)*rps)).
-// ---------------------------------------------------------------------------
-template <int NB, bool FP8>
-__global__ __launch_bounds__(256) void k_xty_b16(const uint8_t* __restrict__ x, int64_t n,
-                                                 int64_t d, int64_t ld, int64_t rstart,
-                                                 int64_t rows, int64_t rps,
-                                                 const uint16_t* __restrict__ yb,
-                                                 float* __restrict__ part, int ntiles,
-                                                 int nsplit, int tile_base, int accumulate) {
-  constexpr int ES = FP8 ? 1 : 2;
-  constexpr int Kp = NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int a = lane & 15, g = lane >> 4;
-  int tile, split;
-  xty_tile_split(ntiles, tile, split);
-  tile += tile_base;
-  const int64_t rbeg = (int64_t)split * rps;
-  const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
-  float* pbase = part + ((int64_t)(tile - tile_base) * nsplit + split) * Kp * 256;
-  const bool gram_tile = (tile == (int)((d + 255) / 256));
-
-  if (!gram_tile) {
-    const int64_t c0 = (int64_t)tile * 256 + wave * 64;
-    if (c0 >= d) return;
-    const int64_t col = c0 + 4 * a;
-    f32x4_t acc[4][NB];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    for (int64_t li = rbeg; li < rend; li += 32) {
-      const int64_t rb = (rstart + li) % n;
-      uint2 in[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int64_t lr = li + 8 * g + r;
-        if (lr < rend) {
-          const int64_t row = wrap_row(rb + 8 * g + r, n);
-          in[r] = load_row4<FP8>(x + row * ld * ES, col, d);
+      for (int j = 0; j < XCH; ++j) {
+        uint4 m = chunk_mask<EB>(k0 + xcol[j], d);
+        m = make_uint4(m.x & xrowm[j], m.y & xrowm[j], m.z & xrowm[j], m.w & xrowm[j]);
+        const uint4 v = and4(xi[j], m);
+        if (XCPR == 4) {
+          *reinterpret_cast<uint4*>(xs + xdst[j]) = v;
         } else {
-          in[r] = make_uint2(0, 0);
+          *reinterpret_cast<uint2*>(xs + xdst[j]) = make_uint2(v.x, v.y);
+          *reinterpret_cast<uint2*>(xs + xdst2[j]) = make_uint2(v.z, v.w);
         }
       }
+#pragma unroll
+      for (int j = 0; j < VCH; ++j)
+        *reinterpret_cast<uint4*>(vs + vdst[j]) = and4(vi[j], make_uint4(keep, keep, keep, keep));
+    };
+
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+      const uint8_t* xs = lds + buf * (XSTB + VSTB);
+      const uint8_t* vs = xs + XSTB;
+      if (DT == DT_F32) {
+        float4 af[MW], bf[NB];
+#pragma unroll
+        for (int mb = 0; mb < MW; ++mb) {
+          const int r = wave * MW * 16 + mb * 16 + a;
+          af[mb] = *reinterpret_cast<const float4*>(xs + (r * 4 + (g ^ sw64(r))) * 16);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int r = nb * 16 + a;
+          bf[nb] = *reinterpret_cast<const float4*>(vs + (r * 4 + (g ^ sw64(r))) * 16);
+        }
+#pragma unroll
+        for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].x, bf[nb].x, acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].y, bf[nb].y, acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].z, bf[nb].z, acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].w, bf[nb].w, acc[mb][nb], 0, 0, 0);
+          }
+      } else {
+        uint4 af[MW], bf[NB];
+#pragma unroll
+        for (int mb = 0; mb < MW; ++mb) {
+          const int r = wave * MW * 16 + mb * 16 + a;
+          if (DT == DT_FP8) {
+            const uint2 w = *reinterpret_cast<const uint2*>(xs + r * 32 + (g ^ sw32(r)) * 8);
+            const uint2 lo = fp8x4_to_bf16x4(w.x), hi = fp8x4_to_bf16x4(w.y);
+            af[mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+          } else {
+            af[mb] = *reinterpret_cast<const uint4*>(xs + (r * 4 + (g ^ sw64(r))) * 16);
+          }
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int r = nb * 16 + a;
+          bf[nb] = *reinterpret_cast<const uint4*>(vs + (r * 4 + (g ^ sw64(r))) * 16);
+        }
+#pragma unroll
+        for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[mb]), as_bf16x8(bf[nb]),
+                                                                  acc[mb][nb], 0, 0, 0);
+      }
+    };
+
+    // Straight-line loop body (a branch between a stage's loads and its LDS
+    // write lets the compiler sink the loads to their use).  Steps past the
+    // last one load a clamped, valid stage and write it with an all-zero
+    // column mask, so their MFMAs add exactly zero.
+    const int nk = (int)((d + KS - 1) / KS);
+    const int64_t klast = (int64_t)(nk - 1) * KS;
+#pragma unroll
+    for (int i = 0; i < PSX - 1; ++i) gload(min((int64_t)i * KS, klast), xr[i], vr[i]);
+    lwrite(0, 0, xr[0], vr[0]);
+    __syncthreads();
+    for (int k = 0; k < nk; k += PSX) {
+      unroll_seq(std::make_integer_sequence<int, PSX>{}, [&](auto I) __attribute__((always_inline)) {
+        constexpr int i = decltype(I)::value;
+        const int kk = k + i;
+        gload(min((int64_t)(kk + PSX - 1) * KS, klast), xr[(i + PSX - 1) % PSX], vr[(i + PSX - 1) % PSX]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(i & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        lwrite((i + 1) & 1, (int64_t)(kk + 1) * KS, xr[(i + 1) % PSX], vr[(i + 1) % PSX]);
+        __syncthreads();
+      });
+    }
+
+    // ---- Y tile -> LDS (over the pipeline buffers: the last barrier of the
+    // k-loop ended every read of them), layout [row/YR][Kp][YR].
+    // D[i][j]: lane (j = a, g) holds rows 4g..4g+3 of each 16-row block.
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb) {
+      const int lr = wave * MW * 16 + mb * 16 + 4 * g;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        if (DT == DT_F32) {
+          *reinterpret_cast<float4*>(ylds + ((lr >> 2) * Kp + nb * 16 + a) * 16) =
+              make_float4(acc[mb][nb][0], acc[mb][nb][1], acc[mb][nb][2], acc[mb][nb][3]);
+        } else {
+          uint2 w;
+          w.x = f32_to_bf16_bits(acc[mb][nb][0]) | (f32_to_bf16_bits(acc[mb][nb][1]) << 16);
+          w.y = f32_to_bf16_bits(acc[mb][nb][2]) | (f32_to_bf16_bits(acc[mb][nb][3]) << 16);
+          *reinterpret_cast<uint2*>(ylds + ((lr >> 3) * Kp + nb * 16 + a) * 16 + (lr & 7) * 2) = w;
+        }
+      }
+    }
+    // clear the accumulators for the next tile: AND with an all-zero word the
+    // compiler cannot see through (an exact +0 whatever the value was)
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[mb][nb][e] = __uint_as_float(__float_as_uint(acc[mb][nb][e]) & ~keep);
+    __syncthreads();
+    if (WANT_Y) {
+      // coalesced copy of the tile to the global staging buffer (same layout)
+      uint8_t* ydst = yb + row0 * Kp * YB;
+      for (int s = t; s < YTCHT; s += 256)
+        *reinterpret_cast<uint4*>(ydst + s * 16) = *reinterpret_cast<const uint4*>(ylds + s * 16);
+    }
+    // G += Y^T Y over the tile's rows; wave w takes the column blocks nb = w (mod 4)
+    // (rows past the pass are zero in Y because their X rows were masked)
+    if constexpr (WANT_G) {
+    constexpr int GS = DT == DT_F32 ? 4 : 8;                       // rows per lane group
+    f32x4_t accg[NB][NBG];
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+      for (int q = 0; q < NBG; ++q) accg[mb][q] = gs(mb, q);
+#pragma unroll
+    for (int r0 = 0; r0 < WGR; r0 += 4 * GS) {
+      const int rg = r0 / YR + g;                                  // chunk row of this lane group
+      if (DT == DT_F32) {
+        float4 yf[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          yf[nb] = *reinterpret_cast<const float4*>(ylds + (rg * Kp + nb * 16 + a) * 16);
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+          for (int q = 0; q < NBG; ++q) {
+            const int nb = wave + 4 * q;
+            if (nb < NB) {
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].x, yf[nb].x, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].y, yf[nb].y, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].z, yf[nb].z, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].w, yf[nb].w, accg[mb][q], 0, 0, 0);
+            }
+          }
+      } else {
+        uint4 yf[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          yf[nb] = *reinterpret_cast<const uint4*>(ylds + (rg * Kp + nb * 16 + a) * 16);
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+          for (int q = 0; q < NBG; ++q) {
+            const int nb = wave + 4 * q;
+            if (nb < NB)
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(yf[mb]), as_bf16x8(yf[nb]),
+                                                                    accg[mb][q], 0, 0, 0);
+          }
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+      for (int q = 0; q < NBG; ++q) gs(mb, q) = accg[mb][q];
+    }
+    __syncthreads();   // the next tile's pipeline overwrites the Y tile
+  }
+  if (!WANT_G) return;
+
+  // G partial of this workgroup: block (mb, nb), lane (j = a, g) holds rows
+  // 16mb + 4g + u, column 16nb + a
+  float* gbase = gpart + (int64_t)blockIdx.x * Kp * Kp;
+#pragma unroll
+  for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+    for (int q = 0; q < NBG; ++q) {
+      const int nb = wave + 4 * q;
+      if (nb >= NB) continue;
+      const f32x4_t v = gs(mb, q);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float* p = gbase + (int64_t)(mb * 16 + 4 * g + u) * Kp + nb * 16 + a;
+        *p = accumulate ? *p + v[u] : v[u];
+      }
+    }
+}
+
+// Block id -> (tile, split).  Block b runs on XCD b mod 8; XCD x takes the
+// contiguous run of (split, tile) pairs [x*per, (x+1)*per) in split-major
+// order, so the tiles of one row split (which all read the same rows of Y)
+// share that XCD's L2.  Blocks past the last pair return at once.
+__device__ inline bool xty_tile_split(int ntiles, int nsplit, int& tile, int& split) {
+  const int b = blockIdx.x;
+  const int total = ntiles * nsplit;
+  const int per = (total + 7) / 8;
+  const int p = (b & 7) * per + (b >> 3);
+  if ((b >> 3) >= per || p >= total) return false;
+  split = p / ntiles;
+  tile = p % ntiles;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Z partials, Z = X^T Y.  Workgroup (tile t, split s): the 256 columns
+// [256t, 256t+256) of X (64 per wave) against all Kp columns of Y over the
+// rows of split s, i.e. rows [s*rps, min(rows, (s+1)*rps)).  k-step = 32 rows
+// (16 for f32).  Same register-staged pipeline as k_xv.
+// Output: part[t][s][Kp][256] float32.
+// ---------------------------------------------------------------------------
+template <int NB, int DT, int PSY>
+__global__ __launch_bounds__(256, 1) void k_xty(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                                int64_t rstart, int64_t rows, int64_t rps,
+                                                const uint8_t* yb, float* part, int ntiles,
+                                                int nsplit, int accumulate) {
+  constexpr int Kp = NB * 16;
+  constexpr int TC = 256;
+  constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
+  constexpr int YB = DT == DT_F32 ? 4 : 2;                        // bytes per Y element
+  constexpr int KS = DT == DT_F32 ? 16 : 32;                      // rows per k-step
+  constexpr int YR = 16 / YB;                                     // rows per Y chunk (8 or 4)
+  constexpr int XRB = TC * EB;                                    // bytes per X row of a tile
+  constexpr int XCPR = XRB / 16;                                  // chunks per X row
+  constexpr int XSTB = KS * XRB;                                  // X bytes per stage
+  constexpr int XCH = XSTB / 16 / 256;                            // X chunks per thread
+  static_assert(XCH * 256 * 16 == XSTB, "whole X chunks per thread");
+  constexpr int YSTB = KS * Kp * YB;                              // Y bytes per stage (NB KB)
+  constexpr int YCHT = YSTB / 16;                                 // Y chunks per stage
+  constexpr int YCH = (YCHT + 255) / 256;                         // Y chunks per thread
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (XSTB + YSTB)];
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int a = lane & 15, g = lane >> 4;
+  int tile, split;
+  if (!xty_tile_split(ntiles, nsplit, tile, split)) return;
+  const int64_t rbeg = (int64_t)split * rps;
+  const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
+  const int64_t c0 = (int64_t)tile * TC;
+
+  // X swizzle: XOR the 16-byte chunk index with a function of the row so that
+  // the 4 lane groups of a fragment read (rows 8 apart; 4 apart for f32) fall
+  // on different banks.  The XOR stays inside the row.
+  auto xswz = [](int r) -> int {
+    if (DT == DT_F32) return ((r >> 2) & 3) << 4;
+    if (DT == DT_BF16) return ((r >> 3) & 3) << 3;
+    return ((r >> 3) & 3) << 2;
+  };
+
+  // ---- loader setup.  A thread keeps the same column chunk for the whole
+  // split (column mask and clamped column are loop invariant) and follows its
+  // data row incrementally (row += KS mod n, with ksn = KS mod n), so the loop
+  // has no division.  Loads are unconditional; rows past the split end and
+  // columns past d are masked to zero at the LDS write.
+  const int64_t ksn = KS % n;
+  int xr_row[XCH], xdst[XCH];
+  const uint8_t* xcp[XCH];     // column base of the chunk
+  int64_t xrow[XCH];           // current data row of the chunk
+  uint4 xmask[XCH];
+#pragma unroll
+  for (int j = 0; j < XCH; ++j) {
+    const int s = t + 256 * j, r = s / XCPR, c = s % XCPR;
+    xr_row[j] = r;
+    const int64_t col = c0 + c * (16 / EB);
+    xcp[j] = x + (col < d ? col : 0) * EB;
+    xmask[j] = chunk_mask<EB>(col, d);
+    xdst[j] = (r * XCPR + (c ^ xswz(r))) * 16;
+    xrow[j] = (rstart + rbeg + r) % n;
+  }
+  // Y chunks (layout [row/YR][Kp][YR] inside a stage); threads past the last
+  // chunk repeat an earlier one.  Rows of a chunk: (s / Kp) * YR + 0..YR-1.
+  int ydst[YCH], yrow[YCH];
+#pragma unroll
+  for (int j = 0; j < YCH; ++j) {
+    const int s = (t + 256 * j) % YCHT;
+    ydst[j] = s * 16;
+    yrow[j] = (s / Kp) * YR;
+  }
+
+  // an empty split (possible for the last splits of a short pass) runs no
+  // step but still writes its zero partial; its clamped Y loads read row 0
+  const int64_t nk = rend > rbeg ? (rend - rbeg + KS - 1) / KS : 0;
+  const int64_t llast = nk > 0 ? rbeg + (nk - 1) * KS : 0;
+
+  uint4 xr[PSY][XCH], yr[PSY][YCH];
+  // loads of the step at pass row li: X rows follow xrow[] (advanced here),
+  // Y rows are clamped to the last step of the split
+  auto gload = [&](int64_t li, uint4 (&xo)[XCH], uint4 (&yo)[YCH]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < XCH; ++j) {
+      xo[j] = *reinterpret_cast<const uint4*>(xcp[j] + xrow[j] * ld * EB);
+      const int64_t nr = xrow[j] + ksn;
+      xrow[j] = nr >= n ? nr - n : nr;
+    }
+    const uint8_t* ysrc = yb + ((li < llast ? li : llast) / YR) * Kp * 16;
+#pragma unroll
+    for (int j = 0; j < YCH; ++j) yo[j] = *reinterpret_cast<const uint4*>(ysrc + ydst[j]);
+  };
+  auto lwrite = [&](int buf, int64_t li, const uint4 (&xi)[XCH], const uint4 (&yi)[YCH]) __attribute__((always_inline)) {
+    uint8_t* xs = lds + buf * (XSTB + YSTB);
+    uint8_t* ys = xs + XSTB;
+#pragma unroll
+    for (int j = 0; j < XCH; ++j) {
+      const uint32_t rm = (li + xr_row[j] < rend) ? 0xFFFFFFFFu : 0u;
+      const uint4 m = make_uint4(xmask[j].x & rm, xmask[j].y & rm, xmask[j].z & rm, xmask[j].w & rm);
+      *reinterpret_cast<uint4*>(xs + xdst[j]) = and4(xi[j], m);
+    }
+    // rows past the split end are zeroed; the AND also keeps the compiler
+    // from fusing the Y load with this store into a memcpy placed here
+#pragma unroll
+    for (int j = 0; j < YCH; ++j) {
+      const uint32_t rm = (li + yrow[j] < rend) ? 0xFFFFFFFFu : 0u;
+      *reinterpret_cast<uint4*>(ys + ydst[j]) = and4(yi[j], make_uint4(rm, rm, rm, rm));
+    }
+  };
+
+  f32x4_t acc[4][NB];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int cw = wave * 64 + 4 * a;   // this lane's first column inside the tile
+
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const uint8_t* xs = lds + buf * (XSTB + YSTB);
+    const uint8_t* ys = xs + XSTB;
+    if (DT == DT_F32) {
+      // k-index of lane group g, MFMA s: row 4g + s of the step
+      float4 bf[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bf[nb] = *reinterpret_cast<const float4*>(ys + (g * Kp + nb * 16 + a) * 16);
+      float4 in[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = 4 * g + s;
+        const int c = cw >> 2;   // chunk of 4 floats
+        in[s] = *reinterpret_cast<const float4*>(xs + (r * XCPR + (c ^ xswz(r))) * 16);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bs[4] = {bf[nb].x, bf[nb].y, bf[nb].z, bf[nb].w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float as[4] = {in[s].x, in[s].y, in[s].z, in[s].w};
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[v], bs[s], acc[v][nb], 0, 0, 0);
+        }
+      }
+    } else {
+      // k-index of lane group g, element e: row 8g + e of the step
       uint4 bf[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const uint4*>(yb + (((li >> 3) + g) * Kp + nb * 16 + a) * 8);
+        bf[nb] = *reinterpret_cast<const uint4*>(ys + (g * Kp + nb * 16 + a) * 16);
+      uint2 in[8];
+#pragma unroll
+      for (int r8 = 0; r8 < 8; ++r8) {
+        const int r = 8 * g + r8;
+        if (DT == DT_FP8) {
+          const int byte = cw;                       // 4 codes at column cw
+          const int c = byte >> 4;
+          const uint32_t w = *reinterpret_cast<const uint32_t*>(
+              xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
+          in[r8] = fp8x4_to_bf16x4(w);
+        } else {
+          const int byte = cw * 2;                   // 4 bf16 at column cw
+          const int c = byte >> 4;
+          in[r8] = *reinterpret_cast<const uint2*>(xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
+        }
+      }
+      // in-register transpose: af[v] = column cw + v over rows 8g .. 8g+7
       uint4 af[4];
       af[0] = make_uint4((in[0].x & 0xFFFFu) | (in[1].x << 16), (in[2].x & 0xFFFFu) | (in[3].x << 16),
                          (in[4].x & 0xFFFFu) | (in[5].x << 16), (in[6].x & 0xFFFFu) | (in[7].x << 16));
@@ -341,165 +609,46 @@ __global__ __launch_bounds__(256) void k_xty_b16(const uint8_t* __restrict__ x, 
           acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[v]), as_bf16x8(bf[nb]),
                                                                acc[v][nb], 0, 0, 0);
     }
-    // lane (j = a, g): acc[v][nb][u] is column c0 + 16g + 4u + v, Y column nb*16 + a
-    const int64_t cl = wave * 64 + 16 * g;
+  };
+
+  // Straight-line pipeline loop (see k_xv); steps past the split end write
+  // all-zero stages, so their MFMAs add exactly zero.
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      float* dst = pbase + (int64_t)(nb * 16 + a) * 256 + cl;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        store_part(dst + 4 * u,
-                   make_float4(acc[0][nb][u], acc[1][nb][u], acc[2][nb][u], acc[3][nb][u]),
-                   accumulate);
-    }
-  } else {
-    // Gram tile: A and B fragments are both slices of Y.
-    constexpr int MB = (NB + 3) / 4;
-    f32x4_t acc[MB][NB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    if (wave >= NB) return;
-    for (int64_t li = rbeg; li < rend; li += 32) {
-      uint4 bf[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const uint4*>(yb + (((li >> 3) + g) * Kp + nb * 16 + a) * 8);
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const int mb = wave + 4 * m;
-        if (mb < NB) {
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(bf[mb]), as_bf16x8(bf[nb]),
-                                                                 acc[m][nb], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      const int mb = wave + 4 * m;
-      if (mb < NB) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          float* dst = pbase + (int64_t)(nb * 16 + a) * 256 + mb * 16 + 4 * g;
-          store_part(dst, make_float4(acc[m][nb][0], acc[m][nb][1], acc[m][nb][2], acc[m][nb][3]),
-                     accumulate);
-        }
-      }
-    }
+  for (int i = 0; i < PSY - 1; ++i) gload(rbeg + (int64_t)i * KS, xr[i], yr[i]);
+  lwrite(0, rbeg, xr[0], yr[0]);
+  __syncthreads();
+  for (int64_t k = 0; k < nk; k += PSY) {
+    unroll_seq(std::make_integer_sequence<int, PSY>{}, [&](auto I) __attribute__((always_inline)) {
+      constexpr int i = decltype(I)::value;
+      const int64_t kk = k + i;
+      gload(rbeg + (kk + PSY - 1) * KS, xr[(i + PSY - 1) % PSY], yr[(i + PSY - 1) % PSY]);
+      __builtin_amdgcn_sched_barrier(0);
+      // LDS buffer = parity of the step (a constant when PSY is even)
+      const int par = PSY % 2 == 0 ? (i & 1) : (int)(kk & 1);
+      compute(par);
+      __builtin_amdgcn_sched_barrier(0);
+      lwrite(par ^ 1, rbeg + (kk + 1) * KS, xr[(i + 1) % PSY], yr[(i + 1) % PSY]);
+      __syncthreads();
+    });
   }
-}
 
-// ---------------------------------------------------------------------------
-// [Z ; G] partials, float32 data, v_mfma_f32_16x16x4_f32, 16 rows per step.
-// ---------------------------------------------------------------------------
-template <int NB>
-__global__ __launch_bounds__(256) void k_xty_f32(const float* __restrict__ x, int64_t n,
-                                                 int64_t d, int64_t ld, int64_t rstart,
-                                                 int64_t rows, int64_t rps,
-                                                 const float* __restrict__ yb,
-                                                 float* __restrict__ part, int ntiles, int nsplit,
-                                                 int tile_base, int accumulate) {
-  constexpr int Kp = NB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int a = lane & 15, g = lane >> 4;
-  int tile, split;
-  xty_tile_split(ntiles, tile, split);
-  tile += tile_base;
-  const int64_t rbeg = (int64_t)split * rps;
-  const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
-  float* pbase = part + ((int64_t)(tile - tile_base) * nsplit + split) * Kp * 256;
-  const bool gram_tile = (tile == (int)((d + 255) / 256));
-  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-
-  if (!gram_tile) {
-    const int64_t c0 = (int64_t)tile * 256 + wave * 64;
-    if (c0 >= d) return;
-    const int64_t col = c0 + 4 * a;
-    f32x4_t acc[4][NB];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    for (int64_t li = rbeg; li < rend; li += 16) {
-      const int64_t rb = (rstart + li) % n;
-      float4 in[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t lr = li + 4 * g + s;
-        if (lr < rend) {
-          const int64_t row = wrap_row(rb + 4 * g + s, n);
-          in[s] = load_row4_f32(x + row * ld, col, d);
-        } else {
-          in[s] = z4;
-        }
-      }
-      float4 bf[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const float4*>(yb + (((li >> 2) + g) * Kp + nb * 16 + a) * 4);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const float bs[4] = {bf[nb].x, bf[nb].y, bf[nb].z, bf[nb].w};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const float as[4] = {in[s].x, in[s].y, in[s].z, in[s].w};
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[v], bs[s], acc[v][nb], 0, 0, 0);
-        }
-      }
-    }
+  if (c0 + wave * 64 < d) {
+    // lane (j = a, g): acc[v][nb][u] is tile column wave*64 + 16g + 4u + v,
+    // Y column nb*16 + a
+    float* pbase = part + ((int64_t)tile * nsplit + split) * Kp * TC;
     const int64_t cl = wave * 64 + 16 * g;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      float* dst = pbase + (int64_t)(nb * 16 + a) * 256 + cl;
+      float* dst = pbase + (int64_t)(nb * 16 + a) * TC + cl;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        store_part(dst + 4 * u,
-                   make_float4(acc[0][nb][u], acc[1][nb][u], acc[2][nb][u], acc[3][nb][u]),
-                   accumulate);
-    }
-  } else {
-    constexpr int MB = (NB + 3) / 4;
-    f32x4_t acc[MB][NB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    if (wave >= NB) return;
-    for (int64_t li = rbeg; li < rend; li += 16) {
-      float4 bf[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const float4*>(yb + (((li >> 2) + g) * Kp + nb * 16 + a) * 4);
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const int mb = wave + 4 * m;
-        if (mb < NB) {
-          const float am[4] = {bf[mb].x, bf[mb].y, bf[mb].z, bf[mb].w};
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const float bs[4] = {bf[nb].x, bf[nb].y, bf[nb].z, bf[nb].w};
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-              acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], bs[s], acc[m][nb], 0, 0, 0);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      const int mb = wave + 4 * m;
-      if (mb < NB) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          float* dst = pbase + (int64_t)(nb * 16 + a) * 256 + mb * 16 + 4 * g;
-          store_part(dst, make_float4(acc[m][nb][0], acc[m][nb][1], acc[m][nb][2], acc[m][nb][3]),
-                     accumulate);
+      for (int u = 0; u < 4; ++u) {
+        const float4 v = make_float4(acc[0][nb][u], acc[1][nb][u], acc[2][nb][u], acc[3][nb][u]);
+        float4* p = reinterpret_cast<float4*>(dst + 4 * u);
+        if (accumulate) {
+          const float4 o = *p;
+          *p = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+        } else {
+          *p = v;
         }
       }
     }
@@ -508,47 +657,59 @@ __global__ __launch_bounds__(256) void k_xty_f32(const float* __restrict__ x, in
 
 // ---------------------------------------------------------------------------
 // Fixed-order float64 reduction of the partials.
-// Z[j][c] = s_j * sum_split part[tile(j)][split][c][j mod 256]   (j < d, c < K)
-// G[i][c] = sum_split part[gram][split][c][i]  for i <= c, mirrored.
+// Blocks [0, zblocks): Z[j][c] = s_j * sum_split part[j / 256][split][c][j mod 256]
+//   (j < d, c < K; consecutive threads take consecutive j of one column c).
+// Blocks [zblocks, ...): 64 consecutive elements (i, c) of G each; the 4
+//   wavefronts sum the k_xv partials in 4 contiguous ranges, then wavefront 0
+//   adds the 4 range sums in order: G[i][c] = sum_w gpart[w][i][c], i <= c,
+//   mirrored.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce_zg(const float* __restrict__ part, int nsplit,
-                                                   int Kp, int64_t d, int K,
+__global__ __launch_bounds__(256) void k_reduce_zg(const float* __restrict__ part,
+                                                   const float* __restrict__ gpart, int nsplit,
+                                                   int ngpart, int Kp, int64_t d, int K,
                                                    const float* __restrict__ scale,
                                                    float* __restrict__ Z, double* __restrict__ G,
-                                                   double* __restrict__ Gc, int gram_only,
+                                                   double* __restrict__ Gc, int zblocks,
                                                    int* status) {
-  const int64_t gtile = (d + 255) / 256;
-  const int64_t nz = gram_only ? 0 : d * K;
-  const int64_t ng = (int64_t)K * K;
-  const int64_t tile_stride = (int64_t)nsplit * Kp * 256;
-  const int64_t gbase = gram_only ? 0 : gtile * tile_stride;
+  constexpr int TC = 256;
+  __shared__ double gsum[4][64];
   bool bad = false;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nz + ng;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    if (e < nz) {
-      // consecutive threads take consecutive rows j for one column c
+  if ((int)blockIdx.x < zblocks) {
+    const int64_t nz = d * K;
+    const int64_t split_stride = (int64_t)Kp * TC;
+    const int64_t tile_stride = (int64_t)nsplit * split_stride;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nz; e += (int64_t)zblocks * 256) {
       const int64_t c = e / d, j = e % d;
-      const float* p = part + (j / 256) * tile_stride + c * 256 + (j % 256);
+      const float* p = part + (j / TC) * tile_stride + c * TC + (j % TC);
       double s = 0.0;
-      for (int t = 0; t < nsplit; ++t) s += (double)p[(int64_t)t * Kp * 256];
+      for (int t = 0; t < nsplit; ++t) s += (double)p[(int64_t)t * split_stride];
       if (scale) s *= (double)scale[j];
       const float zf = (float)s;
       if (!isfinite(zf)) bad = true;
       Z[j * K + c] = zf;
-    } else {
-      const int64_t f = e - nz;
-      const int64_t i = f / K, c = f % K;
-      if (i <= c) {
-        const float* p = part + gbase + c * 256 + i;
-        double s = 0.0;
-        for (int t = 0; t < nsplit; ++t) s += (double)p[(int64_t)t * Kp * 256];
-        if (!isfinite(s)) bad = true;
-        G[i * K + c] = s;
-        G[c * K + i] = s;
-        if (Gc) {
-          Gc[i * K + c] = s;
-          Gc[c * K + i] = s;
-        }
+    }
+  } else {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t f = (int64_t)(blockIdx.x - zblocks) * 64 + lane;
+    const int64_t i = f / K, c = f % K;
+    const bool act = f < (int64_t)K * K && i <= c;
+    const int per = (ngpart + 3) / 4;
+    const int t0 = w * per, t1 = min(ngpart, t0 + per);
+    double s = 0.0;
+    if (act) {
+      const float* p = gpart + i * Kp + c;
+      for (int t = t0; t < t1; ++t) s += (double)p[(int64_t)t * Kp * Kp];
+    }
+    gsum[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && act) {
+      const double g = ((gsum[0][lane] + gsum[1][lane]) + gsum[2][lane]) + gsum[3][lane];
+      if (!isfinite(g)) bad = true;
+      G[i * K + c] = g;
+      G[c * K + i] = g;
+      if (Gc) {
+        Gc[i * K + c] = g;
+        Gc[c * K + i] = g;
       }
     }
   }
@@ -572,70 +733,92 @@ hipError_t dispatch_nb(int Kp, F&& f) {
 
 }  // namespace
 
-int xty_tiles(int64_t d, int Kp) {
+int xty_cols(int Kp) {
   (void)Kp;
-  return (int)((d + 255) / 256) + 1;
+  return 256;
+}
+
+int xty_blocks_per_cu(int Kp) {
+  (void)Kp;
+  return 1;
+}
+
+int xty_tiles(int64_t d, int Kp) { return (int)cdiv(d, xty_cols(Kp)); }
+
+// Row blocks per wave (MW) of k_xv: 4 (256-row tiles) when the pass is long
+// enough to give every CU several tiles, else 1 (64-row tiles); float32 with
+// K > 64 uses 2 (128-row tiles) so that the float32 Y tile fits in LDS.
+constexpr int xv_wide_nb(int dt) { return dt == DT_F32 ? 4 : 8; }
+
+static int xv_mw(int32_t dtype, int Kp, int64_t rows_cap) {
+  if (rows_cap < (int64_t)kNumCU * 256) return 1;
+  return Kp / 16 > xv_wide_nb(dtype) ? 2 : 4;
+}
+
+// Register stages of the pipelines: bytes of X in flight per CU grow with
+// them, the register file bounds them (6 and 5 leave every instance spill
+// free with at least two stages in flight at each wait).
+constexpr int xv_stages(int dt, int nb, int mw) { return 6; }
+constexpr int xty_stages(int dt, int nb) { return 5; }
+
+int xv_grid(int32_t dtype, int Kp, int64_t rows_cap) {
+  const int64_t tiles = cdiv(rows_cap, 64 * xv_mw(dtype, Kp, rows_cap));
+  return (int)(tiles < kNumCU ? tiles : kNumCU);
 }
 
 hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                     hipStream_t s) {
+                     bool want_y, bool want_g, bool accumulate, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
+  if (!want_y && !want_g) return hipErrorInvalidValue;
   const int64_t rstart = (p.r0 + i0) % p.n;
-  const bool small = rows <= 8192;   // short passes (minibatches): 64-row workgroups
+  const int mw = xv_mw(p.dtype, b.Kp, b.rows_cap);
   return dispatch_nb(b.Kp, [&](auto nbc) -> hipError_t {
     constexpr int NB = decltype(nbc)::value;
-    if (p.dtype == PPCA_F32) {
-      if (small) {
-        const int64_t grid = cdiv(rows, 64);
-        hipLaunchKernelGGL((k_xv_f32<NB, 1>), dim3(grid), dim3(256), 0, s, (const float*)p.x, p.n,
-                           p.d, p.ld, rstart, rows, (const float*)b.vop, b.dp, (float*)b.yb);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d,
+                         p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
+                         accumulate ? 1 : 0);
+    };
+    auto by_mw = [&](auto dtc, auto yc, auto gc) {
+      constexpr int DT = decltype(dtc)::value;
+      constexpr bool WY = decltype(yc)::value, WG = decltype(gc)::value;
+      if (mw == 1) {
+        go(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), WY, WG>);
       } else {
-        const int64_t grid = cdiv(rows, 256);
-        hipLaunchKernelGGL((k_xv_f32<NB, 4>), dim3(grid), dim3(256), 0, s, (const float*)p.x, p.n,
-                           p.d, p.ld, rstart, rows, (const float*)b.vop, b.dp, (float*)b.yb);
+        if constexpr (NB > xv_wide_nb(DT)) go(k_xv<NB, DT, 2, xv_stages(DT, NB, 2), WY, WG>);
+        else go(k_xv<NB, DT, 4, xv_stages(DT, NB, 4), WY, WG>);
       }
-    } else {
-      const bool fp8 = p.dtype == PPCA_FP8_E4M3;
-      const int64_t grid = small ? cdiv(rows, 64) : cdiv(rows, 256);
-      auto args = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d,
-                           p.ld, rstart, rows, (const uint16_t*)b.vop, b.dp, (uint16_t*)b.yb);
-      };
-      if (fp8) {
-        if (small) args(k_xv_b16<NB, 1, true>); else args(k_xv_b16<NB, 4, true>);
-      } else {
-        if (small) args(k_xv_b16<NB, 1, false>); else args(k_xv_b16<NB, 4, false>);
-      }
-    }
+    };
+    auto by_dt = [&](auto yc, auto gc) {
+      if (p.dtype == PPCA_F32) by_mw(std::integral_constant<int, DT_F32>{}, yc, gc);
+      else if (p.dtype == PPCA_BF16) by_mw(std::integral_constant<int, DT_BF16>{}, yc, gc);
+      else by_mw(std::integral_constant<int, DT_FP8>{}, yc, gc);
+    };
+    if (want_y && want_g) by_dt(std::true_type{}, std::true_type{});
+    else if (want_y) by_dt(std::true_type{}, std::false_type{});
+    else by_dt(std::false_type{}, std::true_type{});
     return hipGetLastError();
   });
 }
 
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                      bool accumulate, bool gram_only, hipStream_t s) {
+                      bool accumulate, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   const int64_t rstart = (p.r0 + i0) % p.n;
-  const int ntiles_all = xty_tiles(p.d, b.Kp);
-  const int ntiles = gram_only ? 1 : ntiles_all;
-  const int tile_base = gram_only ? ntiles_all - 1 : 0;
+  const int ntiles = xty_tiles(p.d, b.Kp);
   const int step = p.dtype == PPCA_F32 ? 16 : 32;
   const int64_t rps = round_up(cdiv(rows, b.nsplit), step);
-  const int64_t grid = (int64_t)ntiles * b.nsplit;
+  const int64_t grid = 8 * cdiv((int64_t)ntiles * b.nsplit, 8);
   return dispatch_nb(b.Kp, [&](auto nbc) -> hipError_t {
     constexpr int NB = decltype(nbc)::value;
-    if (p.dtype == PPCA_F32) {
-      hipLaunchKernelGGL((k_xty_f32<NB>), dim3(grid), dim3(256), 0, s, (const float*)p.x, p.n,
-                         p.d, p.ld, rstart, rows, rps, (const float*)b.yb, b.part, ntiles,
-                         b.nsplit, tile_base, accumulate ? 1 : 0);
-    } else if (p.dtype == PPCA_FP8_E4M3) {
-      hipLaunchKernelGGL((k_xty_b16<NB, true>), dim3(grid), dim3(256), 0, s, (const uint8_t*)p.x,
-                         p.n, p.d, p.ld, rstart, rows, rps, (const uint16_t*)b.yb, b.part, ntiles,
-                         b.nsplit, tile_base, accumulate ? 1 : 0);
-    } else {
-      hipLaunchKernelGGL((k_xty_b16<NB, false>), dim3(grid), dim3(256), 0, s, (const uint8_t*)p.x,
-                         p.n, p.d, p.ld, rstart, rows, rps, (const uint16_t*)b.yb, b.part, ntiles,
-                         b.nsplit, tile_base, accumulate ? 1 : 0);
-    }
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d, p.ld,
+                         rstart, rows, rps, (const uint8_t*)b.yb, b.part, ntiles, b.nsplit,
+                         accumulate ? 1 : 0);
+    };
+    if (p.dtype == PPCA_F32) go(k_xty<NB, DT_F32, xty_stages(DT_F32, NB)>);
+    else if (p.dtype == PPCA_BF16) go(k_xty<NB, DT_BF16, xty_stages(DT_BF16, NB)>);
+    else go(k_xty<NB, DT_FP8, xty_stages(DT_FP8, NB)>);
     return hipGetLastError();
   });
 }
@@ -643,11 +826,11 @@ hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_
 hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* col_scale,
                             float* Z, double* G, double* G_copy, bool gram_only, int* status,
                             hipStream_t s) {
-  const int64_t total = (gram_only ? 0 : d * K) + (int64_t)K * K;
-  int64_t grid = cdiv(total, 256);
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_reduce_zg, dim3(grid), dim3(256), 0, s, b.part, b.nsplit, b.Kp, d, K,
-                     col_scale, Z, G, G_copy, gram_only ? 1 : 0, status);
+  int64_t zb = gram_only ? 0 : cdiv(d * K, 256);
+  if (zb > 2048) zb = 2048;
+  const int64_t gb = G ? cdiv((int64_t)K * K, 64) : 0;
+  hipLaunchKernelGGL(k_reduce_zg, dim3(zb + gb), dim3(256), 0, s, b.part, b.gpart, b.nsplit,
+                     b.ngpart, b.Kp, d, K, col_scale, Z, G, G_copy, (int)zb, status);
   return hipGetLastError();
 }
 

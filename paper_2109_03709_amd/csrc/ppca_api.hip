@@ -96,21 +96,22 @@ struct Plan {
   int K = 0, Kp = 0;
   int64_t dp = 0;
   int64_t rows_cap = 0;   // rows of the Y staging buffer
-  int ntiles = 0, nsplit = 0;
+  int ntiles = 0, nsplit = 0, ngpart = 0;
   // offsets
-  size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, z = 0, g = 0, b = 0, gparts = 0,
+  size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
          a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
          sums = 0, cmax = 0, mean = 0;
   size_t total = 0;
 };
 
-int nsplit_for(int ntiles, int64_t rows) {
-  int64_t ns = 512 / ntiles;
-  if (ns < 8) ns = 8;
-  const int64_t by_rows = round_up(cdiv(rows, 64), 8);
+// Row splits of the X^T Y kernel: one workgroup per resident slot (the
+// kernel's workgroups per CU times the CU count), at least 64 rows per split.
+int nsplit_for(int ntiles, int Kp, int64_t rows) {
+  int64_t ns = (int64_t)kNumCU * xty_blocks_per_cu(Kp) / ntiles;
+  const int64_t by_rows = cdiv(rows, 64);
   if (ns > by_rows) ns = by_rows;
-  if (ns < 8) ns = 8;
-  return (int)round_up(ns, 8);
+  if (ns < 1) ns = 1;
+  return (int)ns;
 }
 
 Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t batch) {
@@ -151,10 +152,16 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   if (chunk > 0 && chunk < pass_rows) pass_rows = round_up(chunk, 256);
   p.rows_cap = round_up(pass_rows, 256);
   const int es_y = dtype == PPCA_F32 ? 4 : 2;
-  p.yb = c.take((size_t)p.rows_cap * p.Kp * es_y);
+  // the projection pass keeps Y on chip (only G = Y^T Y is needed)
+  p.yb = c.take(op == PPCA_OP_PROJECT ? 16 : (size_t)p.rows_cap * p.Kp * es_y);
+  // the Gram-only pass (projection) runs no X^T Y kernel
   p.ntiles = xty_tiles(d, p.Kp);
-  p.nsplit = nsplit_for(p.ntiles, p.rows_cap);
-  p.part = c.take((size_t)p.ntiles * p.nsplit * p.Kp * 256 * sizeof(float));
+  p.nsplit = nsplit_for(p.ntiles, p.Kp, p.rows_cap);
+  p.part = c.take(op == PPCA_OP_PROJECT
+                      ? 16
+                      : (size_t)p.ntiles * p.nsplit * p.Kp * xty_cols(p.Kp) * sizeof(float));
+  p.ngpart = xv_grid(dtype, p.Kp, p.rows_cap);
+  p.gpart = c.take((size_t)p.ngpart * p.Kp * p.Kp * sizeof(float));
   p.z = c.take((size_t)d * K * sizeof(float));
   p.g = c.take(kk);
   p.b = c.take(kk);
@@ -222,12 +229,16 @@ StreamBufs bufs_of(const Plan& p, void* ws) {
   b.dp = p.dp;
   b.yb = at<void>(ws, p.yb);
   b.part = at<float>(ws, p.part);
+  b.gpart = at<float>(ws, p.gpart);
+  b.rows_cap = p.rows_cap;
   b.nsplit = p.nsplit;
+  b.ngpart = p.ngpart;
   b.Kp = p.Kp;
   return b;
 }
 
-// One streaming pass over rows r0 .. r0+nrows-1 (mod n): Z (unless gram_only), G.
+// One streaming pass over rows r0 .. r0+nrows-1 (mod n): Z (unless gram_only) and
+// G (when G is not null).
 int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t nrows, float* Z,
              double* G, double* Gcopy, bool gram_only, hipStream_t s) {
   PassDesc pd;
@@ -243,8 +254,11 @@ int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t 
   const int64_t chunk = (p.rows_cap < nrows) ? p.rows_cap : nrows;
   for (int64_t i0 = 0; i0 < nrows; i0 += chunk) {
     const int64_t rows = (nrows - i0) < chunk ? (nrows - i0) : chunk;
-    HIP_TRY(timed(0, s, [&] { return launch_xv(pd, b, i0, rows, s); }));
-    HIP_TRY(timed(1, s, [&] { return launch_xty(pd, b, i0, rows, i0 > 0, gram_only, s); }));
+    HIP_TRY(timed(0, s, [&] {
+      return launch_xv(pd, b, i0, rows, !gram_only, G != nullptr, i0 > 0, s);
+    }));
+    if (!gram_only)
+      HIP_TRY(timed(1, s, [&] { return launch_xty(pd, b, i0, rows, i0 > 0, s); }));
   }
   HIP_TRY(launch_reduce_zg(b, X->d, p.K, X->dtype == PPCA_FP8_E4M3 ? X->col_scale : nullptr, Z, G,
                            Gcopy, gram_only, at<int>(ws, p.status), s));
@@ -378,7 +392,9 @@ int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters, 
   for (int t = 0; t < iters; ++t) {
     RET_IF(make_operand(X, V, p, ws, s));
     if (b_hist) RET_IF(operand_gram(X, p, ws, b_hist + t * kk, s));
-    RET_IF(run_pass(X, p, ws, 0, X->n, Z, G, gram_hist ? gram_hist + t * kk : nullptr, false, s));
+    // G = Y^T Y is only formed when the caller asks for its history
+    RET_IF(run_pass(X, p, ws, 0, X->n, Z, gram_hist ? G : nullptr,
+                    gram_hist ? gram_hist + t * kk : nullptr, false, s));
     RET_IF(cholqr2(Z, V, X->d, K, p, ws, s));
   }
   return finish(p, ws, s);

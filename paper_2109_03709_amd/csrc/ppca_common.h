@@ -11,9 +11,6 @@ namespace ppca {
 
 // ---------------------------------------------------------------- constants
 constexpr int kMaxK = PPCA_MAX_K;          // largest K = k + l
-constexpr int kXvRows = 256;               // rows of X per workgroup in the X V' kernel
-constexpr int kXtyCols = 256;              // columns of [X | Y] per workgroup in the X^T Y kernel
-constexpr int kXtyStep = 32;               // rows per k-step of the X^T Y kernel
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -67,17 +64,24 @@ struct StreamBufs {
   const void* vop;      // operand V'^T: [Kp][dp] bf16 (bf16/fp8 data) or f32 (f32 data)
   int64_t dp;           // padded d of the operand
   void* yb;             // Y staging buffer (blocked rows), sized for chunk rows
-  float* part;          // partials [ntiles][nsplit][Kp][256]
-  int nsplit;           // row splits of the X^T Y kernel (multiple of 8)
+  int64_t rows_cap;     // rows the staging buffer holds (largest chunk of a pass)
+  float* part;          // Z partials [ntiles][nsplit][Kp][xty_cols(Kp)]
+  float* gpart;         // G partials [ngpart][Kp][Kp], one per k_xv workgroup
+  int nsplit;           // row splits of the X^T Y kernel
+  int ngpart;           // workgroups of k_xv (fixed for all chunks of a pass)
   int Kp;               // K padded to 16
 };
 
 // stream kernels (k_stream.hip)
-int xty_tiles(int64_t d, int Kp);  // tiles of [X | Y] columns (last one = Y)
+int xty_cols(int Kp);              // columns per tile of the X^T Y kernel
+int xty_blocks_per_cu(int Kp);     // resident workgroups per CU of the X^T Y kernel
+constexpr int kNumCU = 256;        // compute units of an MI355X
+int xty_tiles(int64_t d, int Kp);  // column tiles of X in the X^T Y kernel
+int xv_grid(int32_t dtype, int Kp, int64_t rows_cap);   // workgroups of k_xv
 hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                     hipStream_t s);
+                     bool want_y, bool want_g, bool accumulate, hipStream_t s);
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                      bool accumulate, bool gram_only, hipStream_t s);
+                      bool accumulate, hipStream_t s);
 hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* col_scale,
                             float* Z, double* G, double* G_copy, bool gram_only, int* status,
                             hipStream_t s);
