@@ -158,6 +158,7 @@ def main():
            "config": {"workload": f"ppca-power-{a.storage}", "n": n, "d": d, "k": k, "l": l,
                       "power_iters": iters, "spectrum": a.spectrum, "x_reads_per_step": x_reads,
                       "chunk_rows": a.chunk_rows},
+           "x_stream_per_pass_GBs": round((iters + 1) * xbytes / (ms_per_step * 1e-3) / 1e9, 2),
            "accuracy": {"max_rel_eig_err": rel, "sin_theta_max": sin_t},
            "prep_ms": round(prep_ms, 2),
            "roofline": roofline}
