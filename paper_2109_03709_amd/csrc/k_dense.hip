@@ -50,237 +50,272 @@ __global__ __launch_bounds__(256) void k_make_operand(const float* __restrict__ 
 }
 
 // --------------------------------------------------------------------------
-// Gram partials: parts[w] = A[rows of w]^T A[rows of w], 64 rows per block.
+// Gram partials of a (rows x K) matrix A: block (tile pair, chunk) computes the
+// 32 x 32 tile (ti, tj), ti <= tj, of A[rows of chunk]^T A[rows of chunk] in
+// float64; parts[chunk] holds the upper tiles.  k_sum_gram adds the chunks in
+// order and mirrors the lower tiles.
 // --------------------------------------------------------------------------
-constexpr int kGramRows = 64;
+constexpr int kGT = 32;            // Gram output tile
+constexpr int kGR = 64;            // rows staged per step
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int64_t rows, int K,
-                                                   int64_t lda, double* __restrict__ parts) {
-  __shared__ double tile[kGramRows * kMaxK];
-  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
-  const int nr = (int)((rows - r0) < kGramRows ? (rows - r0) : kGramRows);
-  for (int e = threadIdx.x; e < kGramRows * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    tile[r * K + c] = r < nr ? (double)A[(r0 + r) * lda + c] : 0.0;
+__global__ __launch_bounds__(256) void k_gram_tile(const T* __restrict__ A, int64_t rows, int K,
+                                                   int64_t lda, int nchunk,
+                                                   double* __restrict__ parts) {
+  __shared__ double Ai[kGR][kGT + 1], Aj[kGR][kGT + 1];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int nt = (K + kGT - 1) / kGT;
+  int pidx = blockIdx.x, ti = 0;
+  while (pidx >= nt - ti) {
+    pidx -= nt - ti;
+    ++ti;
   }
-  __syncthreads();
-  const int kq = (K + 3) / 4;
-  double* out = parts + (int64_t)blockIdx.x * K * K;
-  for (int blk = threadIdx.x; blk < kq * kq; blk += blockDim.x) {
-    const int bi = blk / kq, bj = blk % kq;
-    double s[4][4] = {};
-    for (int r = 0; r < nr; ++r) {
-      double ai[4], aj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = 4 * bi + u, j = 4 * bj + u;
-        ai[u] = i < K ? tile[r * K + i] : 0.0;
-        aj[u] = j < K ? tile[r * K + j] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) s[u][v] = fma(ai[u], aj[v], s[u][v]);
+  const int tj = ti + pidx;
+  const int64_t rpc = (rows + nchunk - 1) / nchunk;
+  const int64_t rb = (int64_t)blockIdx.y * rpc;
+  const int64_t re = rb + rpc < rows ? rb + rpc : rows;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t r0 = rb; r0 < re; r0 += kGR) {
+    for (int e = t; e < kGR * kGT; e += 256) {
+      const int r = e / kGT, c = e % kGT;
+      const int64_t row = r0 + r;
+      const int ci = ti * kGT + c, cj = tj * kGT + c;
+      Ai[r][c] = (row < re && ci < K) ? (double)A[row * lda + ci] : 0.0;
+      Aj[r][c] = (row < re && cj < K) ? (double)A[row * lda + cj] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * bi + u, j = 4 * bj + v;
-        if (i < K && j < K) out[i * K + j] = s[u][v];
-      }
+    __syncthreads();
+    const int nr = (int)(re - r0 < kGR ? re - r0 : kGR);
+    for (int r = 0; r < nr; ++r) {
+      const double a0 = Ai[r][2 * ty], a1 = Ai[r][2 * ty + 1];
+      const double b0 = Aj[r][2 * tx], b1 = Aj[r][2 * tx + 1];
+      acc[0][0] = fma(a0, b0, acc[0][0]);
+      acc[0][1] = fma(a0, b1, acc[0][1]);
+      acc[1][0] = fma(a1, b0, acc[1][0]);
+      acc[1][1] = fma(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
   }
+  double* out = parts + (int64_t)blockIdx.y * K * K;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int i = ti * kGT + 2 * ty + u, j = tj * kGT + 2 * tx + v;
+      if (i < K && j < K) out[i * K + j] = acc[u][v];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ parts, int nparts,
-                                                   int64_t count, double* __restrict__ out,
-                                                   int* status) {
+__global__ __launch_bounds__(256) void k_sum_gram(const double* __restrict__ parts, int nparts,
+                                                  int K, double* __restrict__ out, int* status) {
   bool bad = false;
+  const int64_t count = (int64_t)K * K;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += parts[(int64_t)p * count + e];
-    if (!isfinite(s)) bad = true;
-    out[e] = s;
+    const int i = (int)(e / K), j = (int)(e % K);
+    const int64_t src = (i / kGT <= j / kGT) ? e : (int64_t)j * K + i;   // lower tiles: mirror
+    double sacc = 0.0;
+    for (int p = 0; p < nparts; ++p) sacc += parts[(int64_t)p * count + src];
+    if (!isfinite(sacc)) bad = true;
+    out[e] = sacc;
   }
   if (bad) set_status(status, PPCA_ERR_NONFINITE);
 }
 
 // --------------------------------------------------------------------------
-// Upper Cholesky factor R (R^T R = A) and its inverse, K <= 128, one
-// workgroup of 1024 threads.  Thread (ty, tx) = (tid / 32, tid % 32) keeps the
-// 4 x 4 elements (ty + 32p, tx + 32q) of the working matrix in registers.
-// Right-looking factorisation, two barriers per column j:
-//   (a) the owner of (j, j) checks the pivot (finite, > K * eps * |a_jj|,
-//       > 0; else NOT_SPD) and publishes r_jj = sqrt(pivot);
-//   (b) the owners of row j scale it, u_c = m_jc / r_jj, and publish u;
-//   (c) every thread updates its trailing elements, m_ic -= u_i u_c.
-// Then R goes to LDS and X = R^-1 follows from R X = I by right-looking back
-// substitution (row i of X = row i of B / r_ii, then B_p -= r_pi X_i for
-// p < i), one barrier per row.
+// Upper Cholesky factor R (R^T R = A) and X = R^-1, K <= 128, one workgroup of
+// 1024 threads, blocked in 16 x 16 blocks (the matrix is padded with the
+// identity to a multiple of 16; the padding factors to the identity).
+//
+// Factorisation, for each block row J (three barriers per block row):
+//   (1) one wavefront factors the diagonal block with the unblocked
+//       right-looking recurrence (pivot test: finite, > K * eps * |a_jj|,
+//       > 0, else NOT_SPD);
+//   (2) one thread per column c > J solves R_JJ^T R_Jc = M_Jc (forward
+//       substitution) for the row panel;
+//   (3) all threads apply the rank-16 update M_ic -= R_Ji^T R_Jc to the
+//       trailing upper triangle.
+// Inverse: the diagonal blocks are inverted in place, one wavefront each;
+// then for each block row I from the bottom: T = R_I,>I X_>I (the rows of X
+// below are final), X_I,>I = -R_II^-1 T, two barriers per block row.  T is
+// kept in the unused strict lower triangle of the matrix.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A, int K,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv, int* status) {
-  constexpr int KM = kMaxK;          // 128
-  __shared__ double Rs[KM * KM];     // R (row-major) for the inverse
-  __shared__ double ub[KM];          // published row of the current step
-  __shared__ double xb[2][KM];       // published rows of X (double buffered)
-  __shared__ double dg[KM];          // diagonal of A
-  __shared__ double rd[KM];          // diagonal of R
+  constexpr int KM = kMaxK, LDM = KM + 1, BS = 16;   // row stride 129: column reads spread banks
+  __shared__ double M[KM * LDM];
+  __shared__ double dg[KM];
   __shared__ int fail;
-  const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (status_set(status)) return;
+  const int nbk = (K + BS - 1) / BS, Kp = nbk * BS;
   if (tid == 0) fail = 0;
-  double m[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ty + 32 * p, c = tx + 32 * q;
-      m[p][q] = (i < K && c < K) ? A[i * K + c] : 0.0;
-      if (i == c && i < K) dg[i] = m[p][q];
-    }
+  for (int e = tid; e < Kp * Kp; e += blockDim.x) {
+    const int i = e / Kp, c = e - i * Kp;
+    double v;
+    if (i < K && c < K) v = c >= i ? A[i * K + c] : 0.0;
+    else v = (i == c) ? 1.0 : 0.0;
+    M[i * LDM + c] = v;
+    if (i == c) dg[i] = v;
+  }
   __syncthreads();
-  for (int j = 0; j < K; ++j) {
-    const int pj = j >> 5, oj = j & 31;
-    // (a) pivot
-    if (ty == oj && tx == oj) {
-      double piv = 0.0;
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (p == pj && q == pj) piv = m[p][q];
-      if (!(isfinite(piv) && piv > (double)K * kEps * fabs(dg[j]) && piv > 0.0)) fail = 1;
-      else rd[j] = sqrt(piv);
+  for (int J = 0; J < nbk; ++J) {
+    const int j0 = J * BS;
+    // (1) diagonal block, lanes 0..15 of wave 0 own its columns
+    if (wave == 0) {
+      const int c = lane;
+      for (int p = 0; p < BS; ++p) {
+        const int jp = j0 + p;
+        const double piv = M[jp * LDM + jp];
+        const bool ok = isfinite(piv) && piv > (double)K * kEps * fabs(dg[jp]) && piv > 0.0;
+        if (!ok) {
+          if (lane == 0) fail = 1;
+          break;                                  // uniform: every lane read the same pivot
+        }
+        const double rpp = sqrt(piv);
+        if (c < BS && c > p) M[jp * LDM + j0 + c] = M[jp * LDM + j0 + c] / rpp;
+        if (c == p) M[jp * LDM + jp] = rpp;
+        if (c < BS && c > p) {
+          const double uc = M[jp * LDM + j0 + c];
+          for (int i = p + 1; i <= c; ++i)
+            M[(j0 + i) * LDM + j0 + c] -= M[jp * LDM + j0 + i] * uc;
+        }
+      }
     }
     __syncthreads();
     if (fail) {
       if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
       return;
     }
-    const double rjj = rd[j];
-    // (b) row j of R
-    if (ty == oj) {
+    const int n0 = j0 + BS, N = Kp - n0;
+    if (N <= 0) break;
+    // (2) row panel R_J,c for c >= n0: forward substitution with R_JJ^T
+    for (int c = n0 + tid; c < Kp; c += blockDim.x) {
+      double x[BS];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        if (p != pj) continue;
+      for (int p = 0; p < BS; ++p) {
+        double sacc = M[(j0 + p) * LDM + c];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = tx + 32 * q;
-          double v = 0.0;
-          if (c == j) v = rjj;
-          else if (c > j && c < K) v = m[p][q] / rjj;
-          m[p][q] = v;
-          if (c < K) ub[c] = v;
-        }
+        for (int q = 0; q < p; ++q) sacc -= M[(j0 + q) * LDM + j0 + p] * x[q];
+        x[p] = sacc / M[(j0 + p) * LDM + j0 + p];
+        M[(j0 + p) * LDM + c] = x[p];
       }
     }
     __syncthreads();
-    // (c) trailing update of the elements (i, c) with i, c > j
-    double ui[4], uc[4];
+    // (3) trailing update of the upper triangle
+    for (int e = tid; e < N * N; e += blockDim.x) {
+      const int i = e / N, c = e - i * N;
+      if (i > c) continue;
+      const int gi = n0 + i, gc = n0 + c;
+      double sacc = M[gi * LDM + gc];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int i = ty + 32 * p;
-      ui[p] = (i > j && i < K) ? ub[i] : 0.0;
+      for (int p = 0; p < BS; ++p) sacc -= M[(j0 + p) * LDM + gi] * M[(j0 + p) * LDM + gc];
+      M[gi * LDM + gc] = sacc;
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tx + 32 * q;
-      uc[q] = (c > j && c < K) ? ub[c] : 0.0;
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) m[p][q] = fma(-ui[p], uc[q], m[p][q]);
+    __syncthreads();
   }
-  // R out (upper part; rows below their diagonal hold zeros from step (b))
+  // R out (upper triangle; the strict lower part of M is scratch from here on)
+  for (int e = tid; e < K * K; e += blockDim.x) {
+    const int i = e / K, c = e - i * K;
+    R[e] = c >= i ? M[i * LDM + c] : 0.0;
+  }
+  __syncthreads();   // R is read out before the diagonal blocks are overwritten
+  // diagonal blocks -> their inverses, in place (wave J: lanes 0..15 own columns)
+  if (wave < nbk) {
+    const int j0 = wave * BS, c = lane;
+    if (c < BS) {
+      double x[BS];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+      for (int p = BS - 1; p >= 0; --p) {
+        double sacc = (p == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ty + 32 * p, c = tx + 32 * q;
-      if (i < K && c < K) {
-        const double v = c >= i ? m[p][q] : 0.0;
-        R[i * K + c] = v;
-        Rs[i * KM + c] = v;
+        for (int q = p + 1; q < BS; ++q) sacc -= M[(j0 + p) * LDM + j0 + q] * x[q];
+        x[p] = (p <= c) ? sacc / M[(j0 + p) * LDM + j0 + p] : 0.0;
       }
+      // every lane of the wave has read the block before any lane writes it
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int p = 0; p < BS; ++p)
+        if (p <= c) M[(j0 + p) * LDM + j0 + c] = x[p];
     }
-  // X = R^-1: B starts as the identity
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) m[p][q] = (ty + 32 * p == tx + 32 * q) ? 1.0 : 0.0;
+  }
   __syncthreads();
-  for (int i = K - 1; i >= 0; --i) {
-    const int pi = i >> 5, oi = i & 31, buf = i & 1;
-    if (ty == oi) {
-      const double rii = rd[i];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        if (p != pi) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = tx + 32 * q;
-          const double v = (c >= i && c < K) ? m[p][q] / rii : 0.0;
-          m[p][q] = v;
-          if (c < K) xb[buf][c] = v;
-        }
-      }
+  for (int I = nbk - 2; I >= 0; --I) {
+    const int i0 = I * BS, n0 = i0 + BS, N = Kp - n0;
+    // T[r][c] = sum_{k = n0 .. c} R[i0 + r][k] X[k][c], kept transposed at M[c][i0 + r]
+    for (int e = tid; e < BS * N; e += blockDim.x) {
+      const int r = e / N, c = n0 + (e - r * N);
+      double sacc = 0.0;
+      for (int k2 = n0; k2 <= c; ++k2) sacc += M[(i0 + r) * LDM + k2] * M[k2 * LDM + c];
+      M[c * LDM + i0 + r] = sacc;
     }
     __syncthreads();
-    double xc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tx + 32 * q;
-      xc[q] = (c >= i && c < K) ? xb[buf][c] : 0.0;
+    // X[i0 + r][c] = -sum_{q >= r} Xdiag[r][q] T[q][c]
+    for (int e = tid; e < BS * N; e += blockDim.x) {
+      const int r = e / N, c = n0 + (e - r * N);
+      double sacc = 0.0;
+      for (int q = r; q < BS; ++q) sacc += M[(i0 + r) * LDM + i0 + q] * M[c * LDM + i0 + q];
+      M[(i0 + r) * LDM + c] = -sacc;
     }
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int r = ty + 32 * p;
-      if (r < i) {
-        const double rpi = Rs[r * KM + i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) m[p][q] = fma(-rpi, xc[q], m[p][q]);
-      }
-    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ty + 32 * p, c = tx + 32 * q;
-      if (i < K && c < K) Rinv[i * K + c] = c >= i ? m[p][q] : 0.0;
-    }
+  for (int e = tid; e < K * K; e += blockDim.x) {
+    const int i = e / K, c = e - i * K;
+    Rinv[e] = c >= i ? M[i * LDM + c] : 0.0;
+  }
 }
 
 // --------------------------------------------------------------------------
-// out = A * Rinv for upper-triangular Rinv (K x K), 16 rows per block.
+// out = A * Rinv for upper-triangular Rinv (K x K): tiled product, block =
+// 64 rows x 32 columns of out, k-steps of 32 that stop at the tile's last
+// column (Rinv is zero below its diagonal).
 // --------------------------------------------------------------------------
-constexpr int kTrmmRows = 16;
+constexpr int kTR = 64, kTC = 32;
 
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_trmm(const TI* __restrict__ A, int64_t rows, int K,
                                               int64_t lda, const double* __restrict__ Rinv,
                                               TO* __restrict__ out, int64_t ldo, int* status) {
-  __shared__ double Rs[kMaxK * kMaxK];
-  __shared__ double As[kTrmmRows * kMaxK];
+  __shared__ double As[kTR][kTC + 1], Rs[kTC][kTC + 1];
   if (status_set(status)) return;
-  const int64_t r0 = (int64_t)blockIdx.x * kTrmmRows;
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) Rs[e] = Rinv[e];
-  for (int e = threadIdx.x; e < kTrmmRows * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    As[e] = (r0 + r < rows) ? (double)A[(r0 + r) * lda + c] : 0.0;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * kTR;
+  const int c0 = blockIdx.y * kTC;
+  const int kend = c0 + kTC < K ? c0 + kTC : K;
+  double acc[4][2] = {};
+  for (int p0 = 0; p0 < kend; p0 += kTC) {
+    for (int e = t; e < kTR * kTC; e += 256) {
+      const int r = e / kTC, c = e % kTC;
+      const int64_t row = r0 + r;
+      const int col = p0 + c;
+      As[r][c] = (row < rows && col < K) ? (double)A[row * lda + col] : 0.0;
+    }
+    for (int e = t; e < kTC * kTC; e += 256) {
+      const int r = e / kTC, c = e % kTC;
+      const int pr = p0 + r, pc = c0 + c;
+      Rs[r][c] = (pr < K && pc < K) ? Rinv[pr * K + pc] : 0.0;
+    }
+    __syncthreads();
+    for (int pp = 0; pp < kTC; ++pp) {
+      const double b0 = Rs[pp][2 * tx], b1 = Rs[pp][2 * tx + 1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double av = As[4 * ty + u][pp];
+        acc[u][0] = fma(av, b0, acc[u][0]);
+        acc[u][1] = fma(av, b1, acc[u][1]);
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kTrmmRows * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    if (r0 + r >= rows) continue;
-    double s = 0.0;
-    for (int p = 0; p <= c; ++p) s = fma(As[r * K + p], Rs[p * K + c], s);
-    out[(r0 + r) * ldo + c] = (TO)s;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t row = r0 + 4 * ty + u;
+    if (row >= rows) continue;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int col = c0 + 2 * tx + v;
+      if (col < K) out[row * ldo + col] = (TO)acc[u][v];
+    }
   }
 }
 
@@ -336,7 +371,7 @@ __device__ double block_sum(double v, double* red) {
 __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, int K,
                                                  double* __restrict__ Ws, double* __restrict__ evals,
                                                  int max_sweeps, int* status) {
-  __shared__ double A[kMaxK * kMaxK];
+  __shared__ double A[kMaxK * (kMaxK + 1)];   // row stride kpad + 1: column accesses spread banks
   __shared__ double Wl[kJacRows * kMaxK];
   __shared__ double cs[kMaxK / 2], sn[kMaxK / 2];
   __shared__ int pp[kMaxK / 2], qq[kMaxK / 2];
@@ -347,10 +382,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
   if (status_set(status)) return;
   const int kpad = K + (K & 1);     // index K is a dummy when K is odd
   const int npair = kpad / 2;
+  const int la = kpad + 1;          // LDS row stride of A
   const int row0 = blockIdx.x * kJacRows;
   for (int e = tid; e < kpad * kpad; e += blockDim.x) {
     const int i = e / kpad, j = e % kpad;
-    A[e] = (i < K && j < K) ? 0.5 * (H[i * K + j] + H[j * K + i]) : 0.0;
+    A[i * la + j] = (i < K && j < K) ? 0.5 * (H[i * K + j] + H[j * K + i]) : 0.0;
   }
   for (int e = tid; e < kJacRows * kpad; e += blockDim.x) {
     const int r = e / kpad, j = e % kpad;
@@ -358,14 +394,17 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
   }
   __syncthreads();
   double loc = 0.0;
-  for (int e = tid; e < kpad * kpad; e += blockDim.x) loc += A[e] * A[e];
+  for (int e = tid; e < kpad * kpad; e += blockDim.x) {
+    const int i = e / kpad, j = e % kpad;
+    loc += A[i * la + j] * A[i * la + j];
+  }
   const double fro = sqrt(block_sum(loc, red));
   bool converged = (K <= 1) || fro == 0.0;
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     loc = 0.0;
     for (int e = tid; e < kpad * kpad; e += blockDim.x) {
       const int i = e / kpad, j = e % kpad;
-      if (i != j) loc += A[e] * A[e];
+      if (i != j) loc += A[i * la + j] * A[i * la + j];
     }
     const double off = sqrt(block_sum(loc, red));
     if (off <= 1e-15 * fro) {
@@ -380,7 +419,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < K) {
-          const double apq = A[p * kpad + q], app = A[p * kpad + p], aqq = A[q * kpad + q];
+          const double apq = A[p * la + q], app = A[p * la + p], aqq = A[q * la + q];
           if (!(fabs(apq) <= 1e-300 || fabs(apq) < 0.1 * kEps * sqrt(fabs(app * aqq)))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
@@ -392,42 +431,44 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
         pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
       }
       __syncthreads();
-      // 2x2 blocks (bi <= bj), each updated by one thread and mirrored
-      for (int e = tid; e < npair * npair; e += blockDim.x) {
-        const int bi = e / npair, bj = e % npair;
-        if (bi > bj) continue;
-        const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
-        const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
-        if (si == 0.0 && sj == 0.0) continue;
-        const double a = A[pi * kpad + pj], b = A[pi * kpad + qj];
-        const double e0 = A[qi * kpad + pj], f = A[qi * kpad + qj];
-        const double a1 = ci * a - si * e0, b1 = ci * b - si * f;
-        const double e1 = si * a + ci * e0, f1 = si * b + ci * f;
-        double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
-        double e2 = cj * e1 - sj * f1, f2 = sj * e1 + cj * f1;
-        if (bi == bj) {
-          b2 = 0.0;
-          e2 = 0.0;
-          A[pi * kpad + pi] = a2;
-          A[qi * kpad + qi] = f2;
-          A[pi * kpad + qi] = 0.0;
-          A[qi * kpad + pi] = 0.0;
-        } else {
-          A[pi * kpad + pj] = a2; A[pj * kpad + pi] = a2;
-          A[pi * kpad + qj] = b2; A[qj * kpad + pi] = b2;
-          A[qi * kpad + pj] = e2; A[pj * kpad + qi] = e2;
-          A[qi * kpad + qj] = f2; A[qj * kpad + qi] = f2;
+      // 2x2 blocks (bi <= bj), each updated by one thread and mirrored;
+      // thread t takes bi = t/16 + 64m, bj = t%16 + 16m' (no division)
+      for (int bi = tid >> 4; bi < npair; bi += 64) {
+        for (int bj = tid & 15; bj < npair; bj += 16) {
+          if (bi > bj) continue;
+          const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
+          const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+          if (si == 0.0 && sj == 0.0) continue;
+          const double a = A[pi * la + pj], b = A[pi * la + qj];
+          const double e0 = A[qi * la + pj], f = A[qi * la + qj];
+          const double a1 = ci * a - si * e0, b1 = ci * b - si * f;
+          const double e1 = si * a + ci * e0, f1 = si * b + ci * f;
+          double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
+          double e2 = cj * e1 - sj * f1, f2 = sj * e1 + cj * f1;
+          if (bi == bj) {
+            A[pi * la + pi] = a2;
+            A[qi * la + qi] = f2;
+            A[pi * la + qi] = 0.0;
+            A[qi * la + pi] = 0.0;
+          } else {
+            A[pi * la + pj] = a2; A[pj * la + pi] = a2;
+            A[pi * la + qj] = b2; A[qj * la + pi] = b2;
+            A[qi * la + pj] = e2; A[pj * la + qi] = e2;
+            A[qi * la + qj] = f2; A[qj * la + qi] = f2;
+          }
         }
       }
-      for (int e = tid; e < kJacRows * npair; e += blockDim.x) {
-        const int lr = e / npair, i = e % npair;
-        const double s = sn[i];
-        if (s == 0.0) continue;
-        const double c = cs[i];
-        const int p = pp[i], q = qq[i];
-        const double wp = Wl[lr * kpad + p], wq = Wl[lr * kpad + q];
-        Wl[lr * kpad + p] = c * wp - s * wq;
-        Wl[lr * kpad + q] = s * wp + c * wq;
+      // W rows of this workgroup: thread t takes row t/64 and pair t%64
+      for (int lr = tid >> 6; lr < kJacRows; lr += 16) {
+        for (int i = tid & 63; i < npair; i += 64) {
+          const double s = sn[i];
+          if (s == 0.0) continue;
+          const double c = cs[i];
+          const int p = pp[i], q = qq[i];
+          const double wp = Wl[lr * kpad + p], wq = Wl[lr * kpad + q];
+          Wl[lr * kpad + p] = c * wp - s * wq;
+          Wl[lr * kpad + q] = s * wp + c * wq;
+        }
       }
       __syncthreads();
     }
@@ -438,7 +479,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
     loc = 0.0;
     for (int e = tid; e < kpad * kpad; e += blockDim.x) {
       const int i = e / kpad, j = e % kpad;
-      if (i != j) loc += A[e] * A[e];
+      if (i != j) loc += A[i * la + j] * A[i * la + j];
     }
     const double off = sqrt(block_sum(loc, red));
     if (off > 1e-15 * fro) {
@@ -448,10 +489,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
   }
   // stable descending ranks
   for (int i = tid; i < K; i += blockDim.x) {
-    const double ti = A[i * kpad + i];
+    const double ti = A[i * la + i];
     int rk = 0;
     for (int j = 0; j < K; ++j) {
-      const double tj = A[j * kpad + j];
+      const double tj = A[j * la + j];
       rk += (tj > ti) || (tj == ti && j < i);
     }
     rank_of[i] = rk;
@@ -543,19 +584,32 @@ hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t
   return hipGetLastError();
 }
 
-int gram_parts(int64_t rows) { return (int)cdiv(rows, kGramRows); }
+static int gram_tiles(int K) {
+  const int nt = (int)cdiv(K, kGT);
+  return nt * (nt + 1) / 2;
+}
+
+// row chunks of the Gram: about 512 blocks in all, at least 16 rows a chunk
+int gram_parts(int64_t rows, int K) {
+  int64_t nc = cdiv(512, gram_tiles(K));
+  const int64_t by_rows = cdiv(rows, 16);
+  if (nc > by_rows) nc = by_rows;
+  if (nc < 1) nc = 1;
+  return (int)nc;
+}
 
 hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t lda, double* parts,
                        double* out, int* status, hipStream_t s) {
-  const int np = gram_parts(rows);
+  const int np = gram_parts(rows, K);
+  const dim3 grid(gram_tiles(K), np);
   if (in_f64)
-    hipLaunchKernelGGL(k_gram_part<double>, dim3(np), dim3(256), 0, s, (const double*)A, rows, K,
-                       lda, parts);
+    hipLaunchKernelGGL(k_gram_tile<double>, grid, dim3(256), 0, s, (const double*)A, rows, K, lda,
+                       np, parts);
   else
-    hipLaunchKernelGGL(k_gram_part<float>, dim3(np), dim3(256), 0, s, (const float*)A, rows, K,
-                       lda, parts);
-  hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((int64_t)K * K)), dim3(256), 0, s, parts, np,
-                     (int64_t)K * K, out, status);
+    hipLaunchKernelGGL(k_gram_tile<float>, grid, dim3(256), 0, s, (const float*)A, rows, K, lda,
+                       np, parts);
+  hipLaunchKernelGGL(k_sum_gram, dim3(grid_for((int64_t)K * K)), dim3(256), 0, s, parts, np, K,
+                     out, status);
   return hipGetLastError();
 }
 
@@ -568,7 +622,7 @@ hipError_t launch_chol_inv(const double* A, int K, double* R, double* Rinv, int*
 hipError_t launch_trmm(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,
                        const double* Rinv, void* out, bool out_f64, int64_t ldo, int* status,
                        hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(rows, kTrmmRows));
+  const dim3 grid((unsigned)cdiv(rows, kTR), (unsigned)cdiv(K, kTC));
   if (in_f64 && out_f64)
     hipLaunchKernelGGL((k_trmm<double, double>), grid, dim3(256), 0, s, (const double*)A, rows, K,
                        lda, Rinv, (double*)out, ldo, status);

@@ -171,9 +171,7 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
     vdst[j] = (r * 4 + (c ^ sw64(r))) * 16;
   }
 
-  // Y accumulators: zeroed once here and cleared after each tile's epilogue
-  // (zeroing them at the top of every tile makes the register allocator
-  // rotate them through extra registers inside the k-loop)
+  // Y accumulators: zeroed once here and cleared at the end of each tile
   f32x4_t acc[MW][NB];
 #pragma unroll
   for (int mb = 0; mb < MW; ++mb)
@@ -320,15 +318,6 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
         }
       }
     }
-    // clear the accumulators for the next tile: AND with an all-zero word the
-    // compiler cannot see through (an exact +0 whatever the value was)
-#pragma unroll
-    for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          acc[mb][nb][e] = __uint_as_float(__float_as_uint(acc[mb][nb][e]) & ~keep);
     __syncthreads();
     if (WANT_Y) {
       // coalesced copy of the tile to the global staging buffer (same layout)
@@ -345,40 +334,46 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
     for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
       for (int q = 0; q < NBG; ++q) accg[mb][q] = gs(mb, q);
+    // B fragments of the wave's blocks nb = wave + 4q are read by address (a
+    // register array indexed by the wave number would live in scratch);
+    // blocks past NB read block 0 and their products are never stored
 #pragma unroll
     for (int r0 = 0; r0 < WGR; r0 += 4 * GS) {
       const int rg = r0 / YR + g;                                  // chunk row of this lane group
+      const uint8_t* yrow = ylds + (rg * Kp + a) * 16;
       if (DT == DT_F32) {
-        float4 yf[NB];
+        float4 ya[NB], yw[NBG];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          yf[nb] = *reinterpret_cast<const float4*>(ylds + (rg * Kp + nb * 16 + a) * 16);
+        for (int nb = 0; nb < NB; ++nb) ya[nb] = *reinterpret_cast<const float4*>(yrow + nb * 256);
+#pragma unroll
+        for (int q = 0; q < NBG; ++q) {
+          const int nb = wave + 4 * q;
+          yw[q] = *reinterpret_cast<const float4*>(yrow + (nb < NB ? nb : 0) * 256);
+        }
 #pragma unroll
         for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
           for (int q = 0; q < NBG; ++q) {
-            const int nb = wave + 4 * q;
-            if (nb < NB) {
-              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].x, yf[nb].x, accg[mb][q], 0, 0, 0);
-              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].y, yf[nb].y, accg[mb][q], 0, 0, 0);
-              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].z, yf[nb].z, accg[mb][q], 0, 0, 0);
-              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yf[mb].w, yf[nb].w, accg[mb][q], 0, 0, 0);
-            }
+            accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].x, yw[q].x, accg[mb][q], 0, 0, 0);
+            accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].y, yw[q].y, accg[mb][q], 0, 0, 0);
+            accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].z, yw[q].z, accg[mb][q], 0, 0, 0);
+            accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].w, yw[q].w, accg[mb][q], 0, 0, 0);
           }
       } else {
-        uint4 yf[NB];
+        uint4 ya[NB], yw[NBG];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          yf[nb] = *reinterpret_cast<const uint4*>(ylds + (rg * Kp + nb * 16 + a) * 16);
+        for (int nb = 0; nb < NB; ++nb) ya[nb] = *reinterpret_cast<const uint4*>(yrow + nb * 256);
+#pragma unroll
+        for (int q = 0; q < NBG; ++q) {
+          const int nb = wave + 4 * q;
+          yw[q] = *reinterpret_cast<const uint4*>(yrow + (nb < NB ? nb : 0) * 256);
+        }
 #pragma unroll
         for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
-          for (int q = 0; q < NBG; ++q) {
-            const int nb = wave + 4 * q;
-            if (nb < NB)
-              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(yf[mb]), as_bf16x8(yf[nb]),
-                                                                    accg[mb][q], 0, 0, 0);
-          }
+          for (int q = 0; q < NBG; ++q)
+            accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ya[mb]), as_bf16x8(yw[q]),
+                                                                  accg[mb][q], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -386,6 +381,14 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
 #pragma unroll
       for (int q = 0; q < NBG; ++q) gs(mb, q) = accg[mb][q];
     }
+    // clear the accumulators for the next tile with a zero the compiler cannot
+    // see through (a literal zero at the top of the tile makes the register
+    // allocator rotate the accumulators through extra registers in the k-loop)
+    const float zero = __uint_as_float(~keep);
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
     __syncthreads();   // the next tile's pipeline overwrites the Y tile
   }
   if (!WANT_G) return;
@@ -403,9 +406,359 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         float* p = gbase + (int64_t)(mb * 16 + 4 * g + u) * Kp + nb * 16 + a;
-        *p = accumulate ? *p + v[u] : v[u];
+        if (accumulate) *p += v[u];   // chunked passes only
+        else *p = v[u];
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Y = X V' and G = Y^T Y with LDS-DMA stages (bf16 and f32 data).
+//
+// Same work split as k_xv (persistent workgroups over tiles of WGR rows, full
+// d per tile), but the k-step covers 128 bytes of every row (64 bf16 / 32 f32
+// columns: whole cache lines) and its X and V' tiles go straight from global
+// memory to LDS with global_load_lds (no register staging), into three LDS
+// stages kept as separate arrays:
+//   step kk:  wait for this wave's DMA of step kk (step kk+1 stays in flight)
+//             -> barrier -> DMA of step kk+2 into the stage freed by step kk-1
+//             -> MFMAs on stage kk.
+// A DMA writes 64 lanes x 16 bytes to consecutive LDS slots, so the XOR
+// swizzle of a 128-byte row (chunk c at slot c ^ (row & 7), conflict-free
+// fragment reads) is produced by choosing which global chunk each lane loads.
+// Every wave issues the same number of DMAs per step (steps past the last one
+// and the V' blocks of a small K repeat valid loads), so a fixed vmcnt wait
+// always means "the stage I need has landed".
+// Rows past the pass load a valid row; their Y rows are zeroed in the
+// epilogue.  A last step that ends inside a 16-byte chunk has the chunk's
+// columns past d cleared in LDS by the lane that loaded it.
+// ---------------------------------------------------------------------------
+// s_waitcnt with vmcnt = N (expcnt and lgkmcnt left unconstrained)
+template <int N>
+__device__ __attribute__((always_inline)) inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+__device__ __attribute__((always_inline)) inline void wait_lgkm0() {
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+}
+// workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding DMA); the signal fences keep the compiler from
+// moving LDS accesses across it
+__device__ __attribute__((always_inline)) inline void raw_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// One global_load_lds_dwordx4: lane i's 16 bytes at g go to LDS byte
+// lds + 16 i; `lds` must be the same for the whole wavefront.  Written as
+// inline asm so that the compiler's wait insertion, which cannot tell the
+// three stages apart and would make every LDS read wait for every DMA in
+// flight, does not see it: the kernel places its own waits (wait_vmcnt before
+// each barrier).  The instruction has no register result; M0 carries the LDS
+// base and is set in the same block (nothing else in these kernels uses M0).
+__device__ __attribute__((always_inline)) inline void dma16(const void* g, void* lds) {
+  const uint32_t base = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void*)lds);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(g), "s"(base)
+               : "memory");
+}
+
+template <int NB, int DT, int MW, bool WANT_Y, bool WANT_G>
+__global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                                int64_t rstart, int64_t rows, const uint8_t* vop,
+                                                int64_t dp, uint8_t* yb, float* gpart,
+                                                int accumulate) {
+  static_assert(DT == DT_F32 || DT == DT_BF16, "bf16 or f32 data");
+  constexpr int Kp = NB * 16;
+  constexpr int NBG = (NB + 3) / 4;                    // G column blocks per wave
+  constexpr int EB = DT == DT_F32 ? 4 : 2;             // bytes per X / V' / Y element
+  constexpr int KS = 128 / EB;                         // columns per k-step
+  constexpr int WGR = 64 * MW;                         // rows per tile
+  constexpr int XSB = WGR * 128, VSB = Kp * 128;       // stage bytes of X and V'
+  constexpr int STB = XSB + VSB;
+  constexpr int XI = WGR / 32;                         // X DMAs per wave per step
+  constexpr int VBLK = Kp / 8;                         // 1 KB blocks of a V' stage
+  constexpr int VI = (VBLK + 3) / 4;                   // V' DMAs per wave per step
+  constexpr int DPS = XI + VI;                         // DMAs per wave per step
+  constexpr int YR = 16 / EB;                          // rows per Y chunk (8 / 4)
+  constexpr int YTB = WGR * Kp * EB;                   // Y tile bytes
+  constexpr int YHB = YTB / 2;                         // half tile (rows [0, WGR/2) in st0)
+  static_assert(YHB <= STB, "a Y half tile fits a stage");
+  static_assert(2 * DPS < 64, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) uint8_t st0[STB];
+  __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
+  __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
+
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int a = lane & 15, g = lane >> 4;
+  const int64_t ntile = (rows + WGR - 1) / WGR;
+  const int nk = (int)((d + KS - 1) / KS);
+  const int64_t klast = (int64_t)(nk - 1) * KS;
+  // a last k-step ending inside a 16-byte chunk needs its tail cleared
+  const int64_t dtail = d % (16 / EB);
+  const uint32_t keep = dp > 0 ? 0xFFFFFFFFu : 0u;     // all ones, opaque to the compiler
+
+  // DMA sources.  X block j of wave w covers tile rows 8 (w XI + j) .. +7; lane
+  // -> row 8 (w XI + j) + lane / 8, LDS slot lane % 8 holding chunk
+  // (lane % 8) ^ (row & 7).
+  const int p8 = lane & 7;
+  int xr[XI], xc[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = 8 * (w * XI + j) + (lane >> 3);
+    xr[j] = r;
+    xc[j] = (p8 ^ (r & 7)) * (16 / EB);                // first column of the chunk in the step
+  }
+  // data row of each X block row, advanced by (gridDim.x * WGR) mod n per
+  // tile (any valid row serves the rows past the pass: they are zeroed later)
+  const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
+  int64_t xrow[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) xrow[j] = (rstart + (int64_t)blockIdx.x * WGR + xr[j]) % n;
+  const uint8_t* vsrc[VI];
+  int vblk[VI];
+#pragma unroll
+  for (int j = 0; j < VI; ++j) {
+    const int blk = (w * VI + j) % VBLK;
+    const int r = 8 * blk + (lane >> 3);
+    vblk[j] = blk;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+  }
+
+  f32x4_t acc[MW][NB];
+#pragma unroll
+  for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  f32x4_t accg[NB][NBG];
+#pragma unroll
+  for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+    for (int q = 0; q < NBG; ++q) accg[mb][q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t tl = blockIdx.x; tl < ntile; tl += gridDim.x) {
+    const int64_t row0 = tl * WGR;
+    const uint8_t* xsrc[XI];
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      xsrc[j] = x + xrow[j] * ld * EB;
+      const int64_t nr = xrow[j] + tstep;
+      xrow[j] = nr >= n ? nr - n : nr;
+    }
+    auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* {
+      return b == 0 ? st0 : (b == 1 ? st1 : st2);
+    };
+    // DMA of step kk (clamped to the last step) into stage b
+    auto issue = [&](int kk, int b) __attribute__((always_inline)) {
+      uint8_t* sb = stage(b);
+      const int64_t k0 = kk < nk ? (int64_t)kk * KS : klast;
+#pragma unroll
+      for (int j = 0; j < XI; ++j) {
+        const int64_t col = k0 + xc[j];
+        dma16(xsrc[j] + (col < d ? col : 0) * EB, sb + (w * XI + j) * 1024);
+      }
+#pragma unroll
+      for (int j = 0; j < VI; ++j) dma16(vsrc[j] + k0 * EB, sb + XSB + vblk[j] * 1024);
+    };
+    // clear the columns past d of the chunks this lane loaded in the last step
+    auto fix_tail = [&](int b) __attribute__((always_inline)) {
+      uint8_t* sb = stage(b);
+#pragma unroll
+      for (int j = 0; j < XI; ++j) {
+        uint4* slot = reinterpret_cast<uint4*>(sb + (w * XI + j) * 1024 + lane * 16);
+        *slot = and4(*slot, chunk_mask<EB>(klast + xc[j], d));
+      }
+    };
+    auto compute = [&](int b) __attribute__((always_inline)) {
+      const uint8_t* xs = stage(b);
+      const uint8_t* vs = xs + XSB;
+      if (DT == DT_F32) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float4 af[MW], bf[NB];
+          const int c = 4 * q + g;
+#pragma unroll
+          for (int mb = 0; mb < MW; ++mb) {
+            const int r = w * MW * 16 + mb * 16 + a;
+            af[mb] = *reinterpret_cast<const float4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int r = nb * 16 + a;
+            bf[nb] = *reinterpret_cast<const float4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].x, bf[nb].x, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].y, bf[nb].y, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].z, bf[nb].z, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].w, bf[nb].w, acc[mb][nb], 0, 0, 0);
+            }
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          uint4 af[MW], bf[NB];
+          const int c = 4 * h + g;
+#pragma unroll
+          for (int mb = 0; mb < MW; ++mb) {
+            const int r = w * MW * 16 + mb * 16 + a;
+            af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int r = nb * 16 + a;
+            bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[mb]), as_bf16x8(bf[nb]),
+                                                                    acc[mb][nb], 0, 0, 0);
+        }
+      }
+    };
+
+    issue(0, 0);
+    issue(1, 1);
+    auto step = [&](int kk, auto B) __attribute__((always_inline)) {
+      constexpr int b = decltype(B)::value;
+      wait_vmcnt<DPS>();                     // this wave's DMA of step kk has landed
+      if (dtail != 0 && kk == nk - 1) {
+        fix_tail(b);
+        wait_lgkm0();                        // the cleared chunks are written before the barrier
+      }
+      raw_barrier();                         // ... and every wave's; stage (b+2)%3 is free
+      issue(kk + 2, (b + 2) % 3);
+      if (kk < nk) compute(b);
+    };
+    for (int k = 0; k < nk; k += 3) {
+      step(k, std::integral_constant<int, 0>{});
+      step(k + 1, std::integral_constant<int, 1>{});
+      step(k + 2, std::integral_constant<int, 2>{});
+    }
+    wait_vmcnt<0>();
+    raw_barrier();                           // every DMA landed, every stage read
+
+    // ---- Y tile -> LDS, layout [row/YR][Kp][YR]; rows [0, WGR/2) in st0, the
+    // rest in st1.  Rows past the pass are written as zeros.
+    const int64_t vrows = rows - row0;        // valid rows of this tile
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb) {
+      const int lr = w * MW * 16 + mb * 16 + 4 * g;
+      uint8_t* yh = lr < WGR / 2 ? st0 : st1;
+      const int hr = lr & (WGR / 2 - 1);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (lr + u < vrows) ? acc[mb][nb][u] : 0.f;
+        if (DT == DT_F32) {
+          *reinterpret_cast<float4*>(yh + ((hr >> 2) * Kp + nb * 16 + a) * 16) =
+              make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          uint2 wv;
+          wv.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+          wv.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+          *reinterpret_cast<uint2*>(yh + ((hr >> 3) * Kp + nb * 16 + a) * 16 + (hr & 7) * 2) = wv;
+        }
+      }
+    }
+    wait_lgkm0();
+    raw_barrier();
+    if (WANT_Y) {
+      // coalesced copy of the tile to the staging buffer (same blocked layout)
+      uint8_t* ydst = yb + row0 * Kp * EB;
+      constexpr int HCH = YHB / 16;
+      for (int sch = t; sch < 2 * HCH; sch += 256) {
+        const uint8_t* src = sch < HCH ? st0 + sch * 16 : st1 + (sch - HCH) * 16;
+        *reinterpret_cast<uint4*>(ydst + sch * 16) = *reinterpret_cast<const uint4*>(src);
+      }
+    }
+    if constexpr (WANT_G) {
+      // G += Y^T Y over the tile; wave w takes the column blocks nb = w + 4q.
+      // The B fragments of those blocks are read by address (a register
+      // array indexed by the wave number would live in scratch); blocks past
+      // NB read block 0 and their products are never stored.
+      constexpr int NCR = WGR / YR;                    // chunk rows of the tile
+#pragma unroll
+      for (int r0 = 0; r0 < NCR; r0 += 4) {
+        const int rg = r0 + g;
+        const uint8_t* yh = rg < NCR / 2 ? st0 : st1;
+        const int hr = rg & (NCR / 2 - 1);
+        const uint8_t* yrow = yh + (hr * Kp + a) * 16;
+        if (DT == DT_F32) {
+          float4 ya[NB], yw[NBG];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) ya[nb] = *reinterpret_cast<const float4*>(yrow + nb * 256);
+#pragma unroll
+          for (int q = 0; q < NBG; ++q) {
+            const int nb = w + 4 * q;
+            yw[q] = *reinterpret_cast<const float4*>(yrow + (nb < NB ? nb : 0) * 256);
+          }
+#pragma unroll
+          for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+            for (int q = 0; q < NBG; ++q) {
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].x, yw[q].x, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].y, yw[q].y, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].z, yw[q].z, accg[mb][q], 0, 0, 0);
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[mb].w, yw[q].w, accg[mb][q], 0, 0, 0);
+            }
+        } else {
+          uint4 ya[NB], yw[NBG];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) ya[nb] = *reinterpret_cast<const uint4*>(yrow + nb * 256);
+#pragma unroll
+          for (int q = 0; q < NBG; ++q) {
+            const int nb = w + 4 * q;
+            yw[q] = *reinterpret_cast<const uint4*>(yrow + (nb < NB ? nb : 0) * 256);
+          }
+#pragma unroll
+          for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+            for (int q = 0; q < NBG; ++q)
+              accg[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ya[mb]), as_bf16x8(yw[q]),
+                                                                    accg[mb][q], 0, 0, 0);
+        }
+      }
+    }
+    // clear the accumulators for the next tile with a zero the compiler cannot
+    // see through (a literal zero at the top of the tile makes the register
+    // allocator rotate the accumulators through extra registers in the k-loop)
+    const float zero = __uint_as_float(~keep);
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
+    wait_lgkm0();
+    raw_barrier();                           // the next tile's DMAs overwrite the Y tile
+  }
+
+  if constexpr (WANT_G) {
+    float* gbase = gpart + (int64_t)blockIdx.x * Kp * Kp;
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+      for (int q = 0; q < NBG; ++q) {
+        const int nb = w + 4 * q;
+        if (nb >= NB) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float* p = gbase + (int64_t)(mb * 16 + 4 * g + u) * Kp + nb * 16 + a;
+          if (accumulate) *p += accg[mb][q][u];   // chunked passes only
+          else *p = accg[mb][q][u];
+        }
+      }
+  }
 }
 
 // Block id -> (tile, split).  Block b runs on XCD b mod 8; XCD x takes the
@@ -779,14 +1132,20 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
                          p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
                          accumulate ? 1 : 0);
     };
+    // bf16 / f32 data: LDS-DMA kernel; fp8 data: register-staged kernel
     auto by_mw = [&](auto dtc, auto yc, auto gc) {
       constexpr int DT = decltype(dtc)::value;
       constexpr bool WY = decltype(yc)::value, WG = decltype(gc)::value;
-      if (mw == 1) {
-        go(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), WY, WG>);
-      } else {
-        if constexpr (NB > xv_wide_nb(DT)) go(k_xv<NB, DT, 2, xv_stages(DT, NB, 2), WY, WG>);
+      if constexpr (DT == DT_FP8) {
+        if (mw == 1) go(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), WY, WG>);
         else go(k_xv<NB, DT, 4, xv_stages(DT, NB, 4), WY, WG>);
+      } else {
+        if (mw == 1) {
+          go(k_xvd<NB, DT, 1, WY, WG>);
+        } else {
+          if constexpr (NB > xv_wide_nb(DT)) go(k_xvd<NB, DT, 2, WY, WG>);
+          else go(k_xvd<NB, DT, 4, WY, WG>);
+        }
       }
     };
     auto by_dt = [&](auto yc, auto gc) {

@@ -120,7 +120,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.d = d;
   p.K = K;
   p.Kp = (int)round_up(K, 16);
-  p.dp = round_up(d, 32);
+  p.dp = round_up(d, 64);   // whole 64-column k-steps of the streaming kernels
   Carve c;
   p.status = c.take(256);
   if (op == PPCA_OP_CENTER) {
@@ -165,7 +165,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.z = c.take((size_t)d * K * sizeof(float));
   p.g = c.take(kk);
   p.b = c.take(kk);
-  p.gparts = c.take((size_t)gram_parts(d) * K * K * sizeof(double));
+  p.gparts = c.take((size_t)gram_parts(d, K) * K * K * sizeof(double));
   p.a = c.take(kk);
   p.r = c.take(kk);
   p.rinv = c.take(kk);

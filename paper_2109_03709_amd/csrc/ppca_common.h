@@ -91,7 +91,7 @@ hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t
                                int32_t dtype, const float* col_scale, void* vop,
                                double* veff, hipStream_t s);
 // partial Grams of a (rows x K) matrix A (row stride lda); in_f64 selects the type
-int gram_parts(int64_t rows);
+int gram_parts(int64_t rows, int K);
 hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,
                        double* parts, double* out, int* status, hipStream_t s);
 hipError_t launch_chol_inv(const double* A, int K, double* R, double* Rinv, int* status,
