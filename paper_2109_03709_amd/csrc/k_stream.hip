@@ -1009,6 +1009,215 @@ __global__ __launch_bounds__(256, 1) void k_xty(const uint8_t* x, int64_t n, int
 }
 
 // ---------------------------------------------------------------------------
+// Z partials with LDS-DMA stages (all data types): same work split and MFMA
+// code as k_xty, but each k-step's X rows (whole 512-byte row segments for
+// bf16) and Y chunks go straight to LDS with global_load_lds into four LDS
+// stages, three of them in flight while the MFMAs consume the fourth:
+//   step kk: wait for this wave's DMA of step kk -> barrier -> DMA of step
+//            kk+3 into the stage freed by step kk-1 -> MFMAs on stage kk.
+// No masking is needed: columns past d only feed rows of Z that are never
+// read; rows past the pass exist only in the last split, where the Y rows
+// (written by the Y = X V' kernel) are zero.
+// ---------------------------------------------------------------------------
+template <int NB, int DT>
+__global__ __launch_bounds__(256, 1) void k_xtyd(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                                 int64_t rstart, int64_t rows, int64_t rps,
+                                                 const uint8_t* yb, float* part, int ntiles,
+                                                 int nsplit, int accumulate) {
+  constexpr int Kp = NB * 16;
+  constexpr int TC = 256;
+  constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
+  constexpr int YB = DT == DT_F32 ? 4 : 2;                        // bytes per Y element
+  constexpr int KS = DT == DT_F32 ? 16 : 32;                      // rows per k-step
+  constexpr int YR = 16 / YB;                                     // rows per Y chunk (8 or 4)
+  constexpr int XRB = TC * EB;                                    // bytes per X row of a tile
+  constexpr int XCPR = XRB / 16;                                  // chunks per X row
+  constexpr int XSTB = KS * XRB;                                  // X bytes per stage
+  constexpr int YSTB = KS * Kp * YB;                              // Y bytes per stage
+  constexpr int STB = XSTB + YSTB;
+  constexpr int RPB = 1024 / XRB;                                 // X rows per 1 KB DMA block
+  constexpr int LPR = 64 / RPB;                                   // lanes per X row
+  constexpr int XI = XSTB / 1024 / 4;                             // X DMAs per wave per step
+  constexpr int YBLK = YSTB / 1024;                               // 1 KB blocks of a Y stage
+  constexpr int YI = (YBLK + 3) / 4;                              // Y DMAs per wave per step
+  constexpr int DPS = XI + YI;
+  static_assert(XI * 4 * 1024 == XSTB && LPR == XCPR, "stage shape");
+  static_assert(3 * DPS < 64, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) uint8_t st0[STB];
+  __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
+  __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
+  __shared__ __attribute__((aligned(16))) uint8_t st3[STB];
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int a = lane & 15, g = lane >> 4;
+  int tile, split;
+  if (!xty_tile_split(ntiles, nsplit, tile, split)) return;
+  const int64_t rbeg = (int64_t)split * rps;
+  const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
+  const int64_t c0 = (int64_t)tile * TC;
+
+  // X swizzle (as in k_xty): chunk c of row r sits at slot c ^ xswz(r)
+  auto xswz = [](int r) -> int {
+    if (DT == DT_F32) return ((r >> 2) & 3) << 4;
+    if (DT == DT_BF16) return ((r >> 3) & 3) << 3;
+    return ((r >> 3) & 3) << 2;
+  };
+
+  // DMA sources.  X block j of wave w covers stage rows RPB (w XI + j) ..;
+  // lane -> row RPB (w XI + j) + lane / LPR, slot lane % LPR holding chunk
+  // slot ^ xswz(row).  Data rows advance by KS mod n per step.
+  const int64_t ksn = KS % n;
+  const uint8_t* xcp[XI];
+  int64_t xrow[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = RPB * (wave * XI + j) + lane / LPR;
+    const int c = (lane % LPR) ^ xswz(r);
+    const int64_t col = c0 + c * (16 / EB);
+    xcp[j] = x + (col < d ? col : 0) * EB;
+    xrow[j] = (rstart + rbeg + r) % n;
+  }
+  int yblk[YI];
+#pragma unroll
+  for (int j = 0; j < YI; ++j) yblk[j] = (wave * YI + j) % YBLK;
+
+  const int64_t nk = rend > rbeg ? (rend - rbeg + KS - 1) / KS : 0;
+  const int64_t llast = nk > 0 ? rbeg + (nk - 1) * KS : 0;
+
+  auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* {
+    return b == 0 ? st0 : (b == 1 ? st1 : (b == 2 ? st2 : st3));
+  };
+  // DMA of the step at pass row li into stage b (Y rows clamped to the last step)
+  auto issue = [&](int64_t li, int b) __attribute__((always_inline)) {
+    uint8_t* sb = stage(b);
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      dma16(xcp[j] + xrow[j] * ld * EB, sb + (wave * XI + j) * 1024);
+      const int64_t nr = xrow[j] + ksn;
+      xrow[j] = nr >= n ? nr - n : nr;
+    }
+    const uint8_t* ysrc = yb + ((li < llast ? li : llast) / YR) * Kp * 16;
+#pragma unroll
+    for (int j = 0; j < YI; ++j) dma16(ysrc + yblk[j] * 1024 + lane * 16, sb + XSTB + yblk[j] * 1024);
+  };
+
+  f32x4_t acc[4][NB];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int cw = wave * 64 + 4 * a;   // this lane's first column inside the tile
+
+  auto compute = [&](const uint8_t* xs) __attribute__((always_inline)) {
+    const uint8_t* ys = xs + XSTB;
+    if (DT == DT_F32) {
+      // k-index of lane group g, MFMA s: row 4g + s of the step
+      float4 bf[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bf[nb] = *reinterpret_cast<const float4*>(ys + (g * Kp + nb * 16 + a) * 16);
+      float4 in[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = 4 * g + s;
+        const int c = cw >> 2;   // chunk of 4 floats
+        in[s] = *reinterpret_cast<const float4*>(xs + (r * XCPR + (c ^ xswz(r))) * 16);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float bs[4] = {bf[nb].x, bf[nb].y, bf[nb].z, bf[nb].w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float as[4] = {in[s].x, in[s].y, in[s].z, in[s].w};
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[v], bs[s], acc[v][nb], 0, 0, 0);
+        }
+      }
+    } else {
+      // k-index of lane group g, element e: row 8g + e of the step
+      uint4 bf[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bf[nb] = *reinterpret_cast<const uint4*>(ys + (g * Kp + nb * 16 + a) * 16);
+      uint2 in[8];
+#pragma unroll
+      for (int r8 = 0; r8 < 8; ++r8) {
+        const int r = 8 * g + r8;
+        if (DT == DT_FP8) {
+          const int byte = cw;                       // 4 codes at column cw
+          const int c = byte >> 4;
+          const uint32_t w = *reinterpret_cast<const uint32_t*>(
+              xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
+          in[r8] = fp8x4_to_bf16x4(w);
+        } else {
+          const int byte = cw * 2;                   // 4 bf16 at column cw
+          const int c = byte >> 4;
+          in[r8] = *reinterpret_cast<const uint2*>(xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
+        }
+      }
+      // in-register transpose: af[v] = column cw + v over rows 8g .. 8g+7
+      uint4 af[4];
+      af[0] = make_uint4((in[0].x & 0xFFFFu) | (in[1].x << 16), (in[2].x & 0xFFFFu) | (in[3].x << 16),
+                         (in[4].x & 0xFFFFu) | (in[5].x << 16), (in[6].x & 0xFFFFu) | (in[7].x << 16));
+      af[1] = make_uint4((in[0].x >> 16) | (in[1].x & 0xFFFF0000u), (in[2].x >> 16) | (in[3].x & 0xFFFF0000u),
+                         (in[4].x >> 16) | (in[5].x & 0xFFFF0000u), (in[6].x >> 16) | (in[7].x & 0xFFFF0000u));
+      af[2] = make_uint4((in[0].y & 0xFFFFu) | (in[1].y << 16), (in[2].y & 0xFFFFu) | (in[3].y << 16),
+                         (in[4].y & 0xFFFFu) | (in[5].y << 16), (in[6].y & 0xFFFFu) | (in[7].y << 16));
+      af[3] = make_uint4((in[0].y >> 16) | (in[1].y & 0xFFFF0000u), (in[2].y >> 16) | (in[3].y & 0xFFFF0000u),
+                         (in[4].y >> 16) | (in[5].y & 0xFFFF0000u), (in[6].y >> 16) | (in[7].y & 0xFFFF0000u));
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[v]), as_bf16x8(bf[nb]),
+                                                               acc[v][nb], 0, 0, 0);
+    }
+  };
+
+  issue(rbeg, 0);
+  issue(rbeg + KS, 1);
+  issue(rbeg + 2 * KS, 2);
+  auto step = [&](int64_t kk, auto B) __attribute__((always_inline)) {
+    constexpr int b = decltype(B)::value;
+    wait_vmcnt<2 * DPS>();                   // this wave's DMA of step kk has landed
+    raw_barrier();                           // ... and every wave's; stage (b+3)%4 is free
+    issue(rbeg + (kk + 3) * KS, (b + 3) % 4);
+    if (kk < nk) compute(stage(b));
+  };
+  for (int64_t k = 0; k < nk; k += 4) {
+    step(k, std::integral_constant<int, 0>{});
+    step(k + 1, std::integral_constant<int, 1>{});
+    step(k + 2, std::integral_constant<int, 2>{});
+    step(k + 3, std::integral_constant<int, 3>{});
+  }
+  wait_vmcnt<0>();
+
+  if (c0 + wave * 64 < d) {
+    // lane (j = a, g): acc[v][nb][u] is tile column wave*64 + 16g + 4u + v,
+    // Y column nb*16 + a
+    float* pbase = part + ((int64_t)tile * nsplit + split) * Kp * TC;
+    const int64_t cl = wave * 64 + 16 * g;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float* dst = pbase + (int64_t)(nb * 16 + a) * TC + cl;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 v = make_float4(acc[0][nb][u], acc[1][nb][u], acc[2][nb][u], acc[3][nb][u]);
+        float4* p = reinterpret_cast<float4*>(dst + 4 * u);
+        if (accumulate) {
+          const float4 o = *p;
+          *p = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+        } else {
+          *p = v;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fixed-order float64 reduction of the partials.
 // Blocks [0, zblocks): Z[j][c] = s_j * sum_split part[j / 256][split][c][j mod 256]
 //   (j < d, c < K; consecutive threads take consecutive j of one column c).
@@ -1175,9 +1384,9 @@ hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_
                          rstart, rows, rps, (const uint8_t*)b.yb, b.part, ntiles, b.nsplit,
                          accumulate ? 1 : 0);
     };
-    if (p.dtype == PPCA_F32) go(k_xty<NB, DT_F32, xty_stages(DT_F32, NB)>);
-    else if (p.dtype == PPCA_BF16) go(k_xty<NB, DT_BF16, xty_stages(DT_BF16, NB)>);
-    else go(k_xty<NB, DT_FP8, xty_stages(DT_FP8, NB)>);
+    if (p.dtype == PPCA_F32) go(k_xtyd<NB, DT_F32>);
+    else if (p.dtype == PPCA_BF16) go(k_xtyd<NB, DT_BF16>);
+    else go(k_xtyd<NB, DT_FP8>);
     return hipGetLastError();
   });
 }
