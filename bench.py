@@ -143,9 +143,12 @@ def main():
     avg = [s[1] / max(s[0], 1) for s in P_stats]
     achieved_all = [alg_step[i] * a.steps / max(P_stats[i][1] * 1e-3, 1e-12) / 1e9 for i in range(2)]
     dom = int(np.argmax([s[1] for s in P_stats]))
+    traffic = measured_traffic(n, d, K, a.storage, iters)
     roofline = {"bound": "hbm", "achieved": round(achieved_all[dom], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved_all[dom] / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel": names[dom], "avg_ms": round(avg[dom], 4),
+                "traffic": traffic[dom] if traffic else None,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "kernel": names[dom], "avg_ms": round(avg[dom], 4),
                 "alg_bytes_per_launch": alg_step[dom] / launches_step[dom],
                 "launches": P_stats[dom][0],
                 "other_kernel": {"kernel": names[1 - dom], "avg_ms": round(avg[1 - dom], 4),
@@ -175,6 +178,32 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(X, k, l, iters, a.cpu_rows, v0, es)
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_kernels_bf16_2Mx2048_K128.txt")
+
+
+def measured_traffic(n, d, K, storage, iters):
+    """HBM bytes per launch of [k_xv, k_xty] from the committed counter
+    summary, or None when the workload differs or the kernels' source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.startswith("#"):
+                key, val = line.split("=", 1)
+                kv[key.strip()] = val.strip()
+        src = os.path.join(ROOT, "paper_2109_03709_amd", "csrc", "k_stream.hip")
+        if hashlib.sha1(open(src, "rb").read()).hexdigest() != kv["k_stream_sha1"]:
+            return None
+        if kv["workload"] != f"n={n} d={d} K={K} {storage}":
+            return None
+        f = lambda k: int(kv[k + ".fetch_bytes"]) + int(kv[k + ".write_bytes"])
+        xv = (iters * f("xv_power") + f("xv_project")) / (iters + 1)
+        return [int(xv), f("xty")]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _timed(torch, fn, reps=3):

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_gram_tile(const T* __restrict__ A, int6
   const int64_t re = rb + rpc < rows ? rb + rpc : rows;
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int64_t r0 = rb; r0 < re; r0 += kGR) {
-    for (int e = t; e < kGR * kGT; e += 256) {
+#pragma unroll
+    for (int e = t; e < kGR * kGT; e += 256) {   // fixed trip count: all loads issued first
       const int r = e / kGT, c = e % kGT;
       const int64_t row = r0 + r;
       const int ci = ti * kGT + c, cj = tj * kGT + c;
@@ -123,63 +124,98 @@ __global__ __launch_bounds__(256) void k_sum_gram(const double* __restrict__ par
 
 // --------------------------------------------------------------------------
 // Upper Cholesky factor R (R^T R = A) and X = R^-1, K <= 128, one workgroup of
-// 1024 threads, blocked in 16 x 16 blocks (the matrix is padded with the
+// 256 threads (one wavefront per SIMD: the register file holds the unrolled
+// block steps), blocked in 16 x 16 blocks (the matrix is padded with the
 // identity to a multiple of 16; the padding factors to the identity).
 //
 // Factorisation, for each block row J (three barriers per block row):
-//   (1) one wavefront factors the diagonal block with the unblocked
-//       right-looking recurrence (pivot test: finite, > K * eps * |a_jj|,
-//       > 0, else NOT_SPD);
+//   (1) wavefront 0 factors the diagonal block in registers (lane c holds
+//       column c; pivots and row entries are broadcast with readlane).  Pivot
+//       test: finite, > K * eps * |a_jj| and > 0, else NOT_SPD;
 //   (2) one thread per column c > J solves R_JJ^T R_Jc = M_Jc (forward
 //       substitution) for the row panel;
-//   (3) all threads apply the rank-16 update M_ic -= R_Ji^T R_Jc to the
-//       trailing upper triangle.
+//   (3) the rank-16 update M_ic -= R_Ji^T R_Jc of the trailing upper
+//       triangle, 4 x 4 elements per thread.
 // Inverse: the diagonal blocks are inverted in place, one wavefront each;
 // then for each block row I from the bottom: T = R_I,>I X_>I (the rows of X
-// below are final), X_I,>I = -R_II^-1 T, two barriers per block row.  T is
-// kept in the unused strict lower triangle of the matrix.
+// below are final; a thread owns one column and 4 rows of T), then
+// X_I,>I = -R_II^-1 T; two barriers per block row.  T is kept in the unused
+// strict lower triangle of the matrix.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A, int K,
+__device__ inline double bcast_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ A, int K,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv, int* status) {
   constexpr int KM = kMaxK, LDM = KM + 1, BS = 16;   // row stride 129: column reads spread banks
   __shared__ double M[KM * LDM];
   __shared__ double dg[KM];
+  __shared__ double rcp[KM];         // 1 / r_jj
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (status_set(status)) return;
   const int nbk = (K + BS - 1) / BS, Kp = nbk * BS;
   if (tid == 0) fail = 0;
-  for (int e = tid; e < Kp * Kp; e += blockDim.x) {
-    const int i = e / Kp, c = e - i * Kp;
-    double v;
-    if (i < K && c < K) v = c >= i ? A[i * K + c] : 0.0;
-    else v = (i == c) ? 1.0 : 0.0;
-    M[i * LDM + c] = v;
-    if (i == c) dg[i] = v;
+  // load A in batches of 16 elements per thread, all loads in flight before
+  // any is used (a plain loop waits for every load in turn)
+  for (int e0 = tid; e0 < Kp * Kp; e0 += 16 * 256) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u;
+      const int i = e / Kp, c = e - i * Kp;
+      v[u] = (e < Kp * Kp && i < K && c < K && c >= i) ? A[i * K + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u;
+      if (e >= Kp * Kp) continue;
+      const int i = e / Kp, c = e - i * Kp;
+      const double w = (i < K && c < K) ? v[u] : (i == c ? 1.0 : 0.0);
+      M[i * LDM + c] = w;
+      if (i == c) dg[i] = w;
+    }
   }
   __syncthreads();
   for (int J = 0; J < nbk; ++J) {
     const int j0 = J * BS;
-    // (1) diagonal block, lanes 0..15 of wave 0 own its columns
+    // (1) diagonal block in registers of wavefront 0 (lanes 16..63 idle)
     if (wave == 0) {
-      const int c = lane;
+      const int c = lane & (BS - 1);
+      double col[BS];
+#pragma unroll
+      for (int i = 0; i < BS; ++i) col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
+      bool ok = true;
+#pragma unroll
       for (int p = 0; p < BS; ++p) {
+        const double piv = bcast_lane(col[p], p);
         const int jp = j0 + p;
-        const double piv = M[jp * LDM + jp];
-        const bool ok = isfinite(piv) && piv > (double)K * kEps * fabs(dg[jp]) && piv > 0.0;
-        if (!ok) {
-          if (lane == 0) fail = 1;
-          break;                                  // uniform: every lane read the same pivot
+        // uniform: every lane holds the same pivot; after a failure the
+        // values are garbage and are not stored
+        ok = ok && isfinite(piv) && piv > (double)K * kEps * fabs(dg[jp]) && piv > 0.0;
+        // one reciprocal square root per pivot; the row is scaled by it
+        // (shorter dependency chain than a square root and a division)
+        const double rinv = rsqrt(fabs(piv));
+        const double rpp = fabs(piv) * rinv;
+        const double u = (c > p) ? col[p] * rinv : 0.0;   // R[p][c]
+        col[p] = (c == p) ? rpp : ((c > p) ? u : col[p]);
+        if (lane == 0) rcp[jp] = rinv;
+#pragma unroll
+        for (int i = p + 1; i < BS; ++i) {
+          const double ui = bcast_lane(u, i);
+          if (i <= c) col[i] = fma(-ui, u, col[i]);
         }
-        const double rpp = sqrt(piv);
-        if (c < BS && c > p) M[jp * LDM + j0 + c] = M[jp * LDM + j0 + c] / rpp;
-        if (c == p) M[jp * LDM + jp] = rpp;
-        if (c < BS && c > p) {
-          const double uc = M[jp * LDM + j0 + c];
-          for (int i = p + 1; i <= c; ++i)
-            M[(j0 + i) * LDM + j0 + c] -= M[jp * LDM + j0 + i] * uc;
-        }
+      }
+      if (!ok) {
+        if (lane == 0) fail = 1;
+      } else if (lane < BS) {
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+          if (i <= c) M[(j0 + i) * LDM + j0 + c] = col[i];
       }
     }
     __syncthreads();
@@ -196,21 +232,41 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A,
       for (int p = 0; p < BS; ++p) {
         double sacc = M[(j0 + p) * LDM + c];
 #pragma unroll
-        for (int q = 0; q < p; ++q) sacc -= M[(j0 + q) * LDM + j0 + p] * x[q];
-        x[p] = sacc / M[(j0 + p) * LDM + j0 + p];
+        for (int q = 0; q < p; ++q) sacc = fma(-M[(j0 + q) * LDM + j0 + p], x[q], sacc);
+        x[p] = sacc * rcp[j0 + p];
         M[(j0 + p) * LDM + c] = x[p];
       }
     }
     __syncthreads();
-    // (3) trailing update of the upper triangle
-    for (int e = tid; e < N * N; e += blockDim.x) {
-      const int i = e / N, c = e - i * N;
-      if (i > c) continue;
-      const int gi = n0 + i, gc = n0 + c;
-      double sacc = M[gi * LDM + gc];
+    // (3) trailing update of the upper triangle, 4 x 4 per thread
+    const int n4 = N / 4;
+    for (int blk = tid; blk < n4 * n4; blk += blockDim.x) {
+      const int bi = blk / n4, bj = blk - bi * n4;
+      if (bi > bj) continue;
+      const int gi = n0 + 4 * bi, gc = n0 + 4 * bj;
+      double acc[4][4];
 #pragma unroll
-      for (int p = 0; p < BS; ++p) sacc -= M[(j0 + p) * LDM + gi] * M[(j0 + p) * LDM + gc];
-      M[gi * LDM + gc] = sacc;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = M[(gi + u) * LDM + gc + v];
+#pragma unroll
+      for (int p = 0; p < BS; ++p) {
+        double ra[4], rb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ra[u] = M[(j0 + p) * LDM + gi + u];
+          rb[u] = M[(j0 + p) * LDM + gc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(-ra[u], rb[v], acc[u][v]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (gi + u <= gc + v) M[(gi + u) * LDM + gc + v] = acc[u][v];
     }
     __syncthreads();
   }
@@ -220,17 +276,18 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A,
     R[e] = c >= i ? M[i * LDM + c] : 0.0;
   }
   __syncthreads();   // R is read out before the diagonal blocks are overwritten
-  // diagonal blocks -> their inverses, in place (wave J: lanes 0..15 own columns)
-  if (wave < nbk) {
-    const int j0 = wave * BS, c = lane;
+  // diagonal blocks -> their inverses, in place (wave w takes blocks w, w + 4, ..;
+  // lanes 0..15 own columns)
+  for (int Jd = wave; Jd < nbk; Jd += 4) {
+    const int j0 = Jd * BS, c = lane;
     if (c < BS) {
       double x[BS];
 #pragma unroll
       for (int p = BS - 1; p >= 0; --p) {
         double sacc = (p == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = p + 1; q < BS; ++q) sacc -= M[(j0 + p) * LDM + j0 + q] * x[q];
-        x[p] = (p <= c) ? sacc / M[(j0 + p) * LDM + j0 + p] : 0.0;
+        for (int q = p + 1; q < BS; ++q) sacc = fma(-M[(j0 + p) * LDM + j0 + q], x[q], sacc);
+        x[p] = (p <= c) ? sacc * rcp[j0 + p] : 0.0;
       }
       // every lane of the wave has read the block before any lane writes it
       __builtin_amdgcn_wave_barrier();
@@ -242,19 +299,25 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ A,
   __syncthreads();
   for (int I = nbk - 2; I >= 0; --I) {
     const int i0 = I * BS, n0 = i0 + BS, N = Kp - n0;
-    // T[r][c] = sum_{k = n0 .. c} R[i0 + r][k] X[k][c], kept transposed at M[c][i0 + r]
-    for (int e = tid; e < BS * N; e += blockDim.x) {
-      const int r = e / N, c = n0 + (e - r * N);
-      double sacc = 0.0;
-      for (int k2 = n0; k2 <= c; ++k2) sacc += M[(i0 + r) * LDM + k2] * M[k2 * LDM + c];
-      M[c * LDM + i0 + r] = sacc;
+    // T[r][c] = sum_{k = n0 .. c} R[i0 + r][k] X[k][c], kept transposed at
+    // M[c][i0 + r]; thread (c, r4) owns rows 4 r4 .. 4 r4 + 3 of column c
+    for (int e = tid; e < 4 * N; e += blockDim.x) {
+      const int r4 = e / N, c = n0 + (e - r4 * N);
+      double t4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k2 = n0; k2 <= c; ++k2) {
+        const double xk = M[k2 * LDM + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t4[u] = fma(M[(i0 + 4 * r4 + u) * LDM + k2], xk, t4[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) M[c * LDM + i0 + 4 * r4 + u] = t4[u];
     }
     __syncthreads();
     // X[i0 + r][c] = -sum_{q >= r} Xdiag[r][q] T[q][c]
     for (int e = tid; e < BS * N; e += blockDim.x) {
       const int r = e / N, c = n0 + (e - r * N);
       double sacc = 0.0;
-      for (int q = r; q < BS; ++q) sacc += M[(i0 + r) * LDM + i0 + q] * M[c * LDM + i0 + q];
+      for (int q = r; q < BS; ++q) sacc = fma(M[(i0 + r) * LDM + i0 + q], M[c * LDM + i0 + q], sacc);
       M[(i0 + r) * LDM + c] = -sacc;
     }
     __syncthreads();
@@ -284,12 +347,14 @@ __global__ __launch_bounds__(256) void k_trmm(const TI* __restrict__ A, int64_t 
   const int kend = c0 + kTC < K ? c0 + kTC : K;
   double acc[4][2] = {};
   for (int p0 = 0; p0 < kend; p0 += kTC) {
-    for (int e = t; e < kTR * kTC; e += 256) {
+#pragma unroll
+    for (int e = t; e < kTR * kTC; e += 256) {   // fixed trip count: all loads issued first
       const int r = e / kTC, c = e % kTC;
       const int64_t row = r0 + r;
       const int col = p0 + c;
       As[r][c] = (row < rows && col < K) ? (double)A[row * lda + col] : 0.0;
     }
+#pragma unroll
     for (int e = t; e < kTC * kTC; e += 256) {
       const int r = e / kTC, c = e % kTC;
       const int pr = p0 + r, pc = c0 + c;
@@ -384,9 +449,20 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
   const int npair = kpad / 2;
   const int la = kpad + 1;          // LDS row stride of A
   const int row0 = blockIdx.x * kJacRows;
-  for (int e = tid; e < kpad * kpad; e += blockDim.x) {
-    const int i = e / kpad, j = e % kpad;
-    A[i * la + j] = (i < K && j < K) ? 0.5 * (H[i * K + j] + H[j * K + i]) : 0.0;
+  // H in batches of 8 elements per thread (all loads in flight before use)
+  for (int e0 = tid; e0 < kpad * kpad; e0 += 8 * 1024) {
+    double hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 1024 * u;
+      const int i = e / kpad, j = e % kpad;
+      hv[u] = (e < kpad * kpad && i < K && j < K) ? 0.5 * (H[i * K + j] + H[j * K + i]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 1024 * u;
+      if (e < kpad * kpad) A[(e / kpad) * la + (e % kpad)] = hv[u];
+    }
   }
   for (int e = tid; e < kJacRows * kpad; e += blockDim.x) {
     const int r = e / kpad, j = e % kpad;
@@ -615,7 +691,7 @@ hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t 
 
 hipError_t launch_chol_inv(const double* A, int K, double* R, double* Rinv, int* status,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, A, K, R, Rinv, status);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, A, K, R, Rinv, status);
   return hipGetLastError();
 }
 
