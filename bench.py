@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=500000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8"],
+                    default="power-bf16",
+                    help="power-bf16: the headline block-power workload (default); oja-f32 / "
+                         "eigengame-fp8: the minibatch primings at their configuration shapes")
     return ap.parse_args()
 
 
@@ -64,6 +68,8 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if a.workload != "power-bf16":
+        return main_minibatch(a)
     import torch
     import paper_2109_03709_amd as P
     from synthdata import gaussian_block, make_problem_device
@@ -330,6 +336,128 @@ def cpu_baseline(X, k, l, iters, rows, v0, es):
                       f"{iters} power iterations + projection + Rayleigh-Ritz in float64 numpy; "
                       f"GB/s counts {es}-byte stored elements, 2 reads per power iteration + 1, "
                       f"like the GPU value"}
+
+
+# Minibatch primings (Sec. 2.2, 2.3) at the shapes of their configurations:
+#   oja-f32        n = 1,000,000, d = 1024, float32, lambda_i = i^-1.2 + 1e-4,
+#                  k = l = 32, batch 1024, one epoch (977 steps),
+#                  eta_t = eta0 / (1 + t / 1000)
+#   eigengame-fp8  n = 8,000,000, d = 2048, fp8-e4m3 + column scales,
+#                  lambda_i = 0.97^i + 1e-5, k = l = 32, batch 4096, three
+#                  epochs (5860 steps), constant eta
+# One step = the whole priming + the projection pass + Rayleigh-Ritz.
+MINIBATCH = {
+    "oja-f32": dict(n=1_000_000, d=1024, spectrum="pow1.2+1e-4", storage="f32", k=32, l=32,
+                    batch=1024, epochs=1.0, eta0=0.5, t0=1000.0, seed=1002),
+    "eigengame-fp8": dict(n=8_000_000, d=2048, spectrum="exp0.97+1e-5", storage="fp8", k=32,
+                          l=32, batch=4096, epochs=3.0, eta0=0.2, t0=0.0, seed=1004),
+}
+
+
+def main_minibatch(a):
+    import torch
+    import paper_2109_03709_amd as P
+    from synthdata import gaussian_block, make_problem_device
+
+    c = MINIBATCH[a.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, d, k, l, b = c["n"], c["d"], c["k"], c["l"], c["batch"]
+    K = k + l
+    log(f"generating X: n={n} d={d} spectrum={c['spectrum']}")
+    xraw, lam, q = make_problem_device(n, d, c["spectrum"], c["seed"], device=dev)
+    code = {"bf16": P.BF16, "fp8": P.FP8_E4M3, "f32": P.F32}[c["storage"]]
+    es = {"bf16": 2, "fp8": 1, "f32": 4}[c["storage"]]
+    if code == P.F32:
+        X, _ = P.center_quantize(xraw, P.F32, out=xraw)
+    else:
+        X, _ = P.center_quantize(xraw, code)
+        del xraw
+    torch.cuda.synchronize()
+    steps = int(math.ceil(c["epochs"] * n / b))
+    prime = P.prime_oja if a.workload.startswith("oja") else P.prime_eigengame
+    v0 = torch.from_numpy(gaussian_block(d, K, c["seed"] + 1000, np.float32)).to(dev)
+    V = torch.empty_like(v0)
+    ws_p = torch.empty(P.workspace_bytes(P.OP_OJA if prime is P.prime_oja else P.OP_EIGENGAME,
+                                         X, K, b), dtype=torch.uint8, device=dev)
+    ws_prj = torch.empty(P.workspace_bytes(P.OP_PROJECT, X, K), dtype=torch.uint8, device=dev)
+    ws_rr = torch.empty(P.workspace_bytes(P.OP_RR, X, K), dtype=torch.uint8, device=dev)
+
+    def step():
+        V.copy_(v0)
+        prime(X, k, l, V, batch=b, steps=steps, eta0=c["eta0"], t0=c["t0"], ws=ws_p)
+        G, B = P.project_gram(X, K, V, ws=ws_prj)
+        return P.rayleigh_ritz(X, K, k, G, B, V, ws=ws_rr)
+
+    reps = max(1, min(a.steps, 3))
+    for _ in range(max(0, min(a.warmup, 1))):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev, E = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    # X bytes streamed: each minibatch step reads its b rows twice (Y = X_b V',
+    # Z = X_b^T Y); the projection reads X once
+    xbytes = (2 * steps * b + n) * d * es
+    evh = ev.cpu().numpy()
+    rel = float(np.max(np.abs(evh - lam[:k]) / lam[:k]))
+    Eh = E.cpu().numpy().astype(np.float64)
+    qe = np.linalg.qr(Eh)[0]
+    sin_t = float(np.linalg.norm(qe - q[:, :k] @ (q[:, :k].T @ qe), 2))
+    # priming alone: the pPCA step takes one projection pass
+    tp0 = time.perf_counter()
+    V.copy_(v0)
+    prime(X, k, l, V, batch=b, steps=steps, eta0=c["eta0"], t0=c["t0"], ws=ws_p)
+    torch.cuda.synchronize()
+    t_prime = time.perf_counter() - tp0
+    out = {"metric": METRIC, "value": round(xbytes / dt / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": reps, "warmup": max(0, min(a.warmup, 1)), "ms_per_step": round(dt * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": c["storage"], "data": "synthetic",
+           "config": {"workload": a.workload, "n": n, "d": d, "k": k, "l": l, "batch": b,
+                      "minibatch_steps": steps, "eta0": c["eta0"], "t0": c["t0"],
+                      "spectrum": c["spectrum"]},
+           "priming_ms": round(t_prime * 1e3, 3),
+           "us_per_minibatch_step": round(t_prime * 1e6 / steps, 2),
+           "accuracy": {"max_rel_eig_err": rel, "sin_theta_max": sin_t}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_minibatch(X, k, l, c, v0, es, prime is P.prime_oja)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_minibatch(X, k, l, c, v0, es, oja):
+    """The float64 oracle's minibatch priming on the same stored rows, timed
+    over a bounded number of steps (about 10 s of host work)."""
+    import torch
+    from oracle import ppca_oracle as O
+    b = c["batch"]
+    tsteps = 200 if oja else 40
+    rows = min(X.n, tsteps * b)
+    if X.dtype == 1:
+        xs = O.bf16_value(X.x[:rows].contiguous().view(torch.int16).cpu().numpy().view(np.uint16))
+    elif X.dtype == 2:
+        xs = O.e4m3_value(X.x[:rows].contiguous().cpu().numpy()) * \
+            X.col_scale.cpu().numpy().astype(np.float64)[None, :]
+    else:
+        xs = X.x[:rows].cpu().numpy().astype(np.float64)
+    vh = v0.cpu().numpy().astype(np.float64)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() \
+            else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    fn = O.prime_oja if oja else O.prime_eigengame
+    t0 = time.perf_counter()
+    fn(xs, vh, batch=b, steps=tsteps, eta0=c["eta0"], t0=c["t0"])
+    dt = time.perf_counter() - t0
+    return {"value": round(2 * tsteps * b * X.d * es / dt / 1e9, 4), "unit": "GB/s",
+            "cores": cores, "kind": "oracle", "seconds": round(dt, 2),
+            "us_per_minibatch_step": round(dt * 1e6 / tsteps, 1),
+            "sample": f"{tsteps} minibatch steps of {b} rows (the first {rows} stored rows), "
+                      f"float64 numpy; GB/s counts 2 reads of the minibatch per step"}
 
 
 if __name__ == "__main__":

@@ -1,34 +1,31 @@
 // Streaming kernels of one pass over X (block power step, minibatch step and
 // pPCA projection, Alg. 1 steps 2-3 and Sec. 2.1):
 //
-//   k_xv      : Y = X V' and the partial Grams G_w = Y^T Y of workgroup w
-//               (persistent over row tiles of 64/128/256 rows, full d per tile)
-//   k_xty     : Z = X^T Y over (256-column tile, row split) pairs
+//   k_xvd     : Y = X V' and the partial Grams G_w = Y^T Y of workgroup w
+//               (bf16 / f32 data; persistent over row tiles, full d per tile,
+//               LDS-DMA stages)
+//   k_xv      : the same for fp8 data (register-staged pipeline; fp8 codes
+//               are widened to bf16 exactly when read from LDS)
+//   k_xtyd    : Z = X^T Y over (256-column tile, row split) pairs (LDS-DMA)
 //   reduce_zg : fixed-order float64 sum of the partials -> Z (f32), G (f64)
 //
-// The projection pass only needs G, so it runs k_xv alone (one read of X, no
-// Y written).  bf16 and fp8 data run on v_mfma_f32_16x16x32_bf16 (fp8 codes
-// are widened to bf16 exactly when read from LDS); float32 data runs on
-// v_mfma_f32_16x16x4_f32.  Accumulation inside a workgroup is float32;
-// partials are summed in float64 in a fixed order, so results are bitwise
-// reproducible run to run.
-//
-// Pipeline (both kernels): each k-step's tiles of X and of the second operand
-// are loaded into registers several steps ahead, written to one of two LDS
-// buffers one step ahead, and consumed from LDS by the MFMA loop; one barrier
-// per k-step.  LDS rows are XOR-swizzled at 16-byte granularity so that the
-// fragment reads of a wavefront hit distinct banks.
+// The projection pass only needs G, so it runs the Y = X V' kernel alone
+// (one read of X, no Y written).  bf16 and fp8 data run on
+// v_mfma_f32_16x16x32_bf16, float32 data on v_mfma_f32_16x16x4_f32.
+// Accumulation inside a workgroup is float32; partials are summed in float64
+// in a fixed order, so results are bitwise reproducible run to run.
 //
 // Layouts
 //   X     row-major [n][ld] (element type per dtype); pass row i is data row
 //         (r0 + i) mod n.
-//   V'^T  operand [Kp][dp] (bf16 or f32), zero padded in both directions.
+//   V'^T  operand [Kp][dp] (bf16 or f32), zero padded in both directions
+//         (dp a multiple of 64).
 //   Y     "blocked" staging buffer so that the X^T Y kernel reads 8 (bf16) or
 //         4 (f32) consecutive rows of one Y column as one 16-byte chunk:
 //         bf16: yb[row/8][Kp][8], f32: yb[row/4][Kp][4].
 //   part  [tile][split][Kp][256] float32: column c of tile t is column
 //         t*256 + c of X.
-//   gpart [workgroup of k_xv][Kp][Kp] float32.
+//   gpart [workgroup of the Y = X V' kernel][Kp][Kp] float32.
 #include "ppca_common.h"
 
 namespace ppca {
@@ -779,240 +776,11 @@ __device__ inline bool xty_tile_split(int ntiles, int nsplit, int& tile, int& sp
 // ---------------------------------------------------------------------------
 // Z partials, Z = X^T Y.  Workgroup (tile t, split s): the 256 columns
 // [256t, 256t+256) of X (64 per wave) against all Kp columns of Y over the
-// rows of split s, i.e. rows [s*rps, min(rows, (s+1)*rps)).  k-step = 32 rows
-// (16 for f32).  Same register-staged pipeline as k_xv.
-// Output: part[t][s][Kp][256] float32.
-// ---------------------------------------------------------------------------
-template <int NB, int DT, int PSY>
-__global__ __launch_bounds__(256, 1) void k_xty(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
-                                                int64_t rstart, int64_t rows, int64_t rps,
-                                                const uint8_t* yb, float* part, int ntiles,
-                                                int nsplit, int accumulate) {
-  constexpr int Kp = NB * 16;
-  constexpr int TC = 256;
-  constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
-  constexpr int YB = DT == DT_F32 ? 4 : 2;                        // bytes per Y element
-  constexpr int KS = DT == DT_F32 ? 16 : 32;                      // rows per k-step
-  constexpr int YR = 16 / YB;                                     // rows per Y chunk (8 or 4)
-  constexpr int XRB = TC * EB;                                    // bytes per X row of a tile
-  constexpr int XCPR = XRB / 16;                                  // chunks per X row
-  constexpr int XSTB = KS * XRB;                                  // X bytes per stage
-  constexpr int XCH = XSTB / 16 / 256;                            // X chunks per thread
-  static_assert(XCH * 256 * 16 == XSTB, "whole X chunks per thread");
-  constexpr int YSTB = KS * Kp * YB;                              // Y bytes per stage (NB KB)
-  constexpr int YCHT = YSTB / 16;                                 // Y chunks per stage
-  constexpr int YCH = (YCHT + 255) / 256;                         // Y chunks per thread
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (XSTB + YSTB)];
-
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int a = lane & 15, g = lane >> 4;
-  int tile, split;
-  if (!xty_tile_split(ntiles, nsplit, tile, split)) return;
-  const int64_t rbeg = (int64_t)split * rps;
-  const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
-  const int64_t c0 = (int64_t)tile * TC;
-
-  // X swizzle: XOR the 16-byte chunk index with a function of the row so that
-  // the 4 lane groups of a fragment read (rows 8 apart; 4 apart for f32) fall
-  // on different banks.  The XOR stays inside the row.
-  auto xswz = [](int r) -> int {
-    if (DT == DT_F32) return ((r >> 2) & 3) << 4;
-    if (DT == DT_BF16) return ((r >> 3) & 3) << 3;
-    return ((r >> 3) & 3) << 2;
-  };
-
-  // ---- loader setup.  A thread keeps the same column chunk for the whole
-  // split (column mask and clamped column are loop invariant) and follows its
-  // data row incrementally (row += KS mod n, with ksn = KS mod n), so the loop
-  // has no division.  Loads are unconditional; rows past the split end and
-  // columns past d are masked to zero at the LDS write.
-  const int64_t ksn = KS % n;
-  int xr_row[XCH], xdst[XCH];
-  const uint8_t* xcp[XCH];     // column base of the chunk
-  int64_t xrow[XCH];           // current data row of the chunk
-  uint4 xmask[XCH];
-#pragma unroll
-  for (int j = 0; j < XCH; ++j) {
-    const int s = t + 256 * j, r = s / XCPR, c = s % XCPR;
-    xr_row[j] = r;
-    const int64_t col = c0 + c * (16 / EB);
-    xcp[j] = x + (col < d ? col : 0) * EB;
-    xmask[j] = chunk_mask<EB>(col, d);
-    xdst[j] = (r * XCPR + (c ^ xswz(r))) * 16;
-    xrow[j] = (rstart + rbeg + r) % n;
-  }
-  // Y chunks (layout [row/YR][Kp][YR] inside a stage); threads past the last
-  // chunk repeat an earlier one.  Rows of a chunk: (s / Kp) * YR + 0..YR-1.
-  int ydst[YCH], yrow[YCH];
-#pragma unroll
-  for (int j = 0; j < YCH; ++j) {
-    const int s = (t + 256 * j) % YCHT;
-    ydst[j] = s * 16;
-    yrow[j] = (s / Kp) * YR;
-  }
-
-  // an empty split (possible for the last splits of a short pass) runs no
-  // step but still writes its zero partial; its clamped Y loads read row 0
-  const int64_t nk = rend > rbeg ? (rend - rbeg + KS - 1) / KS : 0;
-  const int64_t llast = nk > 0 ? rbeg + (nk - 1) * KS : 0;
-
-  uint4 xr[PSY][XCH], yr[PSY][YCH];
-  // loads of the step at pass row li: X rows follow xrow[] (advanced here),
-  // Y rows are clamped to the last step of the split
-  auto gload = [&](int64_t li, uint4 (&xo)[XCH], uint4 (&yo)[YCH]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int j = 0; j < XCH; ++j) {
-      xo[j] = *reinterpret_cast<const uint4*>(xcp[j] + xrow[j] * ld * EB);
-      const int64_t nr = xrow[j] + ksn;
-      xrow[j] = nr >= n ? nr - n : nr;
-    }
-    const uint8_t* ysrc = yb + ((li < llast ? li : llast) / YR) * Kp * 16;
-#pragma unroll
-    for (int j = 0; j < YCH; ++j) yo[j] = *reinterpret_cast<const uint4*>(ysrc + ydst[j]);
-  };
-  auto lwrite = [&](int buf, int64_t li, const uint4 (&xi)[XCH], const uint4 (&yi)[YCH]) __attribute__((always_inline)) {
-    uint8_t* xs = lds + buf * (XSTB + YSTB);
-    uint8_t* ys = xs + XSTB;
-#pragma unroll
-    for (int j = 0; j < XCH; ++j) {
-      const uint32_t rm = (li + xr_row[j] < rend) ? 0xFFFFFFFFu : 0u;
-      const uint4 m = make_uint4(xmask[j].x & rm, xmask[j].y & rm, xmask[j].z & rm, xmask[j].w & rm);
-      *reinterpret_cast<uint4*>(xs + xdst[j]) = and4(xi[j], m);
-    }
-    // rows past the split end are zeroed; the AND also keeps the compiler
-    // from fusing the Y load with this store into a memcpy placed here
-#pragma unroll
-    for (int j = 0; j < YCH; ++j) {
-      const uint32_t rm = (li + yrow[j] < rend) ? 0xFFFFFFFFu : 0u;
-      *reinterpret_cast<uint4*>(ys + ydst[j]) = and4(yi[j], make_uint4(rm, rm, rm, rm));
-    }
-  };
-
-  f32x4_t acc[4][NB];
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-  const int cw = wave * 64 + 4 * a;   // this lane's first column inside the tile
-
-  auto compute = [&](int buf) __attribute__((always_inline)) {
-    const uint8_t* xs = lds + buf * (XSTB + YSTB);
-    const uint8_t* ys = xs + XSTB;
-    if (DT == DT_F32) {
-      // k-index of lane group g, MFMA s: row 4g + s of the step
-      float4 bf[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const float4*>(ys + (g * Kp + nb * 16 + a) * 16);
-      float4 in[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = 4 * g + s;
-        const int c = cw >> 2;   // chunk of 4 floats
-        in[s] = *reinterpret_cast<const float4*>(xs + (r * XCPR + (c ^ xswz(r))) * 16);
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const float bs[4] = {bf[nb].x, bf[nb].y, bf[nb].z, bf[nb].w};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const float as[4] = {in[s].x, in[s].y, in[s].z, in[s].w};
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[v], bs[s], acc[v][nb], 0, 0, 0);
-        }
-      }
-    } else {
-      // k-index of lane group g, element e: row 8g + e of the step
-      uint4 bf[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bf[nb] = *reinterpret_cast<const uint4*>(ys + (g * Kp + nb * 16 + a) * 16);
-      uint2 in[8];
-#pragma unroll
-      for (int r8 = 0; r8 < 8; ++r8) {
-        const int r = 8 * g + r8;
-        if (DT == DT_FP8) {
-          const int byte = cw;                       // 4 codes at column cw
-          const int c = byte >> 4;
-          const uint32_t w = *reinterpret_cast<const uint32_t*>(
-              xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
-          in[r8] = fp8x4_to_bf16x4(w);
-        } else {
-          const int byte = cw * 2;                   // 4 bf16 at column cw
-          const int c = byte >> 4;
-          in[r8] = *reinterpret_cast<const uint2*>(xs + (r * XCPR + (c ^ xswz(r))) * 16 + (byte & 15));
-        }
-      }
-      // in-register transpose: af[v] = column cw + v over rows 8g .. 8g+7
-      uint4 af[4];
-      af[0] = make_uint4((in[0].x & 0xFFFFu) | (in[1].x << 16), (in[2].x & 0xFFFFu) | (in[3].x << 16),
-                         (in[4].x & 0xFFFFu) | (in[5].x << 16), (in[6].x & 0xFFFFu) | (in[7].x << 16));
-      af[1] = make_uint4((in[0].x >> 16) | (in[1].x & 0xFFFF0000u), (in[2].x >> 16) | (in[3].x & 0xFFFF0000u),
-                         (in[4].x >> 16) | (in[5].x & 0xFFFF0000u), (in[6].x >> 16) | (in[7].x & 0xFFFF0000u));
-      af[2] = make_uint4((in[0].y & 0xFFFFu) | (in[1].y << 16), (in[2].y & 0xFFFFu) | (in[3].y << 16),
-                         (in[4].y & 0xFFFFu) | (in[5].y << 16), (in[6].y & 0xFFFFu) | (in[7].y << 16));
-      af[3] = make_uint4((in[0].y >> 16) | (in[1].y & 0xFFFF0000u), (in[2].y >> 16) | (in[3].y & 0xFFFF0000u),
-                         (in[4].y >> 16) | (in[5].y & 0xFFFF0000u), (in[6].y >> 16) | (in[7].y & 0xFFFF0000u));
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[v]), as_bf16x8(bf[nb]),
-                                                               acc[v][nb], 0, 0, 0);
-    }
-  };
-
-  // Straight-line pipeline loop (see k_xv); steps past the split end write
-  // all-zero stages, so their MFMAs add exactly zero.
-#pragma unroll
-  for (int i = 0; i < PSY - 1; ++i) gload(rbeg + (int64_t)i * KS, xr[i], yr[i]);
-  lwrite(0, rbeg, xr[0], yr[0]);
-  __syncthreads();
-  for (int64_t k = 0; k < nk; k += PSY) {
-    unroll_seq(std::make_integer_sequence<int, PSY>{}, [&](auto I) __attribute__((always_inline)) {
-      constexpr int i = decltype(I)::value;
-      const int64_t kk = k + i;
-      gload(rbeg + (kk + PSY - 1) * KS, xr[(i + PSY - 1) % PSY], yr[(i + PSY - 1) % PSY]);
-      __builtin_amdgcn_sched_barrier(0);
-      // LDS buffer = parity of the step (a constant when PSY is even)
-      const int par = PSY % 2 == 0 ? (i & 1) : (int)(kk & 1);
-      compute(par);
-      __builtin_amdgcn_sched_barrier(0);
-      lwrite(par ^ 1, rbeg + (kk + 1) * KS, xr[(i + 1) % PSY], yr[(i + 1) % PSY]);
-      __syncthreads();
-    });
-  }
-
-  if (c0 + wave * 64 < d) {
-    // lane (j = a, g): acc[v][nb][u] is tile column wave*64 + 16g + 4u + v,
-    // Y column nb*16 + a
-    float* pbase = part + ((int64_t)tile * nsplit + split) * Kp * TC;
-    const int64_t cl = wave * 64 + 16 * g;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      float* dst = pbase + (int64_t)(nb * 16 + a) * TC + cl;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float4 v = make_float4(acc[0][nb][u], acc[1][nb][u], acc[2][nb][u], acc[3][nb][u]);
-        float4* p = reinterpret_cast<float4*>(dst + 4 * u);
-        if (accumulate) {
-          const float4 o = *p;
-          *p = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
-        } else {
-          *p = v;
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Z partials with LDS-DMA stages (all data types): same work split and MFMA
-// code as k_xty, but each k-step's X rows (whole 512-byte row segments for
-// bf16) and Y chunks go straight to LDS with global_load_lds into four LDS
-// stages, three of them in flight while the MFMAs consume the fourth:
+// rows of split s, i.e. rows [s*rps, min(rows, (s+1)*rps)); k-step = 32 rows
+// (16 for f32).  Output: part[t][s][Kp][256] float32.
+// Each k-step's X rows (whole 512-byte row segments for bf16) and Y chunks go
+// straight to LDS with global_load_lds into four LDS stages, three of them in
+// flight while the MFMAs consume the fourth:
 //   step kk: wait for this wave's DMA of step kk -> barrier -> DMA of step
 //            kk+3 into the stage freed by step kk-1 -> MFMAs on stage kk.
 // No masking is needed: columns past d only feed rows of Z that are never
@@ -1056,7 +824,9 @@ __global__ __launch_bounds__(256, 1) void k_xtyd(const uint8_t* x, int64_t n, in
   const int64_t rend = rbeg + rps < rows ? rbeg + rps : rows;
   const int64_t c0 = (int64_t)tile * TC;
 
-  // X swizzle (as in k_xty): chunk c of row r sits at slot c ^ xswz(r)
+  // X swizzle: chunk c of row r sits at slot c ^ xswz(r), so that the 4 lane
+  // groups of a fragment read (rows 8 apart; 4 apart for f32) fall on
+  // different banks
   auto xswz = [](int r) -> int {
     if (DT == DT_F32) return ((r >> 2) & 3) << 4;
     if (DT == DT_BF16) return ((r >> 3) & 3) << 3;
@@ -1317,11 +1087,10 @@ static int xv_mw(int32_t dtype, int Kp, int64_t rows_cap) {
   return Kp / 16 > xv_wide_nb(dtype) ? 2 : 4;
 }
 
-// Register stages of the pipelines: bytes of X in flight per CU grow with
-// them, the register file bounds them (6 and 5 leave every instance spill
-// free with at least two stages in flight at each wait).
+// Register stages of the fp8 Y = X V' pipeline: bytes of X in flight per CU
+// grow with them, the register file bounds them (6 leaves every instance
+// spill free with at least two stages in flight at each wait).
 constexpr int xv_stages(int dt, int nb, int mw) { return 6; }
-constexpr int xty_stages(int dt, int nb) { return 5; }
 
 int xv_grid(int32_t dtype, int Kp, int64_t rows_cap) {
   const int64_t tiles = cdiv(rows_cap, 64 * xv_mw(dtype, Kp, rows_cap));
