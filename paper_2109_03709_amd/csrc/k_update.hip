@@ -13,7 +13,37 @@ namespace ppca {
 
 namespace {
 
-constexpr int kRowsPerBlock = 16;
+// Thread layout shared by the update kernels: with ng = 256 / K row groups,
+// thread t < ng * K owns column c = t % K and row group g = t / K; a block covers
+// rb = ng * kRowsPerThread rows and the thread handles rows g + ng * q of it.
+// The 256 - ng * K spare threads (K not a power of two) load like group ng - 1
+// but store nothing.  All loads are unconditional (row indices clamped to d - 1)
+// so that they issue back to back.  Reductions over rows run in a fixed order
+// (rows of a thread, then groups, then blocks): results do not depend on timing.
+constexpr int kThreads = 256;
+constexpr int kRowsPerThread = 8;
+
+__host__ __device__ inline int row_groups(int K) { return kThreads / K; }
+__host__ __device__ inline int block_rows(int K) { return row_groups(K) * kRowsPerThread; }
+
+struct Lane {
+  int c, g, ng, rb;
+  bool act;
+  int64_t j0;
+  __device__ Lane(int K) {
+    const int t = threadIdx.x;
+    ng = row_groups(K);
+    rb = ng * kRowsPerThread;
+    c = t % K;
+    g = min(t / K, ng - 1);
+    act = t < ng * K;
+    j0 = (int64_t)blockIdx.x * rb;
+  }
+  __device__ int64_t row(int q) const { return j0 + g + ng * q; }
+  __device__ int lrow(int q) const { return g + ng * q; }
+};
+
+__device__ inline int64_t clamp_row(int64_t j, int64_t d) { return j < d ? j : d - 1; }
 
 __device__ inline bool status_set(const int* status) {
   return *reinterpret_cast<const volatile int*>(status) != 0;
@@ -27,140 +57,229 @@ __device__ inline double momentum_step(double g, double mu, int nesterov, float*
   return nesterov ? g + mu * buf : buf;
 }
 
-__global__ __launch_bounds__(256) void k_sanger(float* __restrict__ V, const float* __restrict__ Z,
-                                                const double* __restrict__ G, int64_t d, int K,
-                                                int b, double eta, double mu, int nesterov,
-                                                float* __restrict__ mom, int* status) {
-  __shared__ double Gs[kMaxK * kMaxK];
-  __shared__ double Vs[kRowsPerBlock * kMaxK];
-  if (status_set(status)) return;
-  const int64_t j0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    Gs[e] = i <= c ? G[e] : 0.0;
+// out[c] = sum over w < nblk of part[w * K + c], for c < K (LDS result; scr
+// holds kThreads doubles).  Loads go out eight at a time.
+__device__ inline void sum_partials(const double* __restrict__ part, int nblk, int K,
+                                    const Lane& L, double* scr, double* out) {
+  const int t = threadIdx.x;
+  double s = 0.0;
+  int w = L.g;
+  for (; w + 7 * L.ng < nblk; w += 8 * L.ng) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + u * L.ng) * K + L.c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int64_t j = j0 + e / K;
-    Vs[e] = j < d ? (double)V[j * K + e % K] : 0.0;
+  for (; w < nblk; w += L.ng) s += part[(int64_t)w * K + L.c];
+  if (L.act) scr[t] = s;
+  __syncthreads();
+  if (t < K) {
+    double r = 0.0;
+    for (int g = 0; g < L.ng; ++g) r += scr[g * K + t];
+    out[t] = r;
   }
   __syncthreads();
-  const double inv_b = 1.0 / (double)b;
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    const int64_t j = j0 + r;
-    if (j >= d) continue;
-    double s = (double)Z[j * K + c];
-    for (int i = 0; i <= c; ++i) s = fma(-Vs[r * K + i], Gs[i * K + c], s);
-    const double step = momentum_step(s * inv_b, mu, nesterov, mom, j * K + c);
-    V[j * K + c] = (float)(Vs[r * K + c] + eta * step);
+}
+
+// Per-block column sums of the thread values (fixed order) -> part[blk * K + c].
+__device__ inline void block_column_sum(double val, int K, const Lane& L, double* scr,
+                                        double* __restrict__ part) {
+  const int t = threadIdx.x;
+  if (L.act) scr[t] = val;
+  __syncthreads();
+  if (t < K) {
+    double s = 0.0;
+    for (int g = 0; g < L.ng; ++g) s += scr[g * K + t];
+    part[(int64_t)blockIdx.x * K + t] = s;
   }
 }
 
-// EigenGame, phase 1: grad = (2/b) Z R, per-block partial dots v_c . grad_c.
-__global__ __launch_bounds__(256) void k_eg_grad(const float* __restrict__ V,
-                                                 const float* __restrict__ Z,
-                                                 const double* __restrict__ G, int64_t d, int K,
-                                                 int b, double* __restrict__ grad,
-                                                 double* __restrict__ pdot, int* status) {
-  __shared__ double Rs[kMaxK * kMaxK];
-  __shared__ double Zs[kRowsPerBlock * kMaxK];
-  __shared__ double red[kRowsPerBlock * kMaxK];
-  if (status_set(status)) return;
-  const int64_t j0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    double r = 0.0;
-    if (i == c) r = 1.0;
-    else if (i < c && G[i * K + i] > 1e-300) r = -G[e] / G[i * K + i];
-    Rs[e] = r;
+// Sanger / generalised Oja step.  LDS: Gs [K][K] f64 (upper triangle of G, zeros
+// below) | Vs [rb][K] f32 (the block's rows of V).
+__global__ __launch_bounds__(kThreads) void k_sanger(float* __restrict__ V,
+                                                     const float* __restrict__ Z,
+                                                     const double* __restrict__ G, int64_t d,
+                                                     int K, int b, double eta, double mu,
+                                                     int nesterov, float* __restrict__ mom,
+                                                     int* status) {
+  extern __shared__ double lds[];
+  double* Gs = lds;
+  const Lane L(K);
+  float* Vs = reinterpret_cast<float*>(lds + K * K);
+  const int c = L.c;
+  double z[kRowsPerThread];
+  float v[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t jc = clamp_row(L.row(q), d);
+    z[q] = (double)Z[jc * K + c];
+    v[q] = V[jc * K + c];
   }
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int64_t j = j0 + e / K;
-    Zs[e] = j < d ? (double)Z[j * K + e % K] : 0.0;
-  }
-  __syncthreads();
-  const double sc = 2.0 / (double)b;
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    const int64_t j = j0 + r;
-    double gv = 0.0;
-    if (j < d) {
-      double s = 0.0;
-      for (int i = 0; i <= c; ++i) s = fma(Zs[r * K + i], Rs[i * K + c], s);
-      gv = sc * s;
-      grad[j * K + c] = gv;
-      red[e] = (double)V[j * K + c] * gv;
-    } else {
-      red[e] = 0.0;
+  // rows i = g, g + ng, ... of G, eight loads in flight (clamped index)
+  for (int i0 = L.g; i0 < K; i0 += 8 * L.ng) {
+    double gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) gv[u] = G[min(i0 + u * L.ng, K - 1) * K + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * L.ng;
+      if (L.act && i < K) Gs[i * K + c] = i <= c ? gv[u] : 0.0;
     }
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < K; c += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < kRowsPerBlock; ++r) s += red[r * K + c];
-    pdot[(int64_t)blockIdx.x * K + c] = s;
+  if (L.act) {
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) Vs[L.lrow(q) * K + c] = v[q];
   }
+  const bool stop = status_set(status);
+  __syncthreads();
+  if (stop || !L.act) return;
+  // s = Z_jc - sum_{i <= c} V_ji G_ic, terms in order of i (zeros past c add nothing)
+  for (int i = 0; i < K; ++i) {
+    const double gi = Gs[i * K + c];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q)
+      z[q] = fma(-(double)Vs[L.lrow(q) * K + i], gi, z[q]);
+  }
+  const double inv_b = 1.0 / (double)b;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t j = L.row(q);
+    if (j >= d) continue;
+    const double step = momentum_step(z[q] * inv_b, mu, nesterov, mom, j * K + c);
+    V[j * K + c] = (float)((double)v[q] + eta * step);
+  }
+}
+
+// EigenGame, phase 1: grad = (2/b) Z R and per-block partial dots v_c . grad_c.
+// LDS: Rs [K][K] f64 | scr [kThreads] f64 | Zs [rb][K] f32.
+__global__ __launch_bounds__(kThreads) void k_eg_grad(const float* __restrict__ V,
+                                                      const float* __restrict__ Z,
+                                                      const double* __restrict__ G, int64_t d,
+                                                      int K, int b, double* __restrict__ grad,
+                                                      double* __restrict__ pdot, int* status) {
+  extern __shared__ double lds[];
+  const Lane L(K);
+  double* Rs = lds;
+  double* scr = lds + K * K;
+  float* Zs = reinterpret_cast<float*>(scr + kThreads);
+  const int c = L.c;
+  float v[kRowsPerThread], z[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t jc = clamp_row(L.row(q), d);
+    z[q] = Z[jc * K + c];
+    v[q] = V[jc * K + c];
+  }
+  // R_ic for rows i = g, g + ng, ..., eight row pairs of loads in flight
+  for (int i0 = L.g; i0 < K; i0 += 8 * L.ng) {
+    double gii[8], gic[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + u * L.ng, K - 1);
+      gii[u] = G[i * K + i];
+      gic[u] = G[i * K + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * L.ng;
+      const double qv = -gic[u] / gii[u];
+      const double r = (i < c && gii[u] > 1e-300) ? qv : (i == c ? 1.0 : 0.0);
+      if (L.act && i < K) Rs[i * K + c] = r;
+    }
+  }
+  if (L.act) {
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) Zs[L.lrow(q) * K + c] = L.row(q) < d ? z[q] : 0.f;
+  }
+  const bool stop = status_set(status);
+  __syncthreads();
+  if (stop) return;
+  double s[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) s[q] = 0.0;
+  for (int i = 0; i < K; ++i) {
+    const double ri = Rs[i * K + c];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) s[q] = fma((double)Zs[L.lrow(q) * K + i], ri, s[q]);
+  }
+  const double sc = 2.0 / (double)b;
+  double dot = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t j = L.row(q);
+    if (L.act && j < d) {
+      const double gv = sc * s[q];
+      grad[j * K + c] = gv;
+      dot += (double)v[q] * gv;
+    }
+  }
+  block_column_sum(dot, K, L, scr, pdot);
 }
 
 // EigenGame, phase 2: Riemannian projection, momentum, ascent step; partial norms.
-__global__ __launch_bounds__(256) void k_eg_step(const float* __restrict__ V,
-                                                 const double* __restrict__ grad,
-                                                 const double* __restrict__ pdot, int nblk,
-                                                 int64_t d, int K, double eta, double mu,
-                                                 int nesterov, float* __restrict__ mom,
-                                                 double* __restrict__ vnew,
-                                                 double* __restrict__ pnorm, int* status) {
+__global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ V,
+                                                      const double* __restrict__ grad,
+                                                      const double* __restrict__ pdot, int nblk,
+                                                      int64_t d, int K, double eta, double mu,
+                                                      int nesterov, float* __restrict__ mom,
+                                                      double* __restrict__ vnew,
+                                                      double* __restrict__ pnorm, int* status) {
   __shared__ double dots[kMaxK];
-  __shared__ double red[kRowsPerBlock * kMaxK];
+  __shared__ double scr[kThreads];
+  const Lane L(K);
+  const int c = L.c;
+  float v[kRowsPerThread];
+  double gr[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t jc = clamp_row(L.row(q), d);
+    v[q] = V[jc * K + c];
+    gr[q] = grad[jc * K + c];
+  }
+  sum_partials(pdot, nblk, K, L, scr, dots);
   if (status_set(status)) return;
-  for (int c = threadIdx.x; c < K; c += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < nblk; ++w) s += pdot[(int64_t)w * K + c];
-    dots[c] = s;
-  }
-  __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    const int64_t j = j0 + r;
-    double sq = 0.0;
-    if (j < d) {
-      const double v = (double)V[j * K + c];
-      const double g = grad[j * K + c] - dots[c] * v;
-      const double step = momentum_step(g, mu, nesterov, mom, j * K + c);
-      const double vn = v + eta * step;
+  double sq = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t j = L.row(q);
+    if (L.act && j < d) {
+      const double vq = (double)v[q];
+      const double gq = gr[q] - dots[c] * vq;
+      const double step = momentum_step(gq, mu, nesterov, mom, j * K + c);
+      const double vn = vq + eta * step;
       vnew[j * K + c] = vn;
-      sq = vn * vn;
+      sq += vn * vn;
     }
-    red[e] = sq;
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < K; c += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < kRowsPerBlock; ++r) s += red[r * K + c];
-    pnorm[(int64_t)blockIdx.x * K + c] = s;
-  }
+  block_column_sum(sq, K, L, scr, pnorm);
 }
 
 // EigenGame, phase 3: unit-norm columns.
-__global__ __launch_bounds__(256) void k_eg_normalise(float* __restrict__ V,
-                                                      const double* __restrict__ vnew,
-                                                      const double* __restrict__ pnorm, int nblk,
-                                                      int64_t d, int K, int* status) {
-  __shared__ double inv[kMaxK];
+__global__ __launch_bounds__(kThreads) void k_eg_normalise(float* __restrict__ V,
+                                                           const double* __restrict__ vnew,
+                                                           const double* __restrict__ pnorm,
+                                                           int nblk, int64_t d, int K,
+                                                           int* status) {
+  __shared__ double nrm[kMaxK];
+  __shared__ double scr[kThreads];
+  const Lane L(K);
+  const int c = L.c;
+  double vn[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) vn[q] = vnew[clamp_row(L.row(q), d) * K + c];
+  sum_partials(pnorm, nblk, K, L, scr, nrm);
   if (status_set(status)) return;
-  for (int c = threadIdx.x; c < K; c += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < nblk; ++w) s += pnorm[(int64_t)w * K + c];
-    inv[c] = 1.0 / sqrt(s);
+  if (threadIdx.x < K) {
+    const double s = nrm[threadIdx.x];
     if (!(s > 0.0) || !isfinite(s)) set_status(status, PPCA_ERR_NONFINITE);
   }
-  __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  for (int e = threadIdx.x; e < kRowsPerBlock * K; e += blockDim.x) {
-    const int64_t j = j0 + e / K;
-    const int c = e % K;
-    if (j < d) V[j * K + c] = (float)(vnew[j * K + c] * inv[c]);
+  if (!L.act) return;
+  const double ic = 1.0 / sqrt(nrm[c]);
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t j = L.row(q);
+    if (j < d) V[j * K + c] = (float)(vn[q] * ic);
   }
 }
 
@@ -172,11 +291,14 @@ __global__ void k_copy_f32(const float* __restrict__ s, float* __restrict__ d, i
 
 }  // namespace
 
+int eigengame_blocks(int64_t d, int K) { return (int)cdiv(d, block_rows(K)); }
+
 hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K, int b,
                                 double eta, double mu, int nesterov, float* mom, int* status,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_sanger, dim3((unsigned)cdiv(d, kRowsPerBlock)), dim3(256), 0, s, V, Z, G, d,
-                     K, b, eta, mu, nesterov, mom, status);
+  const size_t lds = (size_t)K * K * sizeof(double) + (size_t)block_rows(K) * K * sizeof(float);
+  hipLaunchKernelGGL(k_sanger, dim3((unsigned)cdiv(d, block_rows(K))), dim3(kThreads), lds, s, V,
+                     Z, G, d, K, b, eta, mu, nesterov, mom, status);
   return hipGetLastError();
 }
 
@@ -184,15 +306,18 @@ hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
                                    double* scratch, int* status, hipStream_t s) {
-  const int nblk = (int)cdiv(d, kRowsPerBlock);
+  const int nblk = eigengame_blocks(d, K);
   double* grad = scratch;
   double* vnew = grad + d * K;
   double* pdot = vnew + d * K;
   double* pnorm = pdot + (int64_t)nblk * K;
-  hipLaunchKernelGGL(k_eg_grad, dim3(nblk), dim3(256), 0, s, V, Z, G, d, K, b, grad, pdot, status);
-  hipLaunchKernelGGL(k_eg_step, dim3(nblk), dim3(256), 0, s, V, grad, pdot, nblk, d, K, eta, mu,
-                     nesterov, mom, vnew, pnorm, status);
-  hipLaunchKernelGGL(k_eg_normalise, dim3(nblk), dim3(256), 0, s, V, vnew, pnorm, nblk, d, K,
+  const size_t lds = ((size_t)K * K + kThreads) * sizeof(double) +
+                     (size_t)block_rows(K) * K * sizeof(float);
+  hipLaunchKernelGGL(k_eg_grad, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, grad, pdot,
+                     status);
+  hipLaunchKernelGGL(k_eg_step, dim3(nblk), dim3(kThreads), 0, s, V, grad, pdot, nblk, d, K, eta,
+                     mu, nesterov, mom, vnew, pnorm, status);
+  hipLaunchKernelGGL(k_eg_normalise, dim3(nblk), dim3(kThreads), 0, s, V, vnew, pnorm, nblk, d, K,
                      status);
   return hipGetLastError();
 }

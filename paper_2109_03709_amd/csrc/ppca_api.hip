@@ -171,7 +171,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.rinv = c.take(kk);
   p.q1 = c.take((size_t)d * K * sizeof(double));
   if (op == PPCA_OP_EIGENGAME) {
-    const int64_t nblk = cdiv(d, 16);
+    const int64_t nblk = eigengame_blocks(d, K);
     p.egs = c.take((size_t)(2 * d * K + 2 * nblk * K) * sizeof(double));
   }
   p.total = c.off;
