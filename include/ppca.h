@@ -14,6 +14,8 @@
  *   ppca_prime_eigengame   minibatch EigenGame utility ascent
  *   ppca_project_gram      Y = X V', G = Y^T Y, B = V'^T V'   (Alg. 1 steps 2-3)
  *   ppca_rayleigh_ritz     full PCA of the projected data      (Alg. 1 step 4)
+ *   ppca_prime_power_grouped / ppca_rayleigh_ritz_grouped
+ *                          the same for hundreds of small bf16 problems at once
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -192,6 +194,51 @@ int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k,
                        float* E, double* evals,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ---- grouped problems ----------------------------------------------------
+ * Many independent PCA problems of uneven n, d and K solved together: every
+ * power pass of all problems is one persistent launch (the problems' rows are
+ * cut into work items of a few MiB, sorted by size and dealt round-robin to
+ * the workgroups), and CholeskyQR2 and Rayleigh-Ritz run one workgroup per
+ * problem.  Each problem follows the single-problem path step for step
+ * (ppca_prime_power, then ppca_project_gram, then ppca_rayleigh_ritz) for
+ * bf16 data: V' = bf16(V), Y' = bf16(X V'), Z = X^T Y', G = Y'^T Y'.
+ * Limits per problem: dtype PPCA_BF16, 1 <= d <= PPCA_GROUP_MAX_D,
+ * 1 <= k, 0 <= l, K = k + l <= min(PPCA_GROUP_MAX_K, n, d). */
+#define PPCA_GROUP_MAX_D 768
+#define PPCA_GROUP_MAX_K 64
+#define PPCA_GROUP_GRAPH 1   /* flag: replay the power iteration as a captured HIP graph */
+
+typedef struct {
+  ppca_matrix X;   /* bf16 data, allocated as n x ld */
+  int32_t k, l;    /* K = k + l directions, k wanted components */
+  float*  V;       /* device d x K f32: starting directions in, primed V out */
+  double* G;       /* device K x K f64: Gram of the projection on the primed V */
+  double* B;       /* device K x K f64: V_eff^T V_eff of that projection's operand */
+  float*  E;       /* device d x k f32 (Rayleigh-Ritz output; may be NULL) */
+  double* evals;   /* device k f64 (Rayleigh-Ritz output) */
+} ppca_problem;
+
+/* Block power priming of every problem (Sec. 2.1, as ppca_prime_power), then
+ * the projection pass on the primed directions (Alg. 1 steps 2-3, as
+ * ppca_project_gram): V_0 = CholQR2(V); iters times { one pass over X gives
+ * Z = X^T Y', V <- CholQR2(Z) }; then G = Y'^T Y' and B for the final V.
+ * probs: host array of nprob >= 1 problems (V, G, B required; E, evals not
+ * used).  flags: 0 or PPCA_GROUP_GRAPH (the iteration is captured once on
+ * `stream` and replayed; `stream` must not be the legacy NULL stream).
+ * Workspace: ppca_grouped_workspace_bytes(probs, nprob).  The status is the
+ * first failure of any problem. */
+int ppca_prime_power_grouped(const ppca_problem* probs, int32_t nprob, int32_t iters,
+                             int32_t flags, void* ws, size_t ws_bytes, void* stream);
+
+/* Rayleigh-Ritz of every problem (Alg. 1 step 4, as ppca_rayleigh_ritz) from
+ * its G, B and V: evals (descending) and, when E is not NULL, the Ritz
+ * vectors E = V_eff R^-1 W[:, :k] with the sign rule of the header. */
+int ppca_rayleigh_ritz_grouped(const ppca_problem* probs, int32_t nprob,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of the grouped calls for these problems (0 if invalid). */
+size_t ppca_grouped_workspace_bytes(const ppca_problem* probs, int32_t nprob);
+
 /* Bytes of workspace needed by operation `op` (PPCA_OP_*) for data X with
  * K directions and minibatch `batch` (rows of the pass for PPCA_OP_STREAM;
  * ignored by the other non-minibatch operations).
@@ -204,7 +251,9 @@ const char* ppca_strerror(int status);
 /* Optional per-kernel timing of the streaming kernels.  When enabled, the
  * library records a pair of HIP events on the caller's stream around every
  * launch of each streaming kernel and accumulates their elapsed times.
- * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty).
+ * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty),
+ * 2 = fused grouped pass (power and projection passes of the grouped calls,
+ * eager mode only).
  * ppca_kernel_stats returns the number of launches and the total ms since
  * the last reset.  Not thread safe; meant for benchmarks. */
 void ppca_set_kernel_timing(int32_t enable);

@@ -25,7 +25,9 @@ EXPORTS = [
     "ppca_center_quantize", "ppca_prime_power", "ppca_prime_oja", "ppca_prime_eigengame",
     "ppca_stream_pass", "ppca_project_gram", "ppca_rayleigh_ritz", "ppca_workspace_bytes", "ppca_strerror",
     "ppca_set_kernel_timing", "ppca_kernel_stats", "ppca_set_chunk_rows",
+    "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
 ]
+GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
 
 
 class PPCAError(RuntimeError):
@@ -46,6 +48,12 @@ class _Sgd(ctypes.Structure):
                 ("nesterov", ctypes.c_int32), ("start_step", ctypes.c_int64),
                 ("mom_buf", ctypes.c_void_p), ("snapshot_every", ctypes.c_int32),
                 ("snapshots", ctypes.c_void_p), ("orthonormalise_start", ctypes.c_int32)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("X", _Matrix), ("k", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("V", ctypes.c_void_p), ("G", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("evals", ctypes.c_void_p)]
 
 
 _lib = None
@@ -79,6 +87,11 @@ def lib():
         L.ppca_kernel_stats.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         L.ppca_set_chunk_rows.argtypes = [i64]
         L.ppca_set_chunk_rows.restype = None
+        pp = ctypes.POINTER(_Problem)
+        L.ppca_prime_power_grouped.argtypes = [pp, i32, i32, i32, vp, sz, vp]
+        L.ppca_rayleigh_ritz_grouped.argtypes = [pp, i32, vp, sz, vp]
+        L.ppca_grouped_workspace_bytes.argtypes = [pp, i32]
+        L.ppca_grouped_workspace_bytes.restype = sz
         _lib = L
     return _lib
 
@@ -285,3 +298,72 @@ def kernel_stats(kernel: int):
 
 def set_chunk_rows(rows: int):
     lib().ppca_set_chunk_rows(int(rows))
+
+
+# --------------------------------------------------------------- grouped
+@dataclass
+class Problem:
+    """One problem of a grouped call: bf16 data X, k + l directions V (d x K
+    float32, updated in place) and the outputs G, B (K x K float64), evals (k
+    float64) and E (d x k float32, optional)."""
+    X: Data
+    k: int
+    l: int
+    V: torch.Tensor
+    G: torch.Tensor | None = None
+    B: torch.Tensor | None = None
+    evals: torch.Tensor | None = None
+    E: torch.Tensor | None = None
+
+    def alloc(self, vectors: bool = True):
+        K, dev = self.k + self.l, self.V.device
+        if self.G is None:
+            self.G = torch.empty((K, K), dtype=torch.float64, device=dev)
+        if self.B is None:
+            self.B = torch.empty((K, K), dtype=torch.float64, device=dev)
+        if self.evals is None:
+            self.evals = torch.empty(self.k, dtype=torch.float64, device=dev)
+        if vectors and self.E is None:
+            self.E = torch.empty((self.X.d, self.k), dtype=torch.float32, device=dev)
+        return self
+
+    def as_c(self) -> _Problem:
+        _check_v(self.V, self.X.d, self.k + self.l)
+        return _Problem(self.X.as_c(), self.k, self.l, self.V.data_ptr(), _ptr(self.G).value,
+                        _ptr(self.B).value, _ptr(self.E).value, _ptr(self.evals).value)
+
+
+def _problem_array(problems):
+    arr = (_Problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p.alloc(vectors=p.E is not None).as_c()
+    return arr
+
+
+def grouped_workspace_bytes(problems) -> int:
+    arr = _problem_array(problems)
+    return int(lib().ppca_grouped_workspace_bytes(arr, len(problems)))
+
+
+def prime_power_grouped(problems, iters: int, graph: bool = False, ws=None):
+    """Block power priming of every problem, then the projection Gram G and
+    B of the primed V (one fused pass over X per iteration for all problems)."""
+    arr = _problem_array(problems)
+    if ws is None:
+        ws = _workspace(int(lib().ppca_grouped_workspace_bytes(arr, len(problems))),
+                        problems[0].V.device)
+    code = lib().ppca_prime_power_grouped(arr, len(problems), iters, GROUP_GRAPH if graph else 0,
+                                          _ptr(ws), ws.numel(), _stream())
+    _check(code, "ppca_prime_power_grouped")
+    return problems
+
+
+def rayleigh_ritz_grouped(problems, ws=None):
+    """Rayleigh-Ritz of every problem from its G, B and V: evals and E."""
+    arr = _problem_array(problems)
+    if ws is None:
+        ws = _workspace(int(lib().ppca_grouped_workspace_bytes(arr, len(problems))),
+                        problems[0].V.device)
+    code = lib().ppca_rayleigh_ritz_grouped(arr, len(problems), _ptr(ws), ws.numel(), _stream())
+    _check(code, "ppca_rayleigh_ritz_grouped")
+    return problems

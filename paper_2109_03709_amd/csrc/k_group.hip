@@ -1,0 +1,647 @@
+// Grouped primed PCA: hundreds of independent problems (bf16 data, d <= 768,
+// K = k + l <= 64) in a handful of launches per power iteration.
+//
+//   k_gpass     fused power / projection pass (Sec. 2.1; Alg. 1 steps 2-3) over
+//               the work items of all problems: Y = X V', Y' = bf16(Y), then
+//               Z += X^T Y' (power pass) or G += Y'^T Y' (projection pass; the
+//               power iterations need no G).  X is read once per pass: the four
+//               waves of a workgroup split the columns of a 16-row tile, each
+//               wave's slice of X is staged in its own LDS buffers by DMA and
+//               used for both products, and the partial Y of the waves is
+//               summed through LDS (one barrier per tile).
+//   k_greduce   fixed-order float64 sums of the item partials -> Z (f32), G (f64)
+//   k_gcholqr2  CholeskyQR2 per problem (one workgroup): new V, its bf16
+//               operand, and B = V'^T V' after the last step
+//   k_grr_h / k_grr_jacobi / k_grr_e
+//               Rayleigh-Ritz per problem (Alg. 1 step 4): R = chol(B),
+//               H = R^-T G R^-1 / n, Jacobi, E = V' R^-1 W[:, :k], signs.
+//
+// Shape classes of the fused pass (class width dc, waves per row tile WD,
+// 64-column groups per wave CW):
+//   dci 0: dc  64, WD 1, CW 1  (four independent row groups)
+//   dci 1: dc 128, WD 2, CW 1  (two row groups)
+//   dci 2: dc 256, WD 4, CW 1
+//   dci 3: dc 512, WD 4, CW 2
+//   dci 4: dc 768, WD 4, CW 3
+// combined with NB = Kp / 16 in 1..4: 20 code paths in one kernel.
+//
+// Partials: Z of item i, row group r: zpart[zoff + (r * Kp + c) * dc + j]
+// (column c of Z, row j of Z); G of item i, wave w: gpart[goff + (w * Kp + c)
+// * Kp + i] holds G_w[i][c] for i <= c (upper blocks; zero elsewhere).
+#include "dense_dev.h"
+#include "lds_dma.h"
+
+namespace ppca {
+
+int group_class_width(int dci) {
+  static const int w[kGroupClasses] = {64, 128, 256, 512, 768};
+  return w[dci];
+}
+int group_row_groups(int dci) { return dci == 0 ? 4 : (dci == 1 ? 2 : 1); }
+int group_dci(int64_t d) {
+  for (int i = 0; i < kGroupClasses; ++i)
+    if (d <= group_class_width(i)) return i;
+  return -1;
+}
+
+namespace {
+
+using namespace dma;
+using dev::status_set;
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+template <int NB, int DCI>
+struct GCls {
+  static constexpr int WD = DCI == 0 ? 1 : (DCI == 1 ? 2 : 4);   // waves sharing a row tile
+  static constexpr int CW = DCI <= 2 ? 1 : DCI - 1;              // 64-column groups per wave
+  static constexpr int WR = 4 / WD;                              // row groups
+  static constexpr int DW = 64 * CW;                             // columns per wave
+  static constexpr int DC = WD * DW;                             // class width
+  static constexpr int KP = 16 * NB;
+  static constexpr int CPR = DW / 8;                             // 16-byte chunks per slice row
+  static constexpr int XSB = 16 * DW * 2;                        // bytes of one stage
+  static constexpr int DPS = XSB / 1024;                         // DMAs per stage
+  static constexpr int NBT = NB * (NB + 1) / 2;                  // upper blocks of G
+  static constexpr int NGS = (NBT + WD - 1) / WD;                // G blocks per wave
+};
+
+constexpr int kGS = 4;                    // X stages per wave
+constexpr int kGStage = 16 * 192 * 2;     // bytes of one stage at the widest class
+constexpr int kGExch = 2 * 4 * 4 * 64;    // exchange slots [parity][wave][nb][lane]
+
+__device__ inline short4_t pack_bf16(float v0, float v1, float v2, float v3) {
+  return short4_t{(short)f32_to_bf16_bits(v0), (short)f32_to_bf16_bits(v1),
+                  (short)f32_to_bf16_bits(v2), (short)f32_to_bf16_bits(v3)};
+}
+
+__device__ inline short4_t as_s4(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(short4_t, make_uint2(lo, hi));
+}
+
+// One work item (rows [r0, r0 + rows) of one problem) of class (NB, DCI).
+// Sub-tile t of row group rg covers item rows (t * WR + rg) * 16 .. + 15.
+template <int NB, int DCI, bool WZ>
+__device__ __attribute__((always_inline)) inline void run_item(const GProb& P, const GItem& I,
+                                                               uint8_t* xl, f32x4_t* ex,
+                                                               float* zpart, float* gpart,
+                                                               int& phase) {
+  using C = GCls<NB, DCI>;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rg = wave / C::WD, wd = wave % C::WD;
+  const int a = lane & 15, g = lane >> 4;
+  const int c0 = wd * C::DW;
+  const int64_t d = P.d, ld = P.ld, rows = I.rows, r0 = I.r0;
+  const uint8_t* x = reinterpret_cast<const uint8_t*>(P.x);
+  uint8_t* st = xl + wave * (kGS * kGStage);
+
+  // operand fragments of this wave's column slice (k-step s: columns c0 + 32 s ..)
+  uint4 vf[2 * C::CW][NB];
+#pragma unroll
+  for (int s = 0; s < 2 * C::CW; ++s)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      vf[s][nb] = *reinterpret_cast<const uint4*>(P.vop + (int64_t)(16 * nb + a) * C::DC + c0 +
+                                                  32 * s + 8 * g);
+
+  // DMA lanes: slot q = 64 j + lane of a stage is (row q / CPR, slot q % CPR)
+  // and holds the slice's 16-byte column chunk slot ^ (row & 7); chunks past d
+  // load column 0 (their operand rows are zero)
+  int drow[C::DPS];
+  int64_t dcol[C::DPS];
+#pragma unroll
+  for (int j = 0; j < C::DPS; ++j) {
+    const int q = 64 * j + lane, r = q / C::CPR, sl = q % C::CPR;
+    const int64_t col = c0 + 8 * (sl ^ (r & 7));
+    drow[j] = r;
+    dcol[j] = (col < d ? col : 0) * 2;
+  }
+  const int64_t srows = 16 * C::WR;
+  const int64_t nsub = (rows + srows - 1) / srows;
+  // DMA of sub-tile t into stage b (t clamped to the last sub-tile, rows past
+  // the item clamped to its last row: every wave issues the same count)
+  auto issue = [&](int64_t t, int b) __attribute__((always_inline)) {
+    const int64_t tc = t < nsub ? t : nsub - 1;
+    const int64_t lb = (tc * C::WR + rg) * 16;
+    uint8_t* dst = st + b * kGStage;
+#pragma unroll
+    for (int j = 0; j < C::DPS; ++j) {
+      int64_t li = lb + drow[j];
+      li = li < rows ? li : rows - 1;
+      dma16(x + (r0 + li) * ld * 2 + dcol[j], dst + j * 1024);
+    }
+  };
+
+  // Z accumulators (Z pass) or G accumulators (G pass)
+  constexpr int NZ = WZ ? C::CW : 0, NG = WZ ? 0 : C::NGS;
+  f32x4_t zacc[NZ > 0 ? NZ : 1][4][NB];
+  f32x4_t gacc[NG > 0 ? NG : 1];
+#pragma unroll
+  for (int q = 0; q < NZ; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < NG; ++i) gacc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  wait_vmcnt<0>();   // the operand fragments have landed before the DMA stream starts
+  wait_lgkm0();      // LDS reads of the previous item are done before its stages refill
+  issue(0, 0);
+  issue(1, 1);
+  issue(2, 2);
+  for (int64_t t = 0; t < nsub; ++t) {
+    wait_vmcnt<2 * C::DPS>();   // this wave's stage t has landed
+    wait_lgkm0();               // ... and stage t - 1 has been read
+    issue(t + 3, (int)((t + 3) & 3));
+    const uint8_t* xs = st + (int)(t & 3) * kGStage;
+
+    // partial Y of the slice: rows a, k-chunk 4 s + g (16 bytes, row-major)
+    f32x4_t ya[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) ya[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2 * C::CW; ++s) {
+      const uint4 av =
+          *reinterpret_cast<const uint4*>(xs + (a * C::CPR + ((4 * s + g) ^ (a & 7))) * 16);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        ya[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
+                                                         ya[nb], 0, 0, 0);
+    }
+    // sum over the waves of the row group, in wave order (lane layout of the
+    // MFMA output: rows 4 g .. 4 g + 3 of column a)
+    if constexpr (C::WD > 1) {
+      const int par = phase & 1;
+      ++phase;
+      f32x4_t* mine = ex + (par * 4 + wave) * NB * 64 + lane;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) mine[nb * 64] = ya[nb];
+      wait_lgkm0();
+      raw_barrier();
+      const f32x4_t* src = ex + (par * 4 + rg * C::WD) * NB * 64 + lane;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        f32x4_t y = src[nb * 64];
+#pragma unroll
+        for (int j = 1; j < C::WD; ++j) y += src[(j * NB + nb) * 64];
+        ya[nb] = y;
+      }
+    }
+    // Y' = bf16(Y), rows past the item zeroed; the fragment is at once the
+    // B operand (rows 4 g .., column a) of both products below
+    const int64_t vr = rows - (t * C::WR + rg) * 16;
+    short4_t yf[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float y0 = (4 * g + 0 < vr) ? ya[nb][0] : 0.f;
+      const float y1 = (4 * g + 1 < vr) ? ya[nb][1] : 0.f;
+      const float y2 = (4 * g + 2 < vr) ? ya[nb][2] : 0.f;
+      const float y3 = (4 * g + 3 < vr) ? ya[nb][3] : 0.f;
+      yf[nb] = pack_bf16(y0, y1, y2, y3);
+    }
+    // G += Y'^T Y' on the upper blocks (mb <= nb), dealt over the row group's waves
+    if constexpr (!WZ)
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+      for (int nb = mb; nb < NB; ++nb) {
+        const int idx = mb * NB - mb * (mb - 1) / 2 + (nb - mb);
+        if (idx % C::WD == wd)
+          gacc[idx / C::WD] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yf[mb], yf[nb],
+                                                                         gacc[idx / C::WD], 0, 0, 0);
+      }
+    // Z += X^T Y': column group q, lane (a, g) reads 4 columns (4 a ..) of rows
+    // 4 g .. 4 g + 3 and transposes them into 4 A fragments (column 4 a + v)
+    if constexpr (WZ) {
+#pragma unroll
+      for (int q = 0; q < C::CW; ++q) {
+        uint2 in[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 4 * g + i, ch = 8 * q + (a >> 1);
+          in[i] = *reinterpret_cast<const uint2*>(xs + (row * C::CPR + (ch ^ (row & 7))) * 16 +
+                                                  (a & 1) * 8);
+        }
+        short4_t af[4];
+        af[0] = as_s4((in[0].x & 0xFFFFu) | (in[1].x << 16), (in[2].x & 0xFFFFu) | (in[3].x << 16));
+        af[1] = as_s4((in[0].x >> 16) | (in[1].x & 0xFFFF0000u),
+                      (in[2].x >> 16) | (in[3].x & 0xFFFF0000u));
+        af[2] = as_s4((in[0].y & 0xFFFFu) | (in[1].y << 16), (in[2].y & 0xFFFFu) | (in[3].y << 16));
+        af[3] = as_s4((in[0].y >> 16) | (in[1].y & 0xFFFF0000u),
+                      (in[2].y >> 16) | (in[3].y & 0xFFFF0000u));
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            zacc[q][v][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[v], yf[nb],
+                                                                        zacc[q][v][nb], 0, 0, 0);
+      }
+    }
+  }
+  wait_vmcnt<0>();
+
+  // partials.  Z: lane (a, g) of MFMA (q, v, nb) holds Z[c0 + 64 q + 16 g + 4 i + v][16 nb + a]
+  if constexpr (WZ) {
+    float* zp = zpart + I.zoff + (int64_t)rg * C::KP * C::DC;
+#pragma unroll
+    for (int q = 0; q < C::CW; ++q)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          *reinterpret_cast<float4*>(zp + (int64_t)(16 * nb + a) * C::DC + c0 + 64 * q + 16 * g +
+                                     4 * i) =
+              make_float4(zacc[q][0][nb][i], zacc[q][1][nb][i], zacc[q][2][nb][i],
+                          zacc[q][3][nb][i]);
+  }
+  // G: block (mb, nb), lane (a, g) holds G[16 mb + 4 g + i][16 nb + a]
+  if constexpr (!WZ) {
+  float* gp = gpart + I.goff + (int64_t)wave * C::KP * C::KP;
+#pragma unroll
+  for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      f32x4_t v = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      if (mb <= nb) {
+        const int idx = mb * NB - mb * (mb - 1) / 2 + (nb - mb);
+        if (idx % C::WD == wd) v = gacc[idx / C::WD];
+      }
+      *reinterpret_cast<float4*>(gp + (16 * nb + a) * C::KP + 16 * mb + 4 * g) =
+          make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// Persistent fused pass: workgroup w takes items w, w + gridDim.x, ... (the
+// items are sorted by size, largest first).  WZ: power pass (Z only);
+// otherwise projection pass (G only).
+template <bool WZ>
+__global__ __launch_bounds__(256, 1) void k_gpass(const GProb* __restrict__ probs,
+                                                  const GItem* __restrict__ items, int nitems,
+                                                  float* zpart, float* gpart) {
+  __shared__ __attribute__((aligned(16))) uint8_t xl[4 * kGS * kGStage];
+  __shared__ f32x4_t ex[kGExch];
+  int phase = 0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const GItem I = items[it];
+    const GProb& P = probs[I.prob];
+#define PPCA_GCASE(nb, dci)                                              \
+  case (dci) * 4 + (nb) - 1:                                             \
+    run_item<nb, dci, WZ>(P, I, xl, ex, zpart, gpart, phase);            \
+    break;
+    switch (P.cls) {
+      PPCA_GCASE(1, 0) PPCA_GCASE(2, 0) PPCA_GCASE(3, 0) PPCA_GCASE(4, 0)
+      PPCA_GCASE(1, 1) PPCA_GCASE(2, 1) PPCA_GCASE(3, 1) PPCA_GCASE(4, 1)
+      PPCA_GCASE(1, 2) PPCA_GCASE(2, 2) PPCA_GCASE(3, 2) PPCA_GCASE(4, 2)
+      PPCA_GCASE(1, 3) PPCA_GCASE(2, 3) PPCA_GCASE(3, 3) PPCA_GCASE(4, 3)
+      PPCA_GCASE(1, 4) PPCA_GCASE(2, 4) PPCA_GCASE(3, 4) PPCA_GCASE(4, 4)
+      default: break;
+    }
+#undef PPCA_GCASE
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order float64 reduction.  Blocks of problem p: [blk0[p], blk0[p+1]);
+// the first cdiv(d K, 256) of them (want_z) sum Z, one thread per element
+// (column-major over the partial layout), the rest G (i <= c, mirrored).
+// The partials of problem p are summed in item order, then row group / wave.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_greduce(const GProb* __restrict__ probs, int nprob,
+                                                 const int* __restrict__ blk0,
+                                                 const float* __restrict__ zpart,
+                                                 const float* __restrict__ gpart, int want_z,
+                                                 int* status) {
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk0[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const GProb& P = probs[lo];
+  const int b = bid - blk0[lo];
+  const int64_t d = P.d;
+  const int K = P.K, Kp = P.Kp, dc = P.dc;
+  const int64_t zb = want_z ? (d * K + 255) / 256 : 0;
+  const int t = threadIdx.x;
+  if (b < zb) {
+    const int64_t e = (int64_t)b * 256 + t;
+    if (e >= d * K) return;
+    const int c = (int)(e / d);
+    const int64_t j = e - (int64_t)c * d;
+    const int64_t stride = (int64_t)Kp * dc;
+    const int np = P.nitem * P.wr;
+    const float* zp = zpart + P.zbase + (int64_t)c * dc + j;
+    double s = 0.0;
+    int u = 0;
+    for (; u + 8 <= np; u += 8) {
+      float v[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[w] = zp[(int64_t)(u + w) * stride];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) s += (double)v[w];
+    }
+    for (; u < np; ++u) s += (double)zp[(int64_t)u * stride];
+    if (!isfinite(s)) set_status(status, PPCA_ERR_NONFINITE);
+    P.Z[j * K + c] = (float)s;
+  } else {
+    const int e = (int)(b - zb) * 256 + t;
+    if (e >= K * K) return;
+    const int i = e / K, c = e - i * K;
+    if (i > c) return;
+    const int64_t stride = (int64_t)Kp * Kp;
+    const int np = P.nitem * 4;
+    const float* gp = gpart + P.gbase + (int64_t)c * Kp + i;
+    double s = 0.0;
+    int u = 0;
+    for (; u + 8 <= np; u += 8) {
+      float v[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[w] = gp[(int64_t)(u + w) * stride];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) s += (double)v[w];
+    }
+    for (; u < np; ++u) s += (double)gp[(int64_t)u * stride];
+    if (!isfinite(s)) set_status(status, PPCA_ERR_NONFINITE);
+    P.G[i * K + c] = s;
+    P.G[c * K + i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup dense float64 helpers (256 threads, K <= 64).
+// ---------------------------------------------------------------------------
+constexpr int kGStg = 16;   // rows staged per step
+
+// out[i][c] = sum_r a(r, i) a(r, c) for a rows x K block, rows in order;
+// thread t owns the 4 x 4 tile t of the upper triangle (tiles of the 16 x 16
+// tile grid of a 64-wide matrix: at most 136 tiles).  out: global K x K, both
+// triangles written.  stg: LDS [kGStg][64].
+template <typename Load>
+__device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, double* stg) {
+  const int t = threadIdx.x;
+  const int nt = (K + 3) / 4;
+  const int ntile = nt * (nt + 1) / 2;
+  int ti = 0, rem = t;
+  while (ti < nt && rem >= nt - ti) {
+    rem -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const bool act = t < ntile;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t r0 = 0; r0 < rows; r0 += kGStg) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kGStg * 64 / 256; ++m) {
+      const int e = t + 256 * m, rr = e >> 6, cc = e & 63;
+      stg[e] = (r0 + rr < rows && cc < K) ? load(r0 + rr, cc) : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int rr = 0; rr < kGStg; ++rr) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = stg[rr * 64 + 4 * ti + u];
+          bv[u] = stg[rr * 64 + 4 * tj + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * ti + u, c = 4 * tj + v;
+        if (i < K && c < K) {
+          out[i * K + c] = acc[u][v];
+          out[c * K + i] = acc[u][v];
+        }
+      }
+  }
+  __syncthreads();
+}
+
+// out(r, c) = sum_{p <= c} a(r, p) Rinv[p][c] (p ascending) for a rows x K
+// block; Rl: LDS [64][64] copy of Rinv (zero below the diagonal), stg: LDS
+// [kGStg][64].
+template <typename Load, typename Store>
+__device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rinv, double* Rl,
+                               double* stg, Store store) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int i = e >> 6, c = e & 63;
+    Rl[e] = (i < K && c < K && i <= c) ? Rinv[i * K + c] : 0.0;
+  }
+  for (int64_t r0 = 0; r0 < rows; r0 += kGStg) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kGStg * 64 / 256; ++m) {
+      const int e = t + 256 * m, rr = e >> 6, cc = e & 63;
+      stg[e] = (r0 + rr < rows && cc < K) ? load(r0 + rr, cc) : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < kGStg * K; e += 256) {
+      const int rr = e / K, c = e - rr * K;
+      if (r0 + rr >= rows) continue;
+      double s = 0.0;
+      for (int p = 0; p <= c; ++p) s = fma(stg[rr * 64 + p], Rl[p * 64 + c], s);
+      store(r0 + rr, c, s);
+    }
+  }
+  __syncthreads();
+}
+
+// CholeskyQR2 of Z (or of V when from_v) for problem blockIdx.x: V = Q, the
+// operand vop[c][j] = bf16(V[j][c]) (zero for j >= d or c >= K, up to Kp x dc)
+// and, with want_b, B = V'^T V' of the bf16 values.
+__global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ probs, int from_v,
+                                                  int want_b, int* status) {
+  __shared__ double stg[kGStg * 64];
+  __shared__ double Rl[64 * 64];
+  const GProb& P = probs[blockIdx.x];
+  const int64_t d = P.d;
+  const int K = P.K;
+  const float* src = from_v ? P.V : P.Z;
+  double* q1 = P.q1;
+  float* V = P.V;
+  gram_wg([&](int64_t r, int c) { return (double)src[r * K + c]; }, d, K, P.A, stg);
+  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status);
+  __syncthreads();
+  trmm_wg([&](int64_t r, int c) { return (double)src[r * K + c]; }, d, K, P.Rinv, Rl, stg,
+          [&](int64_t r, int c, double v) { q1[r * K + c] = v; });
+  gram_wg([&](int64_t r, int c) { return q1[r * K + c]; }, d, K, P.A, stg);
+  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status);
+  __syncthreads();
+  trmm_wg([&](int64_t r, int c) { return q1[r * K + c]; }, d, K, P.Rinv, Rl, stg,
+          [&](int64_t r, int c, double v) { V[r * K + c] = (float)v; });
+  // operand (V was written by this workgroup before the barrier above)
+  const int Kp = P.Kp, dc = P.dc;
+  for (int e = threadIdx.x; e < Kp * dc; e += 256) {
+    const int c = e / dc, j = e - c * dc;
+    P.vop[e] = (j < d && c < K) ? (uint16_t)f32_to_bf16_bits(V[(int64_t)j * K + c]) : 0;
+  }
+  if (want_b)
+    gram_wg([&](int64_t r, int c) {
+      return (double)bf16_bits_to_f32(f32_to_bf16_bits(V[r * K + c]));
+    }, d, K, P.B, stg);
+}
+
+// Rayleigh-Ritz, part 1: R = chol(B), T = G R^-1, H = (R^-T T) / n.
+__global__ __launch_bounds__(256) void k_grr_h(const GProb* __restrict__ probs, int* status) {
+  __shared__ double Rl[64 * 64];
+  __shared__ double Gl[64 * 64];
+  __shared__ double Tl[64 * 64];
+  const GProb& P = probs[blockIdx.x];
+  const int K = P.K, t = threadIdx.x;
+  dev::chol_inv_dev<kGroupMaxK>(P.B, K, P.R, P.Rinv, status);
+  __syncthreads();
+  for (int e = t; e < K * K; e += 256) {
+    Rl[e] = P.Rinv[e];
+    Gl[e] = P.G[e];
+  }
+  __syncthreads();
+  for (int e = t; e < K * K; e += 256) {
+    const int i = e / K, j = e - i * K;
+    double s = 0.0;
+    for (int p = 0; p < K; ++p) s = fma(Gl[i * K + p], Rl[p * K + j], s);
+    Tl[e] = s;
+  }
+  __syncthreads();
+  const double inv_n = 1.0 / (double)P.n;
+  for (int e = t; e < K * K; e += 256) {
+    const int i = e / K, j = e - i * K;
+    double s = 0.0;
+    for (int p = 0; p < K; ++p) s = fma(Rl[p * K + i], Tl[p * K + j], s);
+    P.H[e] = inv_n * s;
+  }
+}
+
+// Rayleigh-Ritz, part 2: Jacobi on H; workgroup (x, problem) owns W rows 16 x ..
+__global__ __launch_bounds__(1024) void k_grr_jacobi(const GProb* __restrict__ probs,
+                                                     int max_sweeps, int* status) {
+  const GProb& P = probs[blockIdx.y];
+  if ((int)blockIdx.x * dev::kJacRows >= P.K) return;
+  dev::jacobi_dev<kGroupMaxK>(P.H, P.K, P.W, P.ev, max_sweeps, status, blockIdx.x);
+}
+
+// Rayleigh-Ritz, part 3: M = R^-1 W[:, :k], E = V_eff M (V_eff = bf16(V)),
+// column signs (largest |.| positive, lowest row on ties), evals = theta[:k].
+__global__ __launch_bounds__(256) void k_grr_e(const GProb* __restrict__ probs, int* status) {
+  __shared__ double Ml[64 * 64];
+  __shared__ float bv[256];
+  __shared__ int bi[256];
+  __shared__ int flip[64];
+  const GProb& P = probs[blockIdx.x];
+  const int K = P.K, k = P.k, t = threadIdx.x;
+  const int64_t d = P.d;
+  if (t < k) P.evals[t] = P.ev[t];
+  if (P.E == nullptr) return;
+  for (int e = t; e < K * k; e += 256) {
+    const int i = e / k, j = e - i * k;
+    double s = 0.0;
+    for (int p = 0; p < K; ++p) s = fma(P.Rinv[i * K + p], P.W[p * K + j], s);
+    Ml[e] = s;
+  }
+  __syncthreads();
+  float* E = P.E;
+  const float* V = P.V;
+  for (int64_t e = t; e < d * k; e += 256) {
+    const int64_t j = e / k;
+    const int c = (int)(e - j * k);
+    double s = 0.0;
+    for (int p = 0; p < K; ++p)
+      s = fma((double)bf16_bits_to_f32(f32_to_bf16_bits(V[j * K + p])), Ml[p * k + c], s);
+    E[e] = (float)s;
+  }
+  __syncthreads();
+  // thread (c, g): rows g, g + ng, ... of column c
+  const int ng = 256 / k;
+  const int c = t % k, g = t / k;
+  float best = -1.f;
+  int bidx = 0;
+  if (g < ng)
+    for (int64_t j = g; j < d; j += ng) {
+      const float v = fabsf(E[j * k + c]);
+      if (v > best) {
+        best = v;
+        bidx = (int)j;
+      }
+    }
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  if (t < k) {
+    float b = bv[t];
+    int ix = bi[t];
+    for (int h = 1; h < ng; ++h) {
+      const float v = bv[h * k + t];
+      const int i2 = bi[h * k + t];
+      if (v > b || (v == b && i2 < ix)) {
+        b = v;
+        ix = i2;
+      }
+    }
+    flip[t] = E[(int64_t)ix * k + t] < 0.f;
+  }
+  __syncthreads();
+  for (int64_t e = t; e < d * k; e += 256) {
+    const int cc = (int)(e % k);
+    if (flip[cc]) E[e] = -E[e];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_group_pass(const GProb* probs, const GItem* items, int nitems, int grid,
+                             float* zpart, float* gpart, bool want_z, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (want_z)
+    hipLaunchKernelGGL(k_gpass<true>, dim3(grid), dim3(256), 0, s, probs, items, nitems, zpart,
+                       gpart);
+  else
+    hipLaunchKernelGGL(k_gpass<false>, dim3(grid), dim3(256), 0, s, probs, items, nitems, zpart,
+                       gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_reduce(const GProb* probs, int nprob, const int* blk0, int nblk,
+                               const float* zpart, const float* gpart, bool want_z, int* status,
+                               hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_greduce, dim3(nblk), dim3(256), 0, s, probs, nprob, blk0, zpart, gpart,
+                     want_z ? 1 : 0, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_cholqr2(const GProb* probs, int nprob, bool from_v, bool want_b,
+                                int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcholqr2, dim3(nprob), dim3(256), 0, s, probs, from_v ? 1 : 0,
+                     want_b ? 1 : 0, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_rr(const GProb* probs, int nprob, int max_sweeps, int* status,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_grr_h, dim3(nprob), dim3(256), 0, s, probs, status);
+  hipLaunchKernelGGL(k_grr_jacobi, dim3(kGroupMaxK / dev::kJacRows, nprob), dim3(1024), 0, s,
+                     probs, max_sweeps, status);
+  hipLaunchKernelGGL(k_grr_e, dim3(nprob), dim3(256), 0, s, probs, status);
+  return hipGetLastError();
+}
+
+}  // namespace ppca

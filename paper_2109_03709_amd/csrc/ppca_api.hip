@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -24,7 +25,7 @@ struct KStat {
   int64_t launches = 0;
   double ms = 0.0;
 };
-KStat g_stats[2];
+KStat g_stats[3];
 struct Pending {
   hipEvent_t a, b;
   int kernel;
@@ -301,6 +302,173 @@ int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipSt
     if (_rc != PPCA_OK) return _rc; \
   } while (0)
 
+
+// ---------------------------------------------------------- grouped problems
+constexpr int64_t kGroupItemBytes = 3 << 20;   // X bytes per work item (target)
+
+struct GroupPlan {
+  size_t status = 0, probs = 0, items = 0, blk_z = 0, blk_g = 0, zpart = 0, gpart = 0;
+  size_t total = 0;
+  std::vector<GProb> hp;
+  std::vector<GItem> hi;
+  std::vector<int> bz, bg;                       // reduce block starts, nprob + 1 each
+  std::vector<size_t> pv, pz, pq, pk;            // per problem: vop, Z, q1, K x K block
+};
+
+int check_group_problem(const ppca_problem& q) {
+  const int rc = check_matrix(&q.X);
+  if (rc != PPCA_OK) return rc;
+  if (q.X.dtype != PPCA_BF16) return PPCA_ERR_DTYPE;
+  if (q.X.d > kGroupMaxD || q.k < 1 || q.l < 0) return PPCA_ERR_ARG;
+  const int64_t K = (int64_t)q.k + q.l;
+  if (K > kGroupMaxK || K > q.X.d || K > q.X.n) return PPCA_ERR_ARG;
+  return PPCA_OK;
+}
+
+int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
+  if (!pr || nprob < 1) return PPCA_ERR_ARG;
+  Carve c;
+  gp.status = c.take(256);
+  gp.hp.assign(nprob, GProb{});
+  gp.bz.assign(nprob + 1, 0);
+  gp.bg.assign(nprob + 1, 0);
+  gp.pv.resize(nprob);
+  gp.pz.resize(nprob);
+  gp.pq.resize(nprob);
+  gp.pk.resize(nprob);
+  gp.hi.clear();
+  int64_t zf = 0, gf = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const ppca_problem& q = pr[p];
+    const int rc = check_group_problem(q);
+    if (rc != PPCA_OK) return rc;
+    const int64_t n = q.X.n, d = q.X.d;
+    const int K = q.k + q.l, Kp = (int)round_up(K, 16);
+    const int dci = group_dci(d), dc = group_class_width(dci), wr = group_row_groups(dci);
+    GProb& P = gp.hp[p];
+    P.x = reinterpret_cast<const uint16_t*>(q.X.x);
+    P.n = n;
+    P.d = d;
+    P.ld = q.X.ld;
+    P.K = K;
+    P.Kp = Kp;
+    P.k = q.k;
+    P.cls = dci * 4 + Kp / 16 - 1;
+    P.dc = dc;
+    P.wr = wr;
+    // work items: about kGroupItemBytes of X each, whole 16-row tiles of every row group
+    const int64_t step = 16 * wr;
+    int64_t rt = round_up(std::max<int64_t>(cdiv(kGroupItemBytes, d * 2), step), step);
+    int64_t ni = cdiv(n, rt);
+    rt = round_up(cdiv(n, ni), step);
+    ni = cdiv(n, rt);
+    P.nitem = (int32_t)ni;
+    P.zbase = zf;
+    P.gbase = gf;
+    const int64_t zs = (int64_t)wr * Kp * dc, gs = (int64_t)4 * Kp * Kp;
+    for (int64_t m = 0; m < ni; ++m) {
+      GItem it{};
+      it.prob = p;
+      it.r0 = m * rt;
+      it.rows = std::min(rt, n - m * rt);
+      it.zoff = zf + m * zs;
+      it.goff = gf + m * gs;
+      gp.hi.push_back(it);
+    }
+    zf += ni * zs;
+    gf += ni * gs;
+    gp.bz[p + 1] = gp.bz[p] + (int)cdiv(d * K, 256);
+    gp.bg[p + 1] = gp.bg[p] + (int)cdiv((int64_t)K * K, 256);
+    const size_t kk = (size_t)K * K * sizeof(double);
+    gp.pv[p] = c.take((size_t)Kp * dc * sizeof(uint16_t));
+    gp.pz[p] = c.take((size_t)d * K * sizeof(float));
+    gp.pq[p] = c.take((size_t)d * K * sizeof(double));
+    gp.pk[p] = c.take(5 * kk + (size_t)K * sizeof(double));
+  }
+  // largest items first (X bytes), ties by problem and row: a fixed order
+  std::stable_sort(gp.hi.begin(), gp.hi.end(), [&](const GItem& a, const GItem& b) {
+    const int64_t ca = a.rows * gp.hp[a.prob].d, cb = b.rows * gp.hp[b.prob].d;
+    return ca > cb;
+  });
+  gp.probs = c.take(gp.hp.size() * sizeof(GProb));
+  gp.items = c.take(gp.hi.size() * sizeof(GItem));
+  gp.blk_z = c.take(gp.bz.size() * sizeof(int));
+  gp.blk_g = c.take(gp.bg.size() * sizeof(int));
+  gp.zpart = c.take((size_t)zf * sizeof(float));
+  gp.gpart = c.take((size_t)gf * sizeof(float));
+  gp.total = c.off;
+  return PPCA_OK;
+}
+
+// Device pointers of the per-problem buffers and the caller's arrays.
+void bind_group_plan(GroupPlan& gp, const ppca_problem* pr, void* ws) {
+  for (size_t p = 0; p < gp.hp.size(); ++p) {
+    GProb& P = gp.hp[p];
+    const ppca_problem& q = pr[p];
+    P.V = q.V;
+    P.G = q.G;
+    P.B = q.B;
+    P.E = q.E;
+    P.evals = q.evals;
+    P.vop = at<uint16_t>(ws, gp.pv[p]);
+    P.Z = at<float>(ws, gp.pz[p]);
+    P.q1 = at<double>(ws, gp.pq[p]);
+    double* kb = at<double>(ws, gp.pk[p]);
+    const size_t kk = (size_t)P.K * P.K;
+    P.A = kb;
+    P.R = kb + kk;
+    P.Rinv = kb + 2 * kk;
+    P.H = kb + 3 * kk;
+    P.W = kb + 4 * kk;
+    P.ev = kb + 5 * kk;
+  }
+}
+
+int upload_group_plan(const GroupPlan& gp, void* ws, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.probs), gp.hp.data(), gp.hp.size() * sizeof(GProb),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.items), gp.hi.data(), gp.hi.size() * sizeof(GItem),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.blk_z), gp.bz.data(), gp.bz.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.blk_g), gp.bg.data(), gp.bg.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_zero(at<int>(ws, gp.status), 256, s));
+  return PPCA_OK;
+}
+
+int finish_group(const GroupPlan& gp, void* ws, hipStream_t s) {
+  int h = 0;
+  if (hipMemcpyAsync(&h, at<int>(ws, gp.status), sizeof(int), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return PPCA_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return PPCA_ERR_HIP;
+  if (g_timing) resolve_timings();
+  return h;
+}
+
+int check_group_ws(void* ws, size_t ws_bytes, const GroupPlan& gp) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < gp.total)
+    return PPCA_ERR_WORKSPACE;
+  return PPCA_OK;
+}
+
+// One power iteration of every problem: fused Z pass, reduction, CholeskyQR2.
+int group_iteration(const GroupPlan& gp, void* ws, bool want_b, bool time_it, hipStream_t s) {
+  const GProb* dP = at<GProb>(ws, gp.probs);
+  const int nprob = (int)gp.hp.size(), nitems = (int)gp.hi.size();
+  const int grid = std::min(nitems, kNumCU);
+  int* st = at<int>(ws, gp.status);
+  auto pass = [&] {
+    return launch_group_pass(dP, at<GItem>(ws, gp.items), nitems, grid, at<float>(ws, gp.zpart),
+                             at<float>(ws, gp.gpart), true, s);
+  };
+  HIP_TRY(time_it ? timed(2, s, pass) : pass());
+  HIP_TRY(launch_group_reduce(dP, nprob, at<int>(ws, gp.blk_z), gp.bz.back(),
+                              at<float>(ws, gp.zpart), at<float>(ws, gp.gpart), true, st, s));
+  HIP_TRY(launch_group_cholqr2(dP, nprob, false, want_b, st, s));
+  return PPCA_OK;
+}
 int check_sgd(const ppca_matrix* X, const ppca_sgd_params* q) {
   if (!q) return PPCA_ERR_ARG;
   if (q->batch < 1 || q->batch > X->n || q->steps < 0 || q->start_step < 0) return PPCA_ERR_ARG;
@@ -474,6 +642,80 @@ int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k, const double*
   return finish(p, ws, s);
 }
 
+int ppca_prime_power_grouped(const ppca_problem* probs, int32_t nprob, int32_t iters,
+                             int32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (iters < 0 || (flags & ~PPCA_GROUP_GRAPH) != 0) return PPCA_ERR_ARG;
+  if (!probs || nprob < 1) return PPCA_ERR_ARG;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].V || !probs[p].G || !probs[p].B) return PPCA_ERR_ARG;
+  GroupPlan gp;
+  RET_IF(make_group_plan(probs, nprob, gp));
+  RET_IF(check_group_ws(ws, ws_bytes, gp));
+  hipStream_t s = (hipStream_t)stream;
+  const bool graph = (flags & PPCA_GROUP_GRAPH) != 0;
+  if (graph && s == nullptr) return PPCA_ERR_ARG;
+  bind_group_plan(gp, probs, ws);
+  RET_IF(upload_group_plan(gp, ws, s));
+  const GProb* dP = at<GProb>(ws, gp.probs);
+  int* st = at<int>(ws, gp.status);
+  HIP_TRY(launch_group_cholqr2(dP, nprob, true, iters == 0, st, s));
+  if (graph && iters > 1) {
+    // iterations 1 .. iters-1 replay one captured iteration; the last one
+    // (which also forms B) runs eagerly
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = group_iteration(gp, ws, false, false, s);
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (rc != PPCA_OK || ec != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return rc != PPCA_OK ? rc : PPCA_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return PPCA_ERR_HIP;
+    hipError_t el = hipSuccess;
+    for (int t = 0; t + 1 < iters && el == hipSuccess; ++t) el = hipGraphLaunch(ge, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    hipGraphExecDestroy(ge);
+    if (el != hipSuccess || es != hipSuccess) return PPCA_ERR_HIP;
+    RET_IF(group_iteration(gp, ws, true, false, s));
+  } else {
+    for (int t = 0; t < iters; ++t) RET_IF(group_iteration(gp, ws, t == iters - 1, !graph, s));
+  }
+  // projection pass on the primed directions: G only
+  const int nitems = (int)gp.hi.size();
+  auto pass = [&] {
+    return launch_group_pass(dP, at<GItem>(ws, gp.items), nitems, std::min(nitems, kNumCU),
+                             at<float>(ws, gp.zpart), at<float>(ws, gp.gpart), false, s);
+  };
+  HIP_TRY(graph ? pass() : timed(2, s, pass));
+  HIP_TRY(launch_group_reduce(dP, nprob, at<int>(ws, gp.blk_g), gp.bg.back(),
+                              at<float>(ws, gp.zpart), at<float>(ws, gp.gpart), false, st, s));
+  return finish_group(gp, ws, s);
+}
+
+int ppca_rayleigh_ritz_grouped(const ppca_problem* probs, int32_t nprob, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!probs || nprob < 1) return PPCA_ERR_ARG;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].G || !probs[p].B || !probs[p].evals || !probs[p].V) return PPCA_ERR_ARG;
+  GroupPlan gp;
+  RET_IF(make_group_plan(probs, nprob, gp));
+  RET_IF(check_group_ws(ws, ws_bytes, gp));
+  hipStream_t s = (hipStream_t)stream;
+  bind_group_plan(gp, probs, ws);
+  RET_IF(upload_group_plan(gp, ws, s));
+  HIP_TRY(launch_group_rr(at<GProb>(ws, gp.probs), nprob, 60, at<int>(ws, gp.status), s));
+  return finish_group(gp, ws, s);
+}
+
+size_t ppca_grouped_workspace_bytes(const ppca_problem* probs, int32_t nprob) {
+  GroupPlan gp;
+  if (make_group_plan(probs, nprob, gp) != PPCA_OK) return 0;
+  return gp.total;
+}
+
 size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch) {
   if (!X || X->n < 1 || X->d < 1) return 0;
   if (op < PPCA_OP_CENTER || op > PPCA_OP_STREAM) return 0;
@@ -502,12 +744,11 @@ const char* ppca_strerror(int status) {
 void ppca_set_kernel_timing(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_tmu);
   g_timing = enable != 0;
-  g_stats[0] = KStat();
-  g_stats[1] = KStat();
+  for (auto& st : g_stats) st = KStat();
 }
 
 int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
-  if (kernel < 0 || kernel > 1) return PPCA_ERR_ARG;
+  if (kernel < 0 || kernel > 2) return PPCA_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (launches) *launches = g_stats[kernel].launches;
   if (total_ms) *total_ms = g_stats[kernel].ms;

@@ -128,4 +128,52 @@ hipError_t launch_center_quantize(const float* x, int64_t n, int64_t d, int64_t 
                                   double* mean_out, double* ws_sums, float* ws_max,
                                   double* ws_mean, hipStream_t s);
 
+// ------------------------------------------------------ grouped problems
+// Many independent problems in one call (k_group.hip): bf16 data with
+// d <= kGroupMaxD and K <= kGroupMaxK.  A problem belongs to the shape class
+// (dci, NB): dci picks the column split of the fused pass (class width dc =
+// 64, 128, 256, 512, 768), NB = Kp / 16.  Its rows are cut into work items;
+// the items of all problems are sorted by size and dealt round-robin to the
+// persistent workgroups of the fused pass.
+constexpr int kGroupMaxD = 768;
+constexpr int kGroupMaxK = 64;
+constexpr int kGroupClasses = 5;
+int group_class_width(int dci);          // dc of class dci
+int group_row_groups(int dci);           // row groups (waves sharing no rows) of class dci
+int group_dci(int64_t d);                // smallest class whose width holds d
+
+struct GProb {
+  const uint16_t* x;        // bf16 data [n][ld]
+  int64_t n, d, ld;
+  int32_t K, Kp, k, cls;    // cls = dci * 4 + NB - 1
+  int32_t dc, wr;           // class width, row groups of the class
+  int32_t nitem, pad;       // number of work items of the problem
+  int64_t zbase, gbase;     // float offsets of its item partials: item m of the problem
+                            // at zbase + m * wr * Kp * dc and gbase + m * 4 * Kp * Kp
+  float* V;                 // [d][K] f32 (caller)
+  double* G;                // [K][K] (caller, projection Gram)
+  double* B;                // [K][K] (caller)
+  float* E;                 // [d][k] (caller, may be null)
+  double* evals;            // [k] (caller)
+  uint16_t* vop;            // [Kp][dc] bf16 operand (workspace)
+  float* Z;                 // [d][K] (workspace)
+  double* q1;               // [d][K] (workspace)
+  double *A, *R, *Rinv, *H, *W, *ev;   // [K][K], ev [K] (workspace)
+};
+struct GItem {
+  int32_t prob, pad;
+  int64_t r0, rows;         // data rows [r0, r0 + rows) of the problem
+  int64_t zoff, goff;       // float offsets of the item's Z and G partials
+};
+
+hipError_t launch_group_pass(const GProb* probs, const GItem* items, int nitems, int grid,
+                             float* zpart, float* gpart, bool want_z, hipStream_t s);
+hipError_t launch_group_reduce(const GProb* probs, int nprob, const int* blk0, int nblk,
+                               const float* zpart, const float* gpart, bool want_z, int* status,
+                               hipStream_t s);
+hipError_t launch_group_cholqr2(const GProb* probs, int nprob, bool from_v, bool want_b,
+                                int* status, hipStream_t s);
+hipError_t launch_group_rr(const GProb* probs, int nprob, int max_sweeps, int* status,
+                           hipStream_t s);
+
 }  // namespace ppca

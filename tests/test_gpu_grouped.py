@@ -1,0 +1,201 @@
+"""GPU parity of the grouped path (many independent bf16 problems in one call)
+against the float64 oracle, problem by problem.
+
+Each problem follows the single-problem bf16 path: block power with the
+operand V' = bf16(V) in every pass and CholeskyQR2 in float64, then the
+projection Gram G of Y' = bf16(X V') and B = V'^T V', then Rayleigh-Ritz.
+Tolerances are those of the single-problem bf16 tests: V_t against the
+oracle's iteration 2e-2 (principal-angle sine), G 4e-3 of sqrt(G_ii G_jj),
+B 1e-12, pPCA eigenvalues 2e-3 (widened by the Weyl term of the measured
+Gram error on problems of a few dozen rows).  Rayleigh-Ritz from the GPU's own G and B
+matches the oracle's float64 Rayleigh-Ritz to 1e-9.  The Ritz vectors are
+held to the Davis-Kahan bound that the measured Gram error implies (at a few
+hundred rows the bf16 rounding of Y does not average out, so a flat 2e-3
+would not follow from the arithmetic at every shape).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ppca_oracle as O
+from synthdata import gaussian_block, make_problem
+
+from ._gpu_util import BF16, device_data, gram_err, operand_basis, sin_theta
+
+pytestmark = pytest.mark.gpu
+
+# (n, d, k, l, ld padding): every column class of the fused pass
+# (d in (0,64], (64,128], (128,256], (256,512], (512,768]) with K padded to
+# 16, 32, 48 and 64; ragged n, padded rows, d > n, l = 0; the three
+# largest have several work items each.
+SHAPES = [
+    (700, 64, 4, 4, 0), (37, 33, 3, 2, 8), (1500, 100, 12, 12, 0), (900, 128, 20, 20, 16),
+    (2500, 256, 8, 8, 0), (333, 200, 30, 30, 0), (1200, 512, 16, 16, 8), (800, 300, 24, 24, 0),
+    (1000, 768, 32, 32, 0), (640, 700, 5, 5, 24), (150, 600, 20, 20, 0), (3000, 48, 7, 0, 0),
+    (30011, 64, 8, 8, 0), (5003, 768, 16, 16, 0), (9001, 256, 32, 32, 0),
+]
+# enough iterations for the priming of every shape to contract (the
+# end-to-end 2e-3 bound compares two primings whose passes round differently)
+ITERS = 8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03709_amd as P
+    P.lib()
+    yield
+
+
+def P():
+    import paper_2109_03709_amd as mod
+    return mod
+
+
+def _make(i, shape):
+    n, d, k, l, pad = shape
+    mode = "exact" if n > d + 1 else "gaussian"
+    spec = "exp0.9" if i % 2 == 0 else "pow1.5"
+    prob = make_problem(n, d, spec, seed=500 + i, mode=mode)
+    data, xs, _ = device_data(prob.x, BF16, d + pad)
+    v0 = gaussian_block(d, k + l, 900 + i, np.float32)
+    return data, xs, v0
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return [_make(i, s) for i, s in enumerate(SHAPES)]
+
+
+def _run(cases, iters, graph=False):
+    probs = []
+    for (data, _, v0), (n, d, k, l, _) in zip(cases, SHAPES):
+        p = P().Problem(data, k, l, torch.from_numpy(v0.copy()).cuda()).alloc()
+        probs.append(p)
+    P().prime_power_grouped(probs, iters, graph=graph)
+    P().rayleigh_ritz_grouped(probs)
+    torch.cuda.synchronize()
+    return probs
+
+
+def test_grouped_power_projection_rr(cases):
+    probs = _run(cases, ITERS)
+    for (data, xs, v0), (n, d, k, l, _), p in zip(cases, SHAPES, probs):
+        K = k + l
+        tag = f"n={n} d={d} k={k} l={l}"
+        v_gpu = p.V.cpu().numpy().astype(np.float64)
+        # the oracle's iteration on the stored data, operand rebuilt every pass
+        v = O.cholqr2(v0.astype(np.float64))[0]
+        for _ in range(ITERS):
+            z, _ = O.stream_pass(xs, operand_basis(v.astype(np.float32), BF16, None))
+            v = O.cholqr2(z)[0]
+        s_v = sin_theta(v_gpu, v)
+        assert np.linalg.norm(v_gpu.T @ v_gpu - np.eye(K)) < 1e-5 * K, tag
+        # two iterations that round differently drift apart along the
+        # directions that have not converged: the trajectories are compared
+        # where the data's K-th gap determines the subspace (one-step parity
+        # on every shape is test_grouped_one_step)
+        lam = np.sort(np.linalg.eigvalsh(xs.T @ xs))[::-1]
+        if K < d and lam[K] < 0.8 * lam[K - 1]:
+            assert s_v < 2e-2, tag
+        # projection Gram of the GPU's own primed V
+        veff = operand_basis(p.V.cpu().numpy(), BF16, None)
+        g_ref, b_ref = O.project_gram(xs, veff)
+        G, B = p.G.cpu().numpy(), p.B.cpu().numpy()
+        assert np.array_equal(G, G.T), tag
+        assert gram_err(G, g_ref) < 4e-3, tag
+        assert np.allclose(B, b_ref, rtol=1e-12, atol=1e-12 * np.abs(b_ref).max()), tag
+        # Rayleigh-Ritz of the GPU's G and B
+        th, e_or, _ = O.rayleigh_ritz(G, B, veff, n, k)
+        ev, E = p.evals.cpu().numpy(), p.E.cpu().numpy().astype(np.float64)
+        assert np.max(O.rel_eig_error(ev, th)) < 1e-9, tag
+        assert sin_theta(E, e_or) < 1e-6, tag
+        # signs: the largest-magnitude entry of every column is positive
+        idx = np.argmax(np.abs(E), axis=0)
+        assert np.all(E[idx, np.arange(k)] > 0), tag
+        # Ritz vectors against the exact Rayleigh-Ritz of the same V: the bf16
+        # rounding of Y moves G by dG = G - G_exact, hence H by
+        # dH = R^-T dG R^-1 / n, and the Ritz subspace by at most
+        # ||dH||_2 / (theta_k - theta_{k+1}) (Davis-Kahan)
+        th_ex, e_ex, th_all = O.rayleigh_ritz(g_ref, b_ref, veff, n, k)
+        ri = np.linalg.inv(O.cholesky_upper(b_ref))
+        dh = np.linalg.norm(ri.T @ (G - g_ref) @ ri / n, 2)
+        bound = dh / (th_all[k - 1] - th_all[k]) if k < K else 0.0
+        s_ex = sin_theta(E, e_ex)
+        assert s_ex <= 1.01 * bound + 1e-5, tag
+        assert np.max(np.abs(ev - th_ex)) <= 1.01 * dh + 1e-12 * th_ex[0], tag   # Weyl
+        # end to end against the oracle's pPCA of its own primed V
+        th_or, e_pp = O.ppca(xs, v, k)
+        r_ev = np.max(O.rel_eig_error(ev, th_or))
+        print(f"{tag}: sin(V_t) {s_v:.1e}  G {gram_err(G, g_ref):.1e}  pPCA eig {r_ev:.1e}"
+              f"  sin(E, exact RR) {s_ex:.1e} (bound {bound:.1e})"
+              f"  sin(E, oracle pPCA) {sin_theta(E, e_pp):.1e}")
+        # 2e-3, plus what the Gram rounding (Weyl: ||dH||) and the priming
+        # difference (Ritz values move with sin^2 of the subspace angle) allow
+        tol = 2e-3 + 1.01 * dh / th_ex[k - 1] + 2.0 * (th_ex[0] / th_ex[k - 1]) * s_v ** 2
+        assert r_ev < tol, tag
+
+
+def test_grouped_one_step(cases):
+    """iters = 1 from the same V0: V_1 = CholQR2(X^T bf16(X V_0')) against the
+    oracle's step on every shape."""
+    probs = _run(cases, 1)
+    for (data, xs, v0), (n, d, k, l, _), p in zip(cases, SHAPES, probs):
+        v = O.cholqr2(v0.astype(np.float64))[0]
+        z, _ = O.stream_pass(xs, operand_basis(v.astype(np.float32), BF16, None))
+        v1 = O.cholqr2(z)[0]
+        s1 = sin_theta(p.V.cpu().numpy(), v1)
+        assert s1 < 2e-2, f"n={n} d={d} k={k} l={l}: {s1:.2e}"
+
+
+def test_grouped_graph_matches_eager_and_is_deterministic(cases):
+    a = _run(cases, ITERS)
+    b = _run(cases, ITERS)
+    side = torch.cuda.Stream()          # capture needs a stream other than the NULL stream
+    with torch.cuda.stream(side):
+        c = _run(cases, ITERS, graph=True)
+    side.synchronize()
+    # the NULL stream cannot be captured
+    with pytest.raises(P().PPCAError) as e:
+        _run(cases[:1], ITERS, graph=True)
+    assert e.value.code == -1
+    for pa, pb, pc in zip(a, b, c):
+        for name in ("V", "G", "B", "evals", "E"):
+            ta, tb, tc = (getattr(q, name).cpu() for q in (pa, pb, pc))
+            assert torch.equal(ta, tb), name
+            assert torch.equal(ta, tc), name
+
+
+def test_grouped_zero_iterations_is_projection_of_orthonormal_start(cases):
+    """iters = 0: V = CholQR2(V0) and G, B of that V."""
+    data, xs, v0 = cases[4]
+    n, d, k, l, _ = SHAPES[4]
+    p = P().Problem(data, k, l, torch.from_numpy(v0.copy()).cuda()).alloc()
+    P().prime_power_grouped([p], 0)
+    torch.cuda.synchronize()
+    v = O.cholqr2(v0.astype(np.float64))[0]
+    assert sin_theta(p.V.cpu().numpy(), v) < 1e-5
+    veff = operand_basis(p.V.cpu().numpy(), BF16, None)
+    g_ref, _ = O.project_gram(xs, veff)
+    assert gram_err(p.G.cpu().numpy(), g_ref) < 4e-3
+
+
+def test_grouped_argument_errors(cases):
+    data, _, v0 = cases[0]
+    n, d, k, l, _ = SHAPES[0]
+    good = P().Problem(data, k, l, torch.from_numpy(v0.copy()).cuda()).alloc()
+    # K above the grouped limit
+    with pytest.raises(P().PPCAError) as e:
+        P().prime_power_grouped([good, P().Problem(data, 60, 5, torch.zeros((d, 65)).cuda())], 1)
+    assert e.value.code == -1
+    # float32 data is not accepted by the grouped path
+    x32 = P().Data(torch.zeros((n, d), dtype=torch.float32).cuda(), P().F32)
+    with pytest.raises(P().PPCAError) as e:
+        P().prime_power_grouped([P().Problem(x32, k, l, torch.zeros((d, k + l)).cuda())], 1)
+    assert e.value.code == -2
+    # workspace too small
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P().PPCAError) as e:
+        P().prime_power_grouped([good], 1, ws=ws)
+    assert e.value.code == -6
