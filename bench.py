@@ -14,6 +14,9 @@ Prints one JSON line:
                k is <= 1e-3: primed bf16 (power + pPCA step) vs plain float32
                power iteration (K = k, Rayleigh quotients) on the same data
   cpu_baseline the float64 oracle on a bounded row sample, on the host cores
+
+--workload oja-f32 / eigengame-fp8 / grouped-bf16 print the same line for the
+minibatch primings and for 512 independent problems solved together.
 """
 from __future__ import annotations
 
@@ -56,10 +59,11 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=500000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8"],
+    ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8", "grouped-bf16"],
                     default="power-bf16",
                     help="power-bf16: the headline block-power workload (default); oja-f32 / "
-                         "eigengame-fp8: the minibatch primings at their configuration shapes")
+                         "eigengame-fp8: the minibatch primings at their configuration shapes; "
+                         "grouped-bf16: 512 independent problems solved together")
     return ap.parse_args()
 
 
@@ -68,6 +72,8 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if a.workload == "grouped-bf16":
+        return main_grouped(a)
     if a.workload != "power-bf16":
         return main_minibatch(a)
     import torch
@@ -458,6 +464,181 @@ def cpu_baseline_minibatch(X, k, l, c, v0, es, oja):
             "us_per_minibatch_step": round(dt * 1e6 / tsteps, 1),
             "sample": f"{tsteps} minibatch steps of {b} rows (the first {rows} stored rows), "
                       f"float64 numpy; GB/s counts 2 reads of the minibatch per step"}
+
+
+# Grouped problems: 512 independent problems with n ~ LogUniform[2000, 200000],
+# d uniform over {64, 128, 256, 512, 768}, k uniform over 4..32, l = k;
+# spectra alternate between 0.9^i (even problems) and i^-1.5 (odd problems);
+# bf16 storage.  One step = 12 block-power iterations of every problem (one
+# fused pass over its X each) + the projection pass + Rayleigh-Ritz.
+GROUPED = dict(nprob=512, nmin=2000, nmax=200000, dset=(64, 128, 256, 512, 768), kmin=4,
+               kmax=32, iters=12, shape_seed=5, data_seed=50000, v0_seed=60000)
+
+
+def grouped_shapes(c):
+    rng = np.random.Generator(np.random.PCG64(c["shape_seed"]))
+    out = []
+    for p in range(c["nprob"]):
+        n = int(round(math.exp(rng.uniform(math.log(c["nmin"]), math.log(c["nmax"])))))
+        d = int(rng.choice(c["dset"]))
+        k = int(rng.integers(c["kmin"], c["kmax"] + 1))
+        out.append((n, d, k, k, "exp0.9" if p % 2 == 0 else "pow1.5"))
+    return out
+
+
+def main_grouped(a):
+    import torch
+    import paper_2109_03709_amd as P
+    from synthdata import gaussian_block, make_problem_device
+
+    c = GROUPED
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shapes = grouped_shapes(c)
+    iters = c["iters"]
+    log(f"generating {len(shapes)} problems")
+    t0 = time.perf_counter()
+    data, refs, v0s = [], [], []
+    for p, (n, d, k, l, spec) in enumerate(shapes):
+        xraw, lam, q = make_problem_device(n, d, spec, c["data_seed"] + p, device=dev)
+        X, _ = P.center_quantize(xraw, P.BF16)
+        del xraw
+        data.append(X)
+        refs.append((lam[:k].copy(), q[:, :k].copy()))
+        v0s.append(gaussian_block(d, k + l, c["v0_seed"] + p, np.float32))
+        if p % 64 == 63:
+            log(f"  {p + 1} problems ({time.perf_counter() - t0:.0f}s)")
+    torch.cuda.synchronize()
+    # all V in one buffer, so that a step restores them with one copy
+    sizes = [v.size for v in v0s]
+    vbuf0 = torch.from_numpy(np.concatenate([v.reshape(-1) for v in v0s])).to(dev)
+    vbuf = torch.empty_like(vbuf0)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    probs = []
+    for p, (n, d, k, l, _) in enumerate(shapes):
+        V = vbuf[offs[p]:offs[p + 1]].view(d, k + l)
+        probs.append(P.Problem(data[p], k, l, V).alloc())
+    group = P.Group(probs)
+    ws = group.workspace()
+    xbytes = sum(n * d * 2 for (n, d, _, _, _) in shapes)
+    log(f"{xbytes / 1e9:.2f} GB of bf16 data, workspace {group.ws_bytes / 1e6:.0f} MB")
+
+    def step(graph=False):
+        vbuf.copy_(vbuf0)
+        P.prime_power_grouped(group, iters, graph=graph, ws=ws)
+        P.rayleigh_ritz_grouped(group, ws=ws)
+
+    for _ in range(max(a.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    reps = max(1, a.steps)
+    P.set_kernel_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    launches, kms = P.kernel_stats(2)
+    P.set_kernel_timing(False)
+    # the HIP-graph variant (iterations replayed from one capture) on a side stream
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        step(graph=True)
+        side.synchronize()
+        tg = time.perf_counter()
+        for _ in range(reps):
+            step(graph=True)
+        side.synchronize()
+    dtg = (time.perf_counter() - tg) / reps
+
+    passes = iters + 1
+    value = passes * xbytes / dt / 1e9
+    # accuracy of every problem against the exact spectrum of its data
+    rel, sin_t = [], []
+    for pr, (lam_k, q_k) in zip(probs, refs):
+        ev = pr.evals.cpu().numpy()
+        rel.append(float(np.max(np.abs(ev - lam_k) / lam_k)))
+        qe = np.linalg.qr(pr.E.cpu().numpy().astype(np.float64))[0]
+        sin_t.append(float(np.linalg.norm(qe - q_k @ (q_k.T @ qe), 2)))
+    # roofline of the fused pass: algorithmic bytes = X once per launch (V',
+    # Z and G partials are < 6 % on top and left out)
+    avg_ms = kms / max(launches, 1)
+    achieved = xbytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_group_traffic(xbytes),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "kernel": "k_gpass (fused grouped pass)", "avg_ms": round(avg_ms, 4),
+                "alg_bytes_per_launch": xbytes, "launches": launches}
+    dims = np.array([(n, d, k) for (n, d, k, _, _) in shapes])
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": reps, "warmup": max(a.warmup, 1), "ms_per_step": round(dt * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "grouped-bf16", "problems": len(shapes),
+                      "n": [int(dims[:, 0].min()), int(dims[:, 0].max())],
+                      "d": sorted(set(int(x) for x in dims[:, 1])),
+                      "k": [int(dims[:, 2].min()), int(dims[:, 2].max())], "l": "k",
+                      "power_iters": iters, "x_gbytes": round(xbytes / 1e9, 3),
+                      "x_reads_per_step": passes},
+           "graph_ms_per_step": round(dtg * 1e3, 3),
+           "accuracy": {"max_rel_eig_err": max(rel), "median_rel_eig_err": float(np.median(rel)),
+                        "sin_theta_max": max(sin_t), "median_sin_theta": float(np.median(sin_t))},
+           "roofline": roofline}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_grouped(data, shapes, v0s, iters)
+    print(json.dumps(out), flush=True)
+
+
+GROUP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_group_pass_bf16_512problems.txt")
+
+
+def measured_group_traffic(xbytes):
+    """HBM bytes per launch of the fused grouped pass from the committed
+    rocprofv3 counter summary, or None when k_group.hip has changed since."""
+    import hashlib
+    if not os.path.exists(GROUP_TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(GROUP_TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            key, val = line.split("=", 1)
+            kv[key.strip()] = val.strip()
+    src = os.path.join(ROOT, "paper_2109_03709_amd", "csrc", "k_group.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha1") != sha or int(kv.get("x_bytes", "0")) != xbytes:
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def cpu_baseline_grouped(data, shapes, v0s, iters, budget_s=12.0):
+    """The float64 oracle (as it stands) on the problems in order until about
+    budget_s seconds of host work: the same iterations, projection and
+    Rayleigh-Ritz per problem."""
+    import torch
+    from oracle import ppca_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() \
+            else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    done, nbytes, spent = 0, 0, 0.0
+    for X, (n, d, k, l, _), v0 in zip(data, shapes, v0s):
+        xs = O.bf16_value(X.x.contiguous().view(torch.int16).cpu().numpy().view(np.uint16))
+        t0 = time.perf_counter()
+        v, _ = O.prime_power(xs, v0.astype(np.float64), iters)
+        O.ppca(xs, v, k)
+        spent += time.perf_counter() - t0
+        done += 1
+        nbytes += (iters + 1) * n * d * 2
+        if spent >= budget_s:
+            break
+    return {"value": round(nbytes / spent / 1e9, 4), "unit": "GB/s", "cores": cores,
+            "kind": "oracle", "seconds": round(spent, 2),
+            "sample": f"the first {done} of the {len(shapes)} problems, each with {iters} power "
+                      f"iterations + projection + Rayleigh-Ritz in float64 numpy; GB/s counts "
+                      f"one read of the 2-byte stored data per pass, like the GPU value"}
 
 
 if __name__ == "__main__":

@@ -340,6 +340,24 @@ def _problem_array(problems):
     return arr
 
 
+class Group:
+    """A fixed list of problems with its C descriptor array built once (the
+    tensors behind it must stay alive and in place)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.arr = _problem_array(self.problems)
+        # 0 for invalid problems: the calls then report the precise status
+        self.ws_bytes = int(lib().ppca_grouped_workspace_bytes(self.arr, len(self.problems)))
+
+    def workspace(self):
+        return _workspace(self.ws_bytes, self.problems[0].V.device)
+
+
+def _group(problems) -> Group:
+    return problems if isinstance(problems, Group) else Group(problems)
+
+
 def grouped_workspace_bytes(problems) -> int:
     arr = _problem_array(problems)
     return int(lib().ppca_grouped_workspace_bytes(arr, len(problems)))
@@ -347,23 +365,24 @@ def grouped_workspace_bytes(problems) -> int:
 
 def prime_power_grouped(problems, iters: int, graph: bool = False, ws=None):
     """Block power priming of every problem, then the projection Gram G and
-    B of the primed V (one fused pass over X per iteration for all problems)."""
-    arr = _problem_array(problems)
+    B of the primed V (one fused pass over X per iteration for all problems).
+    problems: a list of Problem or a Group."""
+    g = _group(problems)
     if ws is None:
-        ws = _workspace(int(lib().ppca_grouped_workspace_bytes(arr, len(problems))),
-                        problems[0].V.device)
-    code = lib().ppca_prime_power_grouped(arr, len(problems), iters, GROUP_GRAPH if graph else 0,
-                                          _ptr(ws), ws.numel(), _stream())
+        ws = g.workspace()
+    code = lib().ppca_prime_power_grouped(g.arr, len(g.problems), iters,
+                                          GROUP_GRAPH if graph else 0, _ptr(ws), ws.numel(),
+                                          _stream())
     _check(code, "ppca_prime_power_grouped")
-    return problems
+    return g.problems
 
 
 def rayleigh_ritz_grouped(problems, ws=None):
     """Rayleigh-Ritz of every problem from its G, B and V: evals and E."""
-    arr = _problem_array(problems)
+    g = _group(problems)
     if ws is None:
-        ws = _workspace(int(lib().ppca_grouped_workspace_bytes(arr, len(problems))),
-                        problems[0].V.device)
-    code = lib().ppca_rayleigh_ritz_grouped(arr, len(problems), _ptr(ws), ws.numel(), _stream())
+        ws = g.workspace()
+    code = lib().ppca_rayleigh_ritz_grouped(g.arr, len(g.problems), _ptr(ws), ws.numel(),
+                                            _stream())
     _check(code, "ppca_rayleigh_ritz_grouped")
-    return problems
+    return g.problems

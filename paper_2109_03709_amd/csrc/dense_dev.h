@@ -255,12 +255,12 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-template <int KM>
+template <int KM, int JR = kJacRows>
 __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* __restrict__ Ws,
                                   double* __restrict__ evals, int max_sweeps, int* status,
                                   int rowblk) {
   __shared__ double A[KM * (KM + 1)];   // row stride kpad + 1: column accesses spread banks
-  __shared__ double Wl[kJacRows * KM];
+  __shared__ double Wl[JR * KM];
   __shared__ double cs[KM / 2], sn[KM / 2];
   __shared__ int pp[KM / 2], qq[KM / 2];
   __shared__ double red[16];
@@ -275,7 +275,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
   const int kpad = K + (K & 1);     // index K is a dummy when K is odd
   const int npair = kpad / 2;
   const int la = kpad + 1;          // LDS row stride of A
-  const int row0 = rowblk * kJacRows;
+  const int row0 = rowblk * JR;
   // H in batches of 8 elements per thread (all loads in flight before use)
   for (int e0 = tid; e0 < kpad * kpad; e0 += 8 * 1024) {
     double hv[8];
@@ -291,7 +291,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
       if (e < kpad * kpad) A[(e / kpad) * la + (e % kpad)] = hv[u];
     }
   }
-  for (int e = tid; e < kJacRows * kpad; e += blockDim.x) {
+  for (int e = tid; e < JR * kpad; e += blockDim.x) {
     const int r = e / kpad, j = e % kpad;
     Wl[e] = (row0 + r == j) ? 1.0 : 0.0;
   }
@@ -362,7 +362,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
         }
       }
       // W rows of this workgroup: thread t takes row t/64 and pair t%64
-      for (int lr = tid >> 6; lr < kJacRows; lr += 16) {
+      for (int lr = tid >> 6; lr < JR; lr += 16) {
         for (int i = tid & 63; i < npair; i += 64) {
           const double s = sn[i];
           if (s == 0.0) continue;
@@ -402,7 +402,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
     if (rowblk == 0) evals[rk] = ti;
   }
   __syncthreads();
-  for (int e = tid; e < kJacRows * K; e += blockDim.x) {
+  for (int e = tid; e < JR * K; e += blockDim.x) {
     const int lr = e / K, i = e % K;
     if (row0 + lr < K) Ws[(row0 + lr) * K + rank_of[i]] = Wl[lr * kpad + i];
   }

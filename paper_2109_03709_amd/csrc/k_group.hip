@@ -8,9 +8,11 @@
 //               waves of a workgroup split the columns of a 16-row tile, each
 //               wave's slice of X is staged in its own LDS buffers by DMA and
 //               used for both products, and the partial Y of the waves is
-//               summed through LDS (one barrier per tile).
+//               summed through LDS.  Tiles go in pairs so that the second
+//               product runs on 16x16x32 MFMAs (k = the pair's 32 rows).
 //   k_greduce   fixed-order float64 sums of the item partials -> Z (f32), G (f64)
-//   k_gcholqr2  CholeskyQR2 per problem (one workgroup): new V, its bf16
+//   k_gcholqr2  CholeskyQR2 per problem (one workgroup, largest problems
+//               launched first): new V, its bf16
 //               operand, and B = V'^T V' after the last step
 //   k_grr_h / k_grr_jacobi / k_grr_e
 //               Rayleigh-Ritz per problem (Alg. 1 step 4): R = chol(B),
@@ -64,28 +66,25 @@ struct GCls {
   static constexpr int DPS = XSB / 1024;                         // DMAs per stage
   static constexpr int NBT = NB * (NB + 1) / 2;                  // upper blocks of G
   static constexpr int NGS = (NBT + WD - 1) / WD;                // G blocks per wave
+  // X stages per wave: the same LDS for every class (24 KB per wave), so that
+  // the narrow classes keep as many bytes in flight as the wide ones
+  static constexpr int S = 4 * 16 * 192 * 2 / XSB;               // 12, 6 or 4
+  static_assert((S - 1) * DPS < 64 && S >= 4 && S % 2 == 0, "stage ring");
+  // sub-tiles in pairs (second products on 16x16x32 MFMAs), except for the
+  // widest class at K > 48 (see run_item)
+  static constexpr bool ZPAIR = !(DCI == 4 && NB == 4);
 };
 
-constexpr int kGS = 4;                    // X stages per wave
+constexpr int kGS = 4;                    // X stages per wave at the widest class
 constexpr int kGStage = 16 * 192 * 2;     // bytes of one stage at the widest class
-constexpr int kGExch = 2 * 4 * 4 * 64;    // exchange slots [parity][wave][nb][lane]
-
-__device__ inline short4_t pack_bf16(float v0, float v1, float v2, float v3) {
-  return short4_t{(short)f32_to_bf16_bits(v0), (short)f32_to_bf16_bits(v1),
-                  (short)f32_to_bf16_bits(v2), (short)f32_to_bf16_bits(v3)};
-}
-
-__device__ inline short4_t as_s4(uint32_t lo, uint32_t hi) {
-  return __builtin_bit_cast(short4_t, make_uint2(lo, hi));
-}
+constexpr int kGExch = 4 * 2 * 4 * 64;    // exchange slots [wave][sub-tile][nb][lane]
 
 // One work item (rows [r0, r0 + rows) of one problem) of class (NB, DCI).
 // Sub-tile t of row group rg covers item rows (t * WR + rg) * 16 .. + 15.
 template <int NB, int DCI, bool WZ>
 __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, const GItem& I,
                                                                uint8_t* xl, f32x4_t* ex,
-                                                               float* zpart, float* gpart,
-                                                               int& phase) {
+                                                               float* zpart, float* gpart) {
   using C = GCls<NB, DCI>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -124,7 +123,7 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
   auto issue = [&](int64_t t, int b) __attribute__((always_inline)) {
     const int64_t tc = t < nsub ? t : nsub - 1;
     const int64_t lb = (tc * C::WR + rg) * 16;
-    uint8_t* dst = st + b * kGStage;
+    uint8_t* dst = st + b * C::XSB;
 #pragma unroll
     for (int j = 0; j < C::DPS; ++j) {
       int64_t li = lb + drow[j];
@@ -134,6 +133,7 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
   };
 
   // Z accumulators (Z pass) or G accumulators (G pass)
+  const f32x4_t z4 = f32x4_t{0.f, 0.f, 0.f, 0.f};
   constexpr int NZ = WZ ? C::CW : 0, NG = WZ ? 0 : C::NGS;
   f32x4_t zacc[NZ > 0 ? NZ : 1][4][NB];
   f32x4_t gacc[NG > 0 ? NG : 1];
@@ -142,65 +142,110 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = z4;
 #pragma unroll
-  for (int i = 0; i < NG; ++i) gacc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < NG; ++i) gacc[i] = z4;
 
   wait_vmcnt<0>();   // the operand fragments have landed before the DMA stream starts
   wait_lgkm0();      // LDS reads of the previous item are done before its stages refill
-  issue(0, 0);
-  issue(1, 1);
-  issue(2, 2);
-  for (int64_t t = 0; t < nsub; ++t) {
-    wait_vmcnt<2 * C::DPS>();   // this wave's stage t has landed
-    wait_lgkm0();               // ... and stage t - 1 has been read
-    issue(t + 3, (int)((t + 3) & 3));
-    const uint8_t* xs = st + (int)(t & 3) * kGStage;
-
-    // partial Y of the slice: rows a, k-chunk 4 s + g (16 bytes, row-major)
-    f32x4_t ya[NB];
+  // H sub-tiles per iteration.  With H = 2 the second products run on
+  // 16x16x32 MFMAs whose 32 k-slots are the pair's rows: k = 8 g + e is row
+  // 4 g + e of the first sub-tile (e < 4) or row 4 g + e - 4 of the second,
+  // which is how the Y MFMA outputs already sit in the lanes.  With H = 1
+  // (the widest class at K > 48, whose 192 Z accumulators and 96 operand
+  // registers leave no room for a pair) they run on 16x16x16 MFMAs, k = rows
+  // 4 g .. 4 g + 3.  S - H sub-tiles are in flight ahead of the ones used.
+  constexpr int H = C::ZPAIR ? 2 : 1;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) ya[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < C::S - H; ++b) issue(b, b);
+  const int64_t nit = (nsub + H - 1) / H;
+  int bcur = 0;                 // stage of sub-tile H p
+  for (int64_t p = 0; p < nit; ++p) {
+    wait_vmcnt<(C::S - 2 * H) * C::DPS>();   // the H sub-tiles of step p have landed
+    wait_lgkm0();                            // ... and those of step p - 1 have been read
 #pragma unroll
-    for (int s = 0; s < 2 * C::CW; ++s) {
-      const uint4 av =
-          *reinterpret_cast<const uint4*>(xs + (a * C::CPR + ((4 * s + g) ^ (a & 7))) * 16);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        ya[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
-                                                         ya[nb], 0, 0, 0);
+    for (int h = 0; h < H; ++h) {
+      const int bb = bcur - H + h;
+      issue(H * p + C::S - H + h, bb >= 0 ? bb : bb + C::S);
     }
-    // sum over the waves of the row group, in wave order (lane layout of the
-    // MFMA output: rows 4 g .. 4 g + 3 of column a)
-    if constexpr (C::WD > 1) {
-      const int par = phase & 1;
-      ++phase;
-      f32x4_t* mine = ex + (par * 4 + wave) * NB * 64 + lane;
+    const uint8_t* xs[H];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) mine[nb * 64] = ya[nb];
+    for (int h = 0; h < H; ++h) xs[h] = st + (bcur + h) * C::XSB;
+    bcur = bcur + H == C::S ? 0 : bcur + H;
+
+    // partial Y of the slice (rows a, k-chunk 4 s + g) of sub-tile h
+    auto ypart = [&](int h, f32x4_t (&yh)[NB]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) yh[nb] = z4;
+#pragma unroll
+      for (int s = 0; s < 2 * C::CW; ++s) {
+        const uint4 av =
+            *reinterpret_cast<const uint4*>(xs[h] + (a * C::CPR + ((4 * s + g) ^ (a & 7))) * 16);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          yh[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
+                                                           yh[nb], 0, 0, 0);
+      }
+    };
+    // Y' = bf16(Y) of sub-tile h into the k-slot words 2 h, 2 h + 1 of column
+    // block nb (rows past the item zeroed)
+    uint32_t ybw[NB][2 * H];
+    auto ypack = [&](int h, int nb, f32x4_t y) __attribute__((always_inline)) {
+      const int64_t vr = rows - ((H * p + h) * C::WR + rg) * 16;
+      const float y0 = (4 * g + 0 < vr) ? y[0] : 0.f;
+      const float y1 = (4 * g + 1 < vr) ? y[1] : 0.f;
+      const float y2 = (4 * g + 2 < vr) ? y[2] : 0.f;
+      const float y3 = (4 * g + 3 < vr) ? y[3] : 0.f;
+      ybw[nb][2 * h] = f32_to_bf16_bits(y0) | (f32_to_bf16_bits(y1) << 16);
+      ybw[nb][2 * h + 1] = f32_to_bf16_bits(y2) | (f32_to_bf16_bits(y3) << 16);
+    };
+    if constexpr (C::WD > 1) {
+      // sum over the waves of the row group, in wave order (lane layout of
+      // the MFMA output: rows 4 g .. 4 g + 3 of column a); the first barrier
+      // makes sure the previous step's sums have been read
+      f32x4_t* mine = ex + wave * 2 * NB * 64 + lane;
+      raw_barrier();
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        f32x4_t yh[NB];
+        ypart(h, yh);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) mine[(h * NB + nb) * 64] = yh[nb];
+      }
       wait_lgkm0();
       raw_barrier();
-      const f32x4_t* src = ex + (par * 4 + rg * C::WD) * NB * 64 + lane;
+      const f32x4_t* src = ex + rg * C::WD * 2 * NB * 64 + lane;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        f32x4_t y = src[nb * 64];
+      for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int j = 1; j < C::WD; ++j) y += src[(j * NB + nb) * 64];
-        ya[nb] = y;
+        for (int nb = 0; nb < NB; ++nb) {
+          f32x4_t y = src[(h * NB + nb) * 64];
+#pragma unroll
+          for (int j = 1; j < C::WD; ++j) y += src[((j * 2 + h) * NB + nb) * 64];
+          ypack(h, nb, y);
+        }
+    } else {
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        f32x4_t yh[NB];
+        ypart(h, yh);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) ypack(h, nb, yh[nb]);
       }
     }
-    // Y' = bf16(Y), rows past the item zeroed; the fragment is at once the
-    // B operand (rows 4 g .., column a) of both products below
-    const int64_t vr = rows - (t * C::WR + rg) * 16;
-    short4_t yf[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const float y0 = (4 * g + 0 < vr) ? ya[nb][0] : 0.f;
-      const float y1 = (4 * g + 1 < vr) ? ya[nb][1] : 0.f;
-      const float y2 = (4 * g + 2 < vr) ? ya[nb][2] : 0.f;
-      const float y3 = (4 * g + 3 < vr) ? ya[nb][3] : 0.f;
-      yf[nb] = pack_bf16(y0, y1, y2, y3);
-    }
+    // the B operand (k-slots of the step, column a) of both products below
+    auto bop = [&](int nb) __attribute__((always_inline)) {
+      if constexpr (H == 2)
+        return as_bf16x8(make_uint4(ybw[nb][0], ybw[nb][1], ybw[nb][2], ybw[nb][H == 2 ? 3 : 0]));
+      else
+        return __builtin_bit_cast(short4_t, make_uint2(ybw[nb][0], ybw[nb][1]));
+    };
+    auto mfma = [&](auto av, auto bv, f32x4_t acc) __attribute__((always_inline)) {
+      if constexpr (H == 2)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      else
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    };
     // G += Y'^T Y' on the upper blocks (mb <= nb), dealt over the row group's waves
     if constexpr (!WZ)
 #pragma unroll
@@ -208,35 +253,46 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
 #pragma unroll
       for (int nb = mb; nb < NB; ++nb) {
         const int idx = mb * NB - mb * (mb - 1) / 2 + (nb - mb);
-        if (idx % C::WD == wd)
-          gacc[idx / C::WD] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yf[mb], yf[nb],
-                                                                         gacc[idx / C::WD], 0, 0, 0);
+        if (idx % C::WD == wd) gacc[idx / C::WD] = mfma(bop(mb), bop(nb), gacc[idx / C::WD]);
       }
     // Z += X^T Y': column group q, lane (a, g) reads 4 columns (4 a ..) of rows
-    // 4 g .. 4 g + 3 and transposes them into 4 A fragments (column 4 a + v)
+    // 4 g .. 4 g + 3 of the step's sub-tiles and transposes them into 4 A
+    // fragments (column 4 a + v, the step's k-slots)
     if constexpr (WZ) {
 #pragma unroll
       for (int q = 0; q < C::CW; ++q) {
-        uint2 in[4];
+        uint2 in[H][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 4 * g + i, ch = 8 * q + (a >> 1);
-          in[i] = *reinterpret_cast<const uint2*>(xs + (row * C::CPR + (ch ^ (row & 7))) * 16 +
-                                                  (a & 1) * 8);
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 4 * g + i, ch = 8 * q + (a >> 1);
+            in[h][i] = *reinterpret_cast<const uint2*>(
+                xs[h] + (row * C::CPR + (ch ^ (row & 7))) * 16 + (a & 1) * 8);
+          }
+        uint32_t w[4][2 * H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          w[0][2 * h] = (in[h][0].x & 0xFFFFu) | (in[h][1].x << 16);
+          w[0][2 * h + 1] = (in[h][2].x & 0xFFFFu) | (in[h][3].x << 16);
+          w[1][2 * h] = (in[h][0].x >> 16) | (in[h][1].x & 0xFFFF0000u);
+          w[1][2 * h + 1] = (in[h][2].x >> 16) | (in[h][3].x & 0xFFFF0000u);
+          w[2][2 * h] = (in[h][0].y & 0xFFFFu) | (in[h][1].y << 16);
+          w[2][2 * h + 1] = (in[h][2].y & 0xFFFFu) | (in[h][3].y << 16);
+          w[3][2 * h] = (in[h][0].y >> 16) | (in[h][1].y & 0xFFFF0000u);
+          w[3][2 * h + 1] = (in[h][2].y >> 16) | (in[h][3].y & 0xFFFF0000u);
         }
-        short4_t af[4];
-        af[0] = as_s4((in[0].x & 0xFFFFu) | (in[1].x << 16), (in[2].x & 0xFFFFu) | (in[3].x << 16));
-        af[1] = as_s4((in[0].x >> 16) | (in[1].x & 0xFFFF0000u),
-                      (in[2].x >> 16) | (in[3].x & 0xFFFF0000u));
-        af[2] = as_s4((in[0].y & 0xFFFFu) | (in[1].y << 16), (in[2].y & 0xFFFFu) | (in[3].y << 16));
-        af[3] = as_s4((in[0].y >> 16) | (in[1].y & 0xFFFF0000u),
-                      (in[2].y >> 16) | (in[3].y & 0xFFFF0000u));
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v) {
+          auto av = [&] {
+            if constexpr (H == 2)
+              return as_bf16x8(make_uint4(w[v][0], w[v][1], w[v][2], w[v][H == 2 ? 3 : 0]));
+            else
+              return __builtin_bit_cast(short4_t, make_uint2(w[v][0], w[v][1]));
+          }();
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            zacc[q][v][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[v], yf[nb],
-                                                                        zacc[q][v][nb], 0, 0, 0);
+          for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = mfma(av, bop(nb), zacc[q][v][nb]);
+        }
       }
     }
   }
@@ -283,13 +339,12 @@ __global__ __launch_bounds__(256, 1) void k_gpass(const GProb* __restrict__ prob
                                                   float* zpart, float* gpart) {
   __shared__ __attribute__((aligned(16))) uint8_t xl[4 * kGS * kGStage];
   __shared__ f32x4_t ex[kGExch];
-  int phase = 0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem I = items[it];
     const GProb& P = probs[I.prob];
 #define PPCA_GCASE(nb, dci)                                              \
   case (dci) * 4 + (nb) - 1:                                             \
-    run_item<nb, dci, WZ>(P, I, xl, ex, zpart, gpart, phase);            \
+    run_item<nb, dci, WZ>(P, I, xl, ex, zpart, gpart);                   \
     break;
     switch (P.cls) {
       PPCA_GCASE(1, 0) PPCA_GCASE(2, 0) PPCA_GCASE(3, 0) PPCA_GCASE(4, 0)
@@ -374,12 +429,32 @@ __global__ __launch_bounds__(256) void k_greduce(const GProb* __restrict__ probs
 // ---------------------------------------------------------------------------
 // One-workgroup dense float64 helpers (256 threads, K <= 64).
 // ---------------------------------------------------------------------------
-constexpr int kGStg = 16;   // rows staged per step
+constexpr int kGStg = 64;   // rows staged per step
+
+// 64 x 64 stage of a rows x K block (zero outside): thread t holds elements
+// t + 256 m (row e >> 6, column e & 63).  Loads use clamped indices and no
+// branch, so that all 16 are in flight together.
+template <typename Load>
+__device__ inline void stage_load(Load load, int64_t r0, int64_t rows, int K, double (&reg)[16]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int e = t + 256 * m, rr = e >> 6, cc = e & 63;
+    const int64_t r = r0 + rr;
+    const double v = load(r < rows ? r : rows - 1, cc < K ? cc : K - 1);
+    reg[m] = (r < rows && cc < K) ? v : 0.0;
+  }
+}
+__device__ inline void stage_store(const double (&reg)[16], double* stg) {
+#pragma unroll
+  for (int m = 0; m < 16; ++m) stg[threadIdx.x + 256 * m] = reg[m];
+}
 
 // out[i][c] = sum_r a(r, i) a(r, c) for a rows x K block, rows in order;
 // thread t owns the 4 x 4 tile t of the upper triangle (tiles of the 16 x 16
 // tile grid of a 64-wide matrix: at most 136 tiles).  out: global K x K, both
-// triangles written.  stg: LDS [kGStg][64].
+// triangles written.  stg: LDS [kGStg][64]; the next stage is prefetched into
+// registers while the current one is used.
 template <typename Load>
 __device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, double* stg) {
   const int t = threadIdx.x;
@@ -397,14 +472,13 @@ __device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, doub
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  double nxt[16];
+  stage_load(load, 0, rows, K, nxt);
   for (int64_t r0 = 0; r0 < rows; r0 += kGStg) {
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kGStg * 64 / 256; ++m) {
-      const int e = t + 256 * m, rr = e >> 6, cc = e & 63;
-      stg[e] = (r0 + rr < rows && cc < K) ? load(r0 + rr, cc) : 0.0;
-    }
+    stage_store(nxt, stg);
     __syncthreads();
+    if (r0 + kGStg < rows) stage_load(load, r0 + kGStg, rows, K, nxt);
     if (act) {
       for (int rr = 0; rr < kGStg; ++rr) {
         double av[4], bv[4];
@@ -437,30 +511,44 @@ __device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, doub
 
 // out(r, c) = sum_{p <= c} a(r, p) Rinv[p][c] (p ascending) for a rows x K
 // block; Rl: LDS [64][64] copy of Rinv (zero below the diagonal), stg: LDS
-// [kGStg][64].
+// [kGStg][64].  Thread (c = t % K, g = t / K) computes column c of the stage
+// rows g, g + ng, ... (ng = 256 / K): independent accumulation chains.
 template <typename Load, typename Store>
 __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rinv, double* Rl,
                                double* stg, Store store) {
   const int t = threadIdx.x;
+  const int ng = 256 / K;
+  const bool act = t < ng * K;
+  const int c = t % K, g = t / K;
   __syncthreads();
   for (int e = t; e < 64 * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
-    Rl[e] = (i < K && c < K && i <= c) ? Rinv[i * K + c] : 0.0;
+    const int i = e >> 6, cc = e & 63;
+    Rl[e] = (i < K && cc < K && i <= cc) ? Rinv[i * K + cc] : 0.0;
   }
+  double nxt[16];
+  stage_load(load, 0, rows, K, nxt);
   for (int64_t r0 = 0; r0 < rows; r0 += kGStg) {
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kGStg * 64 / 256; ++m) {
-      const int e = t + 256 * m, rr = e >> 6, cc = e & 63;
-      stg[e] = (r0 + rr < rows && cc < K) ? load(r0 + rr, cc) : 0.0;
-    }
+    stage_store(nxt, stg);
     __syncthreads();
-    for (int e = t; e < kGStg * K; e += 256) {
-      const int rr = e / K, c = e - rr * K;
-      if (r0 + rr >= rows) continue;
-      double s = 0.0;
-      for (int p = 0; p <= c; ++p) s = fma(stg[rr * 64 + p], Rl[p * 64 + c], s);
-      store(r0 + rr, c, s);
+    if (r0 + kGStg < rows) stage_load(load, r0 + kGStg, rows, K, nxt);
+    if (act) {
+      double s[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s[q] = 0.0;
+      for (int p = 0; p <= c; ++p) {
+        const double rv = Rl[p * 64 + c];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int rr = g + ng * q;
+          if (rr < kGStg) s[q] = fma(stg[rr * 64 + p], rv, s[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int rr = g + ng * q;
+        if (rr < kGStg && r0 + rr < rows) store(r0 + rr, c, s[q]);
+      }
     }
   }
   __syncthreads();
@@ -469,11 +557,12 @@ __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rin
 // CholeskyQR2 of Z (or of V when from_v) for problem blockIdx.x: V = Q, the
 // operand vop[c][j] = bf16(V[j][c]) (zero for j >= d or c >= K, up to Kp x dc)
 // and, with want_b, B = V'^T V' of the bf16 values.
-__global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ probs, int from_v,
+__global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ probs,
+                                                  const int* __restrict__ order, int from_v,
                                                   int want_b, int* status) {
   __shared__ double stg[kGStg * 64];
   __shared__ double Rl[64 * 64];
-  const GProb& P = probs[blockIdx.x];
+  const GProb& P = probs[order[blockIdx.x]];
   const int64_t d = P.d;
   const int K = P.K;
   const float* src = from_v ? P.V : P.Z;
@@ -502,11 +591,12 @@ __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ prob
 }
 
 // Rayleigh-Ritz, part 1: R = chol(B), T = G R^-1, H = (R^-T T) / n.
-__global__ __launch_bounds__(256) void k_grr_h(const GProb* __restrict__ probs, int* status) {
+__global__ __launch_bounds__(256) void k_grr_h(const GProb* __restrict__ probs,
+                                               const int* __restrict__ order, int* status) {
   __shared__ double Rl[64 * 64];
   __shared__ double Gl[64 * 64];
   __shared__ double Tl[64 * 64];
-  const GProb& P = probs[blockIdx.x];
+  const GProb& P = probs[order[blockIdx.x]];
   const int K = P.K, t = threadIdx.x;
   dev::chol_inv_dev<kGroupMaxK>(P.B, K, P.R, P.Rinv, status);
   __syncthreads();
@@ -531,22 +621,23 @@ __global__ __launch_bounds__(256) void k_grr_h(const GProb* __restrict__ probs, 
   }
 }
 
-// Rayleigh-Ritz, part 2: Jacobi on H; workgroup (x, problem) owns W rows 16 x ..
+// Rayleigh-Ritz, part 2: Jacobi on H, one workgroup per problem holding all of W.
 __global__ __launch_bounds__(1024) void k_grr_jacobi(const GProb* __restrict__ probs,
+                                                     const int* __restrict__ order,
                                                      int max_sweeps, int* status) {
-  const GProb& P = probs[blockIdx.y];
-  if ((int)blockIdx.x * dev::kJacRows >= P.K) return;
-  dev::jacobi_dev<kGroupMaxK>(P.H, P.K, P.W, P.ev, max_sweeps, status, blockIdx.x);
+  const GProb& P = probs[order[blockIdx.x]];
+  dev::jacobi_dev<kGroupMaxK, kGroupMaxK>(P.H, P.K, P.W, P.ev, max_sweeps, status, 0);
 }
 
 // Rayleigh-Ritz, part 3: M = R^-1 W[:, :k], E = V_eff M (V_eff = bf16(V)),
 // column signs (largest |.| positive, lowest row on ties), evals = theta[:k].
-__global__ __launch_bounds__(256) void k_grr_e(const GProb* __restrict__ probs, int* status) {
+__global__ __launch_bounds__(256) void k_grr_e(const GProb* __restrict__ probs,
+                                               const int* __restrict__ order, int* status) {
   __shared__ double Ml[64 * 64];
   __shared__ float bv[256];
   __shared__ int bi[256];
   __shared__ int flip[64];
-  const GProb& P = probs[blockIdx.x];
+  const GProb& P = probs[order[blockIdx.x]];
   const int K = P.K, k = P.k, t = threadIdx.x;
   const int64_t d = P.d;
   if (t < k) P.evals[t] = P.ev[t];
@@ -628,19 +719,19 @@ hipError_t launch_group_reduce(const GProb* probs, int nprob, const int* blk0, i
   return hipGetLastError();
 }
 
-hipError_t launch_group_cholqr2(const GProb* probs, int nprob, bool from_v, bool want_b,
-                                int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_gcholqr2, dim3(nprob), dim3(256), 0, s, probs, from_v ? 1 : 0,
+hipError_t launch_group_cholqr2(const GProb* probs, const int* order, int nprob, bool from_v,
+                                bool want_b, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcholqr2, dim3(nprob), dim3(256), 0, s, probs, order, from_v ? 1 : 0,
                      want_b ? 1 : 0, status);
   return hipGetLastError();
 }
 
-hipError_t launch_group_rr(const GProb* probs, int nprob, int max_sweeps, int* status,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_grr_h, dim3(nprob), dim3(256), 0, s, probs, status);
-  hipLaunchKernelGGL(k_grr_jacobi, dim3(kGroupMaxK / dev::kJacRows, nprob), dim3(1024), 0, s,
-                     probs, max_sweeps, status);
-  hipLaunchKernelGGL(k_grr_e, dim3(nprob), dim3(256), 0, s, probs, status);
+hipError_t launch_group_rr(const GProb* probs, const int* order, int nprob, int max_sweeps,
+                           int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_grr_h, dim3(nprob), dim3(256), 0, s, probs, order, status);
+  hipLaunchKernelGGL(k_grr_jacobi, dim3(nprob), dim3(1024), 0, s, probs, order, max_sweeps,
+                     status);
+  hipLaunchKernelGGL(k_grr_e, dim3(nprob), dim3(256), 0, s, probs, order, status);
   return hipGetLastError();
 }
 

@@ -307,11 +307,12 @@ int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipSt
 constexpr int64_t kGroupItemBytes = 3 << 20;   // X bytes per work item (target)
 
 struct GroupPlan {
-  size_t status = 0, probs = 0, items = 0, blk_z = 0, blk_g = 0, zpart = 0, gpart = 0;
+  size_t status = 0, probs = 0, items = 0, blk_z = 0, blk_g = 0, order = 0, zpart = 0, gpart = 0;
   size_t total = 0;
   std::vector<GProb> hp;
   std::vector<GItem> hi;
   std::vector<int> bz, bg;                       // reduce block starts, nprob + 1 each
+  std::vector<int> ord;                          // problems by d K^2, largest first
   std::vector<size_t> pv, pz, pq, pk;            // per problem: vop, Z, q1, K x K block
 };
 
@@ -390,10 +391,17 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
     const int64_t ca = a.rows * gp.hp[a.prob].d, cb = b.rows * gp.hp[b.prob].d;
     return ca > cb;
   });
+  gp.ord.resize(nprob);
+  for (int p = 0; p < nprob; ++p) gp.ord[p] = p;
+  std::stable_sort(gp.ord.begin(), gp.ord.end(), [&](int a, int b) {
+    const GProb &A = gp.hp[a], &B = gp.hp[b];
+    return A.d * A.K * A.K > B.d * B.K * B.K;
+  });
   gp.probs = c.take(gp.hp.size() * sizeof(GProb));
   gp.items = c.take(gp.hi.size() * sizeof(GItem));
   gp.blk_z = c.take(gp.bz.size() * sizeof(int));
   gp.blk_g = c.take(gp.bg.size() * sizeof(int));
+  gp.order = c.take(gp.ord.size() * sizeof(int));
   gp.zpart = c.take((size_t)zf * sizeof(float));
   gp.gpart = c.take((size_t)gf * sizeof(float));
   gp.total = c.off;
@@ -433,6 +441,8 @@ int upload_group_plan(const GroupPlan& gp, void* ws, hipStream_t s) {
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.blk_g), gp.bg.data(), gp.bg.size() * sizeof(int),
                          hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<void>(ws, gp.order), gp.ord.data(), gp.ord.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
   HIP_TRY(launch_zero(at<int>(ws, gp.status), 256, s));
   return PPCA_OK;
 }
@@ -466,7 +476,7 @@ int group_iteration(const GroupPlan& gp, void* ws, bool want_b, bool time_it, hi
   HIP_TRY(time_it ? timed(2, s, pass) : pass());
   HIP_TRY(launch_group_reduce(dP, nprob, at<int>(ws, gp.blk_z), gp.bz.back(),
                               at<float>(ws, gp.zpart), at<float>(ws, gp.gpart), true, st, s));
-  HIP_TRY(launch_group_cholqr2(dP, nprob, false, want_b, st, s));
+  HIP_TRY(launch_group_cholqr2(dP, at<int>(ws, gp.order), nprob, false, want_b, st, s));
   return PPCA_OK;
 }
 int check_sgd(const ppca_matrix* X, const ppca_sgd_params* q) {
@@ -658,7 +668,7 @@ int ppca_prime_power_grouped(const ppca_problem* probs, int32_t nprob, int32_t i
   RET_IF(upload_group_plan(gp, ws, s));
   const GProb* dP = at<GProb>(ws, gp.probs);
   int* st = at<int>(ws, gp.status);
-  HIP_TRY(launch_group_cholqr2(dP, nprob, true, iters == 0, st, s));
+  HIP_TRY(launch_group_cholqr2(dP, at<int>(ws, gp.order), nprob, true, iters == 0, st, s));
   if (graph && iters > 1) {
     // iterations 1 .. iters-1 replay one captured iteration; the last one
     // (which also forms B) runs eagerly
@@ -706,7 +716,8 @@ int ppca_rayleigh_ritz_grouped(const ppca_problem* probs, int32_t nprob, void* w
   hipStream_t s = (hipStream_t)stream;
   bind_group_plan(gp, probs, ws);
   RET_IF(upload_group_plan(gp, ws, s));
-  HIP_TRY(launch_group_rr(at<GProb>(ws, gp.probs), nprob, 60, at<int>(ws, gp.status), s));
+  HIP_TRY(launch_group_rr(at<GProb>(ws, gp.probs), at<int>(ws, gp.order), nprob, 60,
+                          at<int>(ws, gp.status), s));
   return finish_group(gp, ws, s);
 }
 

@@ -171,9 +171,10 @@ hipError_t launch_group_pass(const GProb* probs, const GItem* items, int nitems,
 hipError_t launch_group_reduce(const GProb* probs, int nprob, const int* blk0, int nblk,
                                const float* zpart, const float* gpart, bool want_z, int* status,
                                hipStream_t s);
-hipError_t launch_group_cholqr2(const GProb* probs, int nprob, bool from_v, bool want_b,
-                                int* status, hipStream_t s);
-hipError_t launch_group_rr(const GProb* probs, int nprob, int max_sweeps, int* status,
-                           hipStream_t s);
+// order: problem indices, largest first (workgroup b takes problem order[b])
+hipError_t launch_group_cholqr2(const GProb* probs, const int* order, int nprob, bool from_v,
+                                bool want_b, int* status, hipStream_t s);
+hipError_t launch_group_rr(const GProb* probs, const int* order, int nprob, int max_sweeps,
+                           int* status, hipStream_t s);
 
 }  // namespace ppca
