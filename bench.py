@@ -585,6 +585,13 @@ def main_grouped(a):
            "accuracy": {"max_rel_eig_err": max(rel), "median_rel_eig_err": float(np.median(rel)),
                         "sin_theta_max": max(sin_t), "median_sin_theta": float(np.median(sin_t))},
            "roofline": roofline}
+    if a.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_grouped(data, shapes, v0s, iters)
     print(json.dumps(out), flush=True)
