@@ -433,14 +433,15 @@ def main_minibatch(a):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_minibatch(X, k, l, c, v0, es, oja):
-    """The float64 oracle's minibatch priming on the same stored rows, timed
-    over a bounded number of steps (about 10 s of host work)."""
+def cpu_baseline_minibatch(X, k, l, c, v0, es, oja, budget_s=10.0):
+    """The float64 oracle's minibatch priming on a bounded sample of the
+    stored rows (the first 40 minibatches, cycled), timed over as many steps
+    as about budget_s seconds of host work allow (a short calibration run
+    sets the count)."""
     import torch
     from oracle import ppca_oracle as O
     b = c["batch"]
-    tsteps = 200 if oja else 40
-    rows = min(X.n, tsteps * b)
+    rows = min(X.n, 40 * b)
     if X.dtype == 1:
         xs = O.bf16_value(X.x[:rows].contiguous().view(torch.int16).cpu().numpy().view(np.uint16))
     elif X.dtype == 2:
@@ -457,13 +458,17 @@ def cpu_baseline_minibatch(X, k, l, c, v0, es, oja):
         cores = os.cpu_count()
     fn = O.prime_oja if oja else O.prime_eigengame
     t0 = time.perf_counter()
+    fn(xs, vh, batch=b, steps=10, eta0=c["eta0"], t0=c["t0"])
+    cal = (time.perf_counter() - t0) / 10
+    tsteps = max(10, int(budget_s / max(cal, 1e-6)))
+    t0 = time.perf_counter()
     fn(xs, vh, batch=b, steps=tsteps, eta0=c["eta0"], t0=c["t0"])
     dt = time.perf_counter() - t0
     return {"value": round(2 * tsteps * b * X.d * es / dt / 1e9, 4), "unit": "GB/s",
             "cores": cores, "kind": "oracle", "seconds": round(dt, 2),
             "us_per_minibatch_step": round(dt * 1e6 / tsteps, 1),
-            "sample": f"{tsteps} minibatch steps of {b} rows (the first {rows} stored rows), "
-                      f"float64 numpy; GB/s counts 2 reads of the minibatch per step"}
+            "sample": f"{tsteps} minibatch steps of {b} rows over the first {rows} stored rows "
+                      f"(cycled), float64 numpy; GB/s counts 2 reads of the minibatch per step"}
 
 
 # Grouped problems: 512 independent problems with n ~ LogUniform[2000, 200000],

@@ -50,12 +50,22 @@ __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ x, int
   const int64_t r0 = (int64_t)blockIdx.y * kPrepRows;
   const int64_t r1 = r0 + kPrepRows < n ? r0 + kPrepRows : n;
   double hi = 0.0, lo = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
+  auto add = [&](float v) {
     double s, e;
-    two_sum(hi, (double)x[r * ld + j], s, e);
+    two_sum(hi, (double)v, s, e);
     hi = s;
     lo += e;
+  };
+  // rows in order; eight loads in flight ahead of the dependent sums
+  int64_t r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[(r + u) * ld + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) add(v[u]);
   }
+  for (; r < r1; ++r) add(x[r * ld + j]);
   double s, e;
   two_sum(hi, lo, s, e);
   part[((int64_t)blockIdx.y * d + j) * 2 + 0] = s;
@@ -90,7 +100,15 @@ __global__ __launch_bounds__(256) void k_colmax(const float* __restrict__ x, int
   const int64_t r1 = r0 + kPrepRows < n ? r0 + kPrepRows : n;
   const double mu = mean[j];
   float m = 0.f;
-  for (int64_t r = r0; r < r1; ++r) m = fmaxf(m, fabsf(centred(x[r * ld + j], mu)));
+  int64_t r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[(r + u) * ld + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmaxf(m, fabsf(centred(v[u], mu)));
+  }
+  for (; r < r1; ++r) m = fmaxf(m, fabsf(centred(x[r * ld + j], mu)));
   part[(int64_t)blockIdx.y * d + j] = m;
 }
 
