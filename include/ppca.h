@@ -203,9 +203,11 @@ int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k,
  * (ppca_prime_power, then ppca_project_gram, then ppca_rayleigh_ritz) for
  * bf16 data: V' = bf16(V), Y' = bf16(X V'), Z = X^T Y', G = Y'^T Y'.
  * Limits per problem: dtype PPCA_BF16, 1 <= d <= PPCA_GROUP_MAX_D,
- * 1 <= k, 0 <= l, K = k + l <= min(PPCA_GROUP_MAX_K, n, d). */
+ * ld <= PPCA_GROUP_MAX_LD, 1 <= k, 0 <= l, K = k + l <= min(PPCA_GROUP_MAX_K,
+ * n, d). */
 #define PPCA_GROUP_MAX_D 768
 #define PPCA_GROUP_MAX_K 64
+#define PPCA_GROUP_MAX_LD (1 << 24)
 #define PPCA_GROUP_GRAPH 1   /* flag: replay the power iteration as a captured HIP graph */
 
 typedef struct {

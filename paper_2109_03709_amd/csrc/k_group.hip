@@ -8,8 +8,10 @@
 //               waves of a workgroup split the columns of a 16-row tile, each
 //               wave's slice of X is staged in its own LDS buffers by DMA and
 //               used for both products, and the partial Y of the waves is
-//               summed through LDS.  Tiles go in pairs so that the second
-//               product runs on 16x16x32 MFMAs (k = the pair's 32 rows).
+//               summed through LDS.  All products run on 32x32x16 MFMAs (with
+//               one wave per SIMD they sustain about 2.5 times the rate of the
+//               16x16 shapes): Y over pairs of 16-row tiles (M = 32 rows),
+//               the second products with K = the 16 rows of one tile.
 //   k_greduce   fixed-order float64 sums of the item partials -> Z (f32), G (f64)
 //   k_gcholqr2  CholeskyQR2 per problem (one workgroup, largest problems
 //               launched first): new V, its bf16
@@ -25,7 +27,8 @@
 //   dci 2: dc 256, WD 4, CW 1
 //   dci 3: dc 512, WD 4, CW 2
 //   dci 4: dc 768, WD 4, CW 3
-// combined with NB = Kp / 16 in 1..4: 20 code paths in one kernel.
+// combined with NB2 = Kp / 32 in 1..2 (K padded to 32): 10 code paths in one
+// kernel.
 //
 // Partials: Z of item i, row group r: zpart[zoff + (r * Kp + c) * dc + j]
 // (column c of Z, row j of Z); G of item i, wave w: gpart[goff + (w * Kp + c)
@@ -51,282 +54,316 @@ namespace {
 using namespace dma;
 using dev::status_set;
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-template <int NB, int DCI>
+template <int NB2, int DCI>
 struct GCls {
   static constexpr int WD = DCI == 0 ? 1 : (DCI == 1 ? 2 : 4);   // waves sharing a row tile
   static constexpr int CW = DCI <= 2 ? 1 : DCI - 1;              // 64-column groups per wave
   static constexpr int WR = 4 / WD;                              // row groups
   static constexpr int DW = 64 * CW;                             // columns per wave
   static constexpr int DC = WD * DW;                             // class width
-  static constexpr int KP = 16 * NB;
+  static constexpr int KP = 32 * NB2;                            // K padded to 32
   static constexpr int CPR = DW / 8;                             // 16-byte chunks per slice row
   static constexpr int XSB = 16 * DW * 2;                        // bytes of one stage
   static constexpr int DPS = XSB / 1024;                         // DMAs per stage
-  static constexpr int NBT = NB * (NB + 1) / 2;                  // upper blocks of G
+  static constexpr int NBT = NB2 * (NB2 + 1) / 2;                // upper blocks of G
   static constexpr int NGS = (NBT + WD - 1) / WD;                // G blocks per wave
   // X stages per wave: the same LDS for every class (24 KB per wave), so that
   // the narrow classes keep as many bytes in flight as the wide ones
   static constexpr int S = 4 * 16 * 192 * 2 / XSB;               // 12, 6 or 4
   static_assert((S - 1) * DPS < 64 && S >= 4 && S % 2 == 0, "stage ring");
-  // sub-tiles in pairs (second products on 16x16x32 MFMAs), except for the
-  // widest class at K > 48 (see run_item)
-  static constexpr bool ZPAIR = !(DCI == 4 && NB == 4);
 };
 
 constexpr int kGS = 4;                    // X stages per wave at the widest class
 constexpr int kGStage = 16 * 192 * 2;     // bytes of one stage at the widest class
-constexpr int kGExch = 4 * 2 * 4 * 64;    // exchange slots [wave][sub-tile][nb][lane]
+constexpr int kGExch = 4 * 2 * 4 * 64;    // f32 exchange slots [wave][nb][quarter][lane] (f32x4)
+constexpr int kGExchB = 2 * 4 * 64;       // bf16 exchange slots [row group][nb][m][lane] (uint4)
 
-// One work item (rows [r0, r0 + rows) of one problem) of class (NB, DCI).
-// Sub-tile t of row group rg covers item rows (t * WR + rg) * 16 .. + 15.
-template <int NB, int DCI, bool WZ>
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// two floats to bf16, round to nearest even (v_cvt_pk_bf16_f32), lo in the low half
+__device__ inline uint32_t pack2_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
+
+// One work item (rows [r0, r0 + rows) of one problem) of class (NB2, DCI).
+// Sub-tile t of row group rg covers item rows (t * WR + rg) * 16 .. + 15; the
+// sub-tiles go in pairs (2 p, 2 p + 1), 32 rows, the M dimension of the
+// 32x32x16 MFMAs of Y = X V'.  Lane l (l32 = l % 32, hl = l / 32) of a 32x32
+// MFMA result holds element i at row 8 (i / 4) + 4 hl + i % 4 and column l32:
+// the eight elements i = 8 m .. 8 m + 7 are rows of sub-tile m, and serve as
+// this lane's eight k-slots (k = 8 hl + e <-> row 8 (e / 4) + 4 hl + e % 4 of
+// sub-tile m) of the second products, Z += X^T Y' and G += Y'^T Y' on
+// 32x32x16 MFMAs with K = the 16 rows of one sub-tile.
+template <int NB2, int DCI, bool WZ>
 __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, const GItem& I,
-                                                               uint8_t* xl, f32x4_t* ex,
+                                                               uint8_t* xl, f32x4_t* exf,
+                                                               uint4* exb,
                                                                float* zpart, float* gpart) {
-  using C = GCls<NB, DCI>;
+  using C = GCls<NB2, DCI>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rg = wave / C::WD, wd = wave % C::WD;
-  const int a = lane & 15, g = lane >> 4;
+  const int l32 = lane & 31, hl = lane >> 5;
   const int c0 = wd * C::DW;
   const int64_t d = P.d, ld = P.ld, rows = I.rows, r0 = I.r0;
   const uint8_t* x = reinterpret_cast<const uint8_t*>(P.x);
   uint8_t* st = xl + wave * (kGS * kGStage);
 
-  // operand fragments of this wave's column slice (k-step s: columns c0 + 32 s ..)
-  uint4 vf[2 * C::CW][NB];
+  // operand fragments of this wave's column slice: k-substep s covers columns
+  // c0 + 16 s .. + 15; lane (l32, hl) holds V' row 32 nb + l32, columns 8 hl ..
+  uint4 vf[C::DW / 16][NB2];
 #pragma unroll
-  for (int s = 0; s < 2 * C::CW; ++s)
+  for (int s = 0; s < C::DW / 16; ++s)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      vf[s][nb] = *reinterpret_cast<const uint4*>(P.vop + (int64_t)(16 * nb + a) * C::DC + c0 +
-                                                  32 * s + 8 * g);
+    for (int nb = 0; nb < NB2; ++nb)
+      vf[s][nb] = *reinterpret_cast<const uint4*>(P.vop + (int64_t)(32 * nb + l32) * C::DC + c0 +
+                                                  16 * s + 8 * hl);
 
   // DMA lanes: slot q = 64 j + lane of a stage is (row q / CPR, slot q % CPR)
   // and holds the slice's 16-byte column chunk slot ^ (row & 7); chunks past d
-  // load column 0 (their operand rows are zero)
-  int drow[C::DPS];
-  int64_t dcol[C::DPS];
-#pragma unroll
-  for (int j = 0; j < C::DPS; ++j) {
+  // load column 0 (their operand rows are zero).  voff: byte offset of lane's
+  // chunk j from its tile's first row.
+  auto drow = [&](int j) __attribute__((always_inline)) { return (64 * j + lane) / C::CPR; };
+  auto dcol = [&](int j) __attribute__((always_inline)) {
     const int q = 64 * j + lane, r = q / C::CPR, sl = q % C::CPR;
     const int64_t col = c0 + 8 * (sl ^ (r & 7));
-    drow[j] = r;
-    dcol[j] = (col < d ? col : 0) * 2;
-  }
+    return (col < d ? col : 0) * 2;
+  };
+  uint32_t voff[C::DPS];
+#pragma unroll
+  for (int j = 0; j < C::DPS; ++j) voff[j] = (uint32_t)(drow(j) * ld * 2 + dcol(j));
   const int64_t srows = 16 * C::WR;
   const int64_t nsub = (rows + srows - 1) / srows;
   // DMA of sub-tile t into stage b (t clamped to the last sub-tile, rows past
-  // the item clamped to its last row: every wave issues the same count)
+  // the item clamped to its last row: every wave issues the same count).
+  // Whole tiles take a scalar base and the 32-bit lane offsets.
   auto issue = [&](int64_t t, int b) __attribute__((always_inline)) {
     const int64_t tc = t < nsub ? t : nsub - 1;
     const int64_t lb = (tc * C::WR + rg) * 16;
     uint8_t* dst = st + b * C::XSB;
+    if (lb + 16 <= rows) {
+      const uint8_t* sb = x + (r0 + lb) * ld * 2;
 #pragma unroll
-    for (int j = 0; j < C::DPS; ++j) {
-      int64_t li = lb + drow[j];
-      li = li < rows ? li : rows - 1;
-      dma16(x + (r0 + li) * ld * 2 + dcol[j], dst + j * 1024);
+      for (int j = 0; j < C::DPS; ++j) dma16s(sb, voff[j], dst + j * 1024);
+    } else {
+#pragma unroll
+      for (int j = 0; j < C::DPS; ++j) {
+        int64_t li = lb + drow(j);
+        li = li < rows ? li : rows - 1;
+        dma16(x + (r0 + li) * ld * 2 + dcol(j), dst + j * 1024);
+      }
     }
   };
 
-  // Z accumulators (Z pass) or G accumulators (G pass)
-  const f32x4_t z4 = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // Z accumulators (Z pass: column group q, column parity v, block nb) or G
+  // accumulators (G pass)
   constexpr int NZ = WZ ? C::CW : 0, NG = WZ ? 0 : C::NGS;
-  f32x4_t zacc[NZ > 0 ? NZ : 1][4][NB];
-  f32x4_t gacc[NG > 0 ? NG : 1];
+  f32x16_t zacc[NZ > 0 ? NZ : 1][2][NB2];
+  f32x16_t gacc[NG > 0 ? NG : 1];
 #pragma unroll
   for (int q = 0; q < NZ; ++q)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 2; ++v)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = z4;
+      for (int nb = 0; nb < NB2; ++nb) zacc[q][v][nb] = f32x16_t{};
 #pragma unroll
-  for (int i = 0; i < NG; ++i) gacc[i] = z4;
+  for (int i = 0; i < NG; ++i) gacc[i] = f32x16_t{};
 
   wait_vmcnt<0>();   // the operand fragments have landed before the DMA stream starts
   wait_lgkm0();      // LDS reads of the previous item are done before its stages refill
-  // H sub-tiles per iteration.  With H = 2 the second products run on
-  // 16x16x32 MFMAs whose 32 k-slots are the pair's rows: k = 8 g + e is row
-  // 4 g + e of the first sub-tile (e < 4) or row 4 g + e - 4 of the second,
-  // which is how the Y MFMA outputs already sit in the lanes.  With H = 1
-  // (the widest class at K > 48, whose 192 Z accumulators and 96 operand
-  // registers leave no room for a pair) they run on 16x16x16 MFMAs, k = rows
-  // 4 g .. 4 g + 3.  S - H sub-tiles are in flight ahead of the ones used.
-  constexpr int H = C::ZPAIR ? 2 : 1;
+  // S - 2 sub-tiles are in flight ahead of the pair being used
 #pragma unroll
-  for (int b = 0; b < C::S - H; ++b) issue(b, b);
-  const int64_t nit = (nsub + H - 1) / H;
-  int bcur = 0;                 // stage of sub-tile H p
-  for (int64_t p = 0; p < nit; ++p) {
-    wait_vmcnt<(C::S - 2 * H) * C::DPS>();   // the H sub-tiles of step p have landed
-    wait_lgkm0();                            // ... and those of step p - 1 have been read
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const int bb = bcur - H + h;
-      issue(H * p + C::S - H + h, bb >= 0 ? bb : bb + C::S);
-    }
-    const uint8_t* xs[H];
-#pragma unroll
-    for (int h = 0; h < H; ++h) xs[h] = st + (bcur + h) * C::XSB;
-    bcur = bcur + H == C::S ? 0 : bcur + H;
+  for (int b = 0; b < C::S - 2; ++b) issue(b, b);
+  const int64_t npair = (nsub + 1) / 2;
+  int bcur = 0;                 // stage of sub-tile 2 p
+  for (int64_t p = 0; p < npair; ++p) {
+    wait_vmcnt<(C::S - 4) * C::DPS>();   // the pair's sub-tiles have landed
+    wait_lgkm0();                        // ... and the previous pair's have been read
+    issue(2 * p + C::S - 2, bcur >= 2 ? bcur - 2 : bcur + C::S - 2);
+    issue(2 * p + C::S - 1, bcur >= 1 ? bcur - 1 : bcur + C::S - 1);
+    const uint8_t* xs0 = st + bcur * C::XSB;
+    const uint8_t* xs1 = xs0 + C::XSB;
+    bcur = bcur + 2 == C::S ? 0 : bcur + 2;
 
-    // partial Y of the slice (rows a, k-chunk 4 s + g) of sub-tile h
-    auto ypart = [&](int h, f32x4_t (&yh)[NB]) __attribute__((always_inline)) {
+    // partial Y of the slice: lane row l32 of the pair (sub-tile l32 / 16),
+    // k-substep s: chunk 2 s + hl
+    f32x16_t ya[NB2];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) yh[nb] = z4;
+    for (int nb = 0; nb < NB2; ++nb) ya[nb] = f32x16_t{};
+    {
+      const int rr = l32 & 15;
+      const uint8_t* xrow = ((l32 >> 4) ? xs1 : xs0) + rr * C::CPR * 16;
 #pragma unroll
-      for (int s = 0; s < 2 * C::CW; ++s) {
+      for (int s = 0; s < C::DW / 16; ++s) {
         const uint4 av =
-            *reinterpret_cast<const uint4*>(xs[h] + (a * C::CPR + ((4 * s + g) ^ (a & 7))) * 16);
+            *reinterpret_cast<const uint4*>(xrow + (((2 * s + hl) ^ (rr & 7)) * 16));
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          yh[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
-                                                           yh[nb], 0, 0, 0);
+        for (int nb = 0; nb < NB2; ++nb)
+          ya[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
+                                                           ya[nb], 0, 0, 0);
       }
-    };
-    // Y' = bf16(Y) of sub-tile h into the k-slot words 2 h, 2 h + 1 of column
-    // block nb (rows past the item zeroed)
-    uint32_t ybw[NB][2 * H];
-    auto ypack = [&](int h, int nb, f32x4_t y) __attribute__((always_inline)) {
-      const int64_t vr = rows - ((H * p + h) * C::WR + rg) * 16;
-      const float y0 = (4 * g + 0 < vr) ? y[0] : 0.f;
-      const float y1 = (4 * g + 1 < vr) ? y[1] : 0.f;
-      const float y2 = (4 * g + 2 < vr) ? y[2] : 0.f;
-      const float y3 = (4 * g + 3 < vr) ? y[3] : 0.f;
-      ybw[nb][2 * h] = f32_to_bf16_bits(y0) | (f32_to_bf16_bits(y1) << 16);
-      ybw[nb][2 * h + 1] = f32_to_bf16_bits(y2) | (f32_to_bf16_bits(y3) << 16);
-    };
+    }
+    // Y' = bf16(Y), rows past the item zeroed: yb[nb][m] holds this lane's
+    // eight k-slots of sub-tile m (elements 8 m .. 8 m + 7 of ya[nb])
+    uint4 yb[NB2][2];
     if constexpr (C::WD > 1) {
-      // sum over the waves of the row group, in wave order (lane layout of
-      // the MFMA output: rows 4 g .. 4 g + 3 of column a); the first barrier
-      // makes sure the previous step's sums have been read
-      f32x4_t* mine = ex + wave * 2 * NB * 64 + lane;
+      // reduce-scatter: wave wd of the row group sums the values f = wd PS ..
+      // wd PS + PS - 1 (f = 16 nb + i) over the group's waves in wave order,
+      // rounds them and writes them to the row group's bf16 slots; then every
+      // wave reads all of them.  The barriers also order the reuse of both
+      // areas across pairs.
+      constexpr int NV = 16 * NB2, PS = NV / C::WD;
+      f32x4_t* mine = exf + wave * (NV / 4) * 64 + lane;
+#pragma unroll
+      for (int nb = 0; nb < NB2; ++nb)
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd)
+          mine[(nb * 4 + qd) * 64] =
+              f32x4_t{ya[nb][4 * qd], ya[nb][4 * qd + 1], ya[nb][4 * qd + 2], ya[nb][4 * qd + 3]};
+      wait_lgkm0();
       raw_barrier();
+      const f32x4_t* src = exf + rg * C::WD * (NV / 4) * 64 + wd * (PS / 4) * 64 + lane;
+      float ys[PS];
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        f32x4_t yh[NB];
-        ypart(h, yh);
+      for (int u = 0; u < PS / 4; ++u) {
+        f32x4_t y = src[u * 64];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) mine[(h * NB + nb) * 64] = yh[nb];
+        for (int j = 1; j < C::WD; ++j) y += src[(j * (NV / 4) + u) * 64];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ys[4 * u + c] = y[c];
+      }
+      uint32_t w[PS / 2];
+#pragma unroll
+      for (int v = 0; v < PS; v += 2) {
+        float y2[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int i = (wd * PS + v + c) & 15, m = i >> 3, e = i & 7;
+          const int64_t vr = rows - ((2 * p + m) * C::WR + rg) * 16;
+          y2[c] = (8 * (e >> 2) + 4 * hl + (e & 3) < vr) ? ys[v + c] : 0.f;
+        }
+        w[v / 2] = pack2_bf16(y2[0], y2[1]);
+      }
+      uint32_t* eb = reinterpret_cast<uint32_t*>(exb + rg * (NV / 8) * 64);
+      const int u0 = wd * (PS / 2);   // first dword of the part
+      if constexpr (PS / 2 == 2) {
+        *reinterpret_cast<uint2*>(eb + ((u0 / 4) * 64 + lane) * 4 + (u0 & 3)) =
+            make_uint2(w[0], w[1]);
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < PS / 8; ++s4)
+          *reinterpret_cast<uint4*>(eb + ((u0 / 4 + s4) * 64 + lane) * 4) =
+              make_uint4(w[4 * s4], w[4 * s4 + 1], w[4 * s4 + 2], w[4 * s4 + 3]);
       }
       wait_lgkm0();
       raw_barrier();
-      const f32x4_t* src = ex + rg * C::WD * 2 * NB * 64 + lane;
 #pragma unroll
-      for (int h = 0; h < H; ++h)
+      for (int nb = 0; nb < NB2; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          f32x4_t y = src[(h * NB + nb) * 64];
-#pragma unroll
-          for (int j = 1; j < C::WD; ++j) y += src[((j * 2 + h) * NB + nb) * 64];
-          ypack(h, nb, y);
-        }
+        for (int m = 0; m < 2; ++m) yb[nb][m] = exb[(rg * (NV / 8) + nb * 2 + m) * 64 + lane];
     } else {
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        f32x4_t yh[NB];
-        ypart(h, yh);
+      for (int m = 0; m < 2; ++m) {
+        const int64_t vr = rows - ((2 * p + m) * C::WR + rg) * 16;
+        float msk[8];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) ypack(h, nb, yh[nb]);
+        for (int e = 0; e < 8; ++e) msk[e] = (8 * (e / 4) + 4 * hl + e % 4 < vr) ? 1.f : 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB2; ++nb) {
+          float y[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) y[e] = msk[e] != 0.f ? ya[nb][8 * m + e] : 0.f;
+          yb[nb][m] = make_uint4(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]),
+                                 pack2_bf16(y[4], y[5]), pack2_bf16(y[6], y[7]));
+        }
       }
     }
-    // the B operand (k-slots of the step, column a) of both products below
-    auto bop = [&](int nb) __attribute__((always_inline)) {
-      if constexpr (H == 2)
-        return as_bf16x8(make_uint4(ybw[nb][0], ybw[nb][1], ybw[nb][2], ybw[nb][H == 2 ? 3 : 0]));
-      else
-        return __builtin_bit_cast(short4_t, make_uint2(ybw[nb][0], ybw[nb][1]));
-    };
-    auto mfma = [&](auto av, auto bv, f32x4_t acc) __attribute__((always_inline)) {
-      if constexpr (H == 2)
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-      else
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-    };
     // G += Y'^T Y' on the upper blocks (mb <= nb), dealt over the row group's waves
-    if constexpr (!WZ)
+    if constexpr (!WZ) {
 #pragma unroll
-    for (int mb = 0; mb < NB; ++mb)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int nb = mb; nb < NB; ++nb) {
-        const int idx = mb * NB - mb * (mb - 1) / 2 + (nb - mb);
-        if (idx % C::WD == wd) gacc[idx / C::WD] = mfma(bop(mb), bop(nb), gacc[idx / C::WD]);
-      }
-    // Z += X^T Y': column group q, lane (a, g) reads 4 columns (4 a ..) of rows
-    // 4 g .. 4 g + 3 of the step's sub-tiles and transposes them into 4 A
-    // fragments (column 4 a + v, the step's k-slots)
+        for (int mb = 0; mb < NB2; ++mb)
+#pragma unroll
+          for (int nb = mb; nb < NB2; ++nb) {
+            const int idx = mb * NB2 - mb * (mb - 1) / 2 + (nb - mb);
+            if (idx % C::WD == wd)
+              gacc[idx / C::WD] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  as_bf16x8(yb[mb][m]), as_bf16x8(yb[nb][m]), gacc[idx / C::WD], 0, 0, 0);
+          }
+    }
+    // Z += X^T Y': column group q (64 columns), lane l32 reads columns
+    // 2 l32, 2 l32 + 1 of its eight k-slot rows of sub-tile m (4-byte reads):
+    // A fragment v is column 2 l32 + v
     if constexpr (WZ) {
 #pragma unroll
-      for (int q = 0; q < C::CW; ++q) {
-        uint2 in[H][4];
+      for (int m = 0; m < 2; ++m) {
+        const uint8_t* xs = m ? xs1 : xs0;
 #pragma unroll
-        for (int h = 0; h < H; ++h)
+        for (int q = 0; q < C::CW; ++q) {
+          uint32_t in[8];
+          const int ch = 8 * q + (l32 >> 2);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = 4 * g + i, ch = 8 * q + (a >> 1);
-            in[h][i] = *reinterpret_cast<const uint2*>(
-                xs[h] + (row * C::CPR + (ch ^ (row & 7))) * 16 + (a & 1) * 8);
+          for (int e = 0; e < 8; ++e) {
+            const int row = 8 * (e / 4) + 4 * hl + e % 4;
+            in[e] = *reinterpret_cast<const uint32_t*>(
+                xs + (row * C::CPR + (ch ^ (row & 7))) * 16 + (l32 & 3) * 4);
           }
-        uint32_t w[4][2 * H];
+          const uint4 a0 = make_uint4((in[0] & 0xFFFFu) | (in[1] << 16),
+                                      (in[2] & 0xFFFFu) | (in[3] << 16),
+                                      (in[4] & 0xFFFFu) | (in[5] << 16),
+                                      (in[6] & 0xFFFFu) | (in[7] << 16));
+          const uint4 a1 = make_uint4((in[0] >> 16) | (in[1] & 0xFFFF0000u),
+                                      (in[2] >> 16) | (in[3] & 0xFFFF0000u),
+                                      (in[4] >> 16) | (in[5] & 0xFFFF0000u),
+                                      (in[6] >> 16) | (in[7] & 0xFFFF0000u));
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-          w[0][2 * h] = (in[h][0].x & 0xFFFFu) | (in[h][1].x << 16);
-          w[0][2 * h + 1] = (in[h][2].x & 0xFFFFu) | (in[h][3].x << 16);
-          w[1][2 * h] = (in[h][0].x >> 16) | (in[h][1].x & 0xFFFF0000u);
-          w[1][2 * h + 1] = (in[h][2].x >> 16) | (in[h][3].x & 0xFFFF0000u);
-          w[2][2 * h] = (in[h][0].y & 0xFFFFu) | (in[h][1].y << 16);
-          w[2][2 * h + 1] = (in[h][2].y & 0xFFFFu) | (in[h][3].y << 16);
-          w[3][2 * h] = (in[h][0].y >> 16) | (in[h][1].y & 0xFFFF0000u);
-          w[3][2 * h + 1] = (in[h][2].y >> 16) | (in[h][3].y & 0xFFFF0000u);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          auto av = [&] {
-            if constexpr (H == 2)
-              return as_bf16x8(make_uint4(w[v][0], w[v][1], w[v][2], w[v][H == 2 ? 3 : 0]));
-            else
-              return __builtin_bit_cast(short4_t, make_uint2(w[v][0], w[v][1]));
-          }();
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) zacc[q][v][nb] = mfma(av, bop(nb), zacc[q][v][nb]);
+          for (int nb = 0; nb < NB2; ++nb) {
+            zacc[q][0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                as_bf16x8(a0), as_bf16x8(yb[nb][m]), zacc[q][0][nb], 0, 0, 0);
+            zacc[q][1][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                as_bf16x8(a1), as_bf16x8(yb[nb][m]), zacc[q][1][nb], 0, 0, 0);
+          }
         }
       }
     }
   }
   wait_vmcnt<0>();
 
-  // partials.  Z: lane (a, g) of MFMA (q, v, nb) holds Z[c0 + 64 q + 16 g + 4 i + v][16 nb + a]
+  // partials.  Element i of lane (l32, hl) sits at M index mi = 8 (i / 4) +
+  // 4 hl + i % 4.  Z: column c0 + 64 q + 2 mi + v of X, column 32 nb + l32 of Z.
   if constexpr (WZ) {
     float* zp = zpart + I.zoff + (int64_t)rg * C::KP * C::DC;
 #pragma unroll
     for (int q = 0; q < C::CW; ++q)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+      for (int nb = 0; nb < NB2; ++nb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          *reinterpret_cast<float4*>(zp + (int64_t)(16 * nb + a) * C::DC + c0 + 64 * q + 16 * g +
-                                     4 * i) =
-              make_float4(zacc[q][0][nb][i], zacc[q][1][nb][i], zacc[q][2][nb][i],
-                          zacc[q][3][nb][i]);
+        for (int i = 0; i < 16; ++i) {
+          const int mi = 8 * (i / 4) + 4 * hl + i % 4;
+          *reinterpret_cast<float2*>(zp + (int64_t)(32 * nb + l32) * C::DC + c0 + 64 * q + 2 * mi) =
+              make_float2(zacc[q][0][nb][i], zacc[q][1][nb][i]);
+        }
   }
-  // G: block (mb, nb), lane (a, g) holds G[16 mb + 4 g + i][16 nb + a]
+  // G: block (mb, nb), element i holds G[32 mb + mi][32 nb + l32]
   if constexpr (!WZ) {
-  float* gp = gpart + I.goff + (int64_t)wave * C::KP * C::KP;
+    float* gp = gpart + I.goff + (int64_t)wave * C::KP * C::KP;
 #pragma unroll
-  for (int mb = 0; mb < NB; ++mb)
+    for (int mb = 0; mb < NB2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      f32x4_t v = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      if (mb <= nb) {
-        const int idx = mb * NB - mb * (mb - 1) / 2 + (nb - mb);
-        if (idx % C::WD == wd) v = gacc[idx / C::WD];
+      for (int nb = 0; nb < NB2; ++nb) {
+        f32x16_t v = f32x16_t{};
+        if (mb <= nb) {
+          const int idx = mb * NB2 - mb * (mb - 1) / 2 + (nb - mb);
+          if (idx % C::WD == wd) v = gacc[idx / C::WD];
+        }
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4)
+          *reinterpret_cast<float4*>(gp + (32 * nb + l32) * C::KP + 32 * mb + 8 * i4 + 4 * hl) =
+              make_float4(v[4 * i4], v[4 * i4 + 1], v[4 * i4 + 2], v[4 * i4 + 3]);
       }
-      *reinterpret_cast<float4*>(gp + (16 * nb + a) * C::KP + 16 * mb + 4 * g) =
-          make_float4(v[0], v[1], v[2], v[3]);
-    }
   }
 }
 
@@ -338,20 +375,19 @@ __global__ __launch_bounds__(256, 1) void k_gpass(const GProb* __restrict__ prob
                                                   const GItem* __restrict__ items, int nitems,
                                                   float* zpart, float* gpart) {
   __shared__ __attribute__((aligned(16))) uint8_t xl[4 * kGS * kGStage];
-  __shared__ f32x4_t ex[kGExch];
+  __shared__ f32x4_t exf[kGExch];
+  __shared__ uint4 exb[kGExchB];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem I = items[it];
     const GProb& P = probs[I.prob];
-#define PPCA_GCASE(nb, dci)                                              \
-  case (dci) * 4 + (nb) - 1:                                             \
-    run_item<nb, dci, WZ>(P, I, xl, ex, zpart, gpart);                   \
+#define PPCA_GCASE(nb2, dci)                                             \
+  case (dci) * 2 + (nb2) - 1:                                            \
+    run_item<nb2, dci, WZ>(P, I, xl, exf, exb, zpart, gpart);            \
     break;
     switch (P.cls) {
-      PPCA_GCASE(1, 0) PPCA_GCASE(2, 0) PPCA_GCASE(3, 0) PPCA_GCASE(4, 0)
-      PPCA_GCASE(1, 1) PPCA_GCASE(2, 1) PPCA_GCASE(3, 1) PPCA_GCASE(4, 1)
-      PPCA_GCASE(1, 2) PPCA_GCASE(2, 2) PPCA_GCASE(3, 2) PPCA_GCASE(4, 2)
-      PPCA_GCASE(1, 3) PPCA_GCASE(2, 3) PPCA_GCASE(3, 3) PPCA_GCASE(4, 3)
-      PPCA_GCASE(1, 4) PPCA_GCASE(2, 4) PPCA_GCASE(3, 4) PPCA_GCASE(4, 4)
+      PPCA_GCASE(1, 0) PPCA_GCASE(2, 0) PPCA_GCASE(1, 1) PPCA_GCASE(2, 1)
+      PPCA_GCASE(1, 2) PPCA_GCASE(2, 2) PPCA_GCASE(1, 3) PPCA_GCASE(2, 3)
+      PPCA_GCASE(1, 4) PPCA_GCASE(2, 4)
       default: break;
     }
 #undef PPCA_GCASE

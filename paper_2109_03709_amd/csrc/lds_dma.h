@@ -44,5 +44,24 @@ __device__ __attribute__((always_inline)) inline void dma16(const void* g, void*
                : "memory");
 }
 
+// The same with the address split into a wavefront-uniform base (SGPR pair)
+// and a 32-bit per-lane byte offset: lane i's 16 bytes at sbase + voff go to
+// LDS byte lds + 16 i.  Saves the 64-bit address arithmetic per lane.
+__device__ __attribute__((always_inline)) inline void dma16s(const void* sbase, uint32_t voff,
+                                                             void* lds) {
+  const uint32_t base = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void*)lds);
+  // readfirstlane returns a signed int: each half goes through uint32_t so
+  // that widening zero-extends it
+  const uint64_t a = (uint64_t)(uintptr_t)sbase;
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint64_t sa = ((uint64_t)hi << 32) | (uint64_t)lo;
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+               :
+               : "v"(voff), "s"(sa), "s"(base)
+               : "memory");
+}
+
 }  // namespace dma
 }  // namespace ppca

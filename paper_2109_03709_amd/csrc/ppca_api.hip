@@ -320,7 +320,7 @@ int check_group_problem(const ppca_problem& q) {
   const int rc = check_matrix(&q.X);
   if (rc != PPCA_OK) return rc;
   if (q.X.dtype != PPCA_BF16) return PPCA_ERR_DTYPE;
-  if (q.X.d > kGroupMaxD || q.k < 1 || q.l < 0) return PPCA_ERR_ARG;
+  if (q.X.d > kGroupMaxD || q.X.ld > kGroupMaxLd || q.k < 1 || q.l < 0) return PPCA_ERR_ARG;
   const int64_t K = (int64_t)q.k + q.l;
   if (K > kGroupMaxK || K > q.X.d || K > q.X.n) return PPCA_ERR_ARG;
   return PPCA_OK;
@@ -344,7 +344,7 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
     const int rc = check_group_problem(q);
     if (rc != PPCA_OK) return rc;
     const int64_t n = q.X.n, d = q.X.d;
-    const int K = q.k + q.l, Kp = (int)round_up(K, 16);
+    const int K = q.k + q.l, Kp = (int)round_up(K, 32);
     const int dci = group_dci(d), dc = group_class_width(dci), wr = group_row_groups(dci);
     GProb& P = gp.hp[p];
     P.x = reinterpret_cast<const uint16_t*>(q.X.x);
@@ -354,7 +354,7 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
     P.K = K;
     P.Kp = Kp;
     P.k = q.k;
-    P.cls = dci * 4 + Kp / 16 - 1;
+    P.cls = dci * 2 + Kp / 32 - 1;
     P.dc = dc;
     P.wr = wr;
     // work items: about kGroupItemBytes of X each, whole 16-row tiles of every row group

@@ -132,11 +132,12 @@ hipError_t launch_center_quantize(const float* x, int64_t n, int64_t d, int64_t 
 // Many independent problems in one call (k_group.hip): bf16 data with
 // d <= kGroupMaxD and K <= kGroupMaxK.  A problem belongs to the shape class
 // (dci, NB): dci picks the column split of the fused pass (class width dc =
-// 64, 128, 256, 512, 768), NB = Kp / 16.  Its rows are cut into work items;
+// 64, 128, 256, 512, 768), NB2 = Kp / 32 (K padded to 32).  Its rows are cut into work items;
 // the items of all problems are sorted by size and dealt round-robin to the
 // persistent workgroups of the fused pass.
 constexpr int kGroupMaxD = 768;
 constexpr int kGroupMaxK = 64;
+constexpr int64_t kGroupMaxLd = 1 << 24;   // 16 rows of X fit a 32-bit byte offset
 constexpr int kGroupClasses = 5;
 int group_class_width(int dci);          // dc of class dci
 int group_row_groups(int dci);           // row groups (waves sharing no rows) of class dci
@@ -145,7 +146,7 @@ int group_dci(int64_t d);                // smallest class whose width holds d
 struct GProb {
   const uint16_t* x;        // bf16 data [n][ld]
   int64_t n, d, ld;
-  int32_t K, Kp, k, cls;    // cls = dci * 4 + NB - 1
+  int32_t K, Kp, k, cls;    // cls = dci * 2 + NB2 - 1
   int32_t dc, wr;           // class width, row groups of the class
   int32_t nitem, pad;       // number of work items of the problem
   int64_t zbase, gbase;     // float offsets of its item partials: item m of the problem
