@@ -1,6 +1,7 @@
 // Device bodies of the one-workgroup dense float64 solvers, shared by the
 // single-problem kernels (k_dense.hip) and the grouped kernels (k_group.hip):
-//   chol_inv_dev  upper Cholesky factor and its inverse (256 threads),
+//   chol_inv_dev  upper Cholesky factor and its inverse (256 threads, float64
+//                 MFMAs for the block products),
 //   jacobi_dev    parallel two-sided Jacobi eigensolver (1024 threads, one
 //                 16-row block of the eigenvector matrix per workgroup).
 // Both use static LDS and report failures through the status word.
@@ -17,24 +18,24 @@ __device__ inline bool status_set(const int* status) {
 }
 
 // --------------------------------------------------------------------------
-// Upper Cholesky factor R (R^T R = A) and X = R^-1, K <= 128, one workgroup of
-// 256 threads (one wavefront per SIMD: the register file holds the unrolled
-// block steps), blocked in 16 x 16 blocks (the matrix is padded with the
+// Upper Cholesky factor R (R^T R = A) and X = R^-1, K <= KM <= 128, one
+// workgroup of 256 threads, in 16 x 16 blocks (the matrix is padded with the
 // identity to a multiple of 16; the padding factors to the identity).
 //
 // Factorisation, for each block row J (three barriers per block row):
-//   (1) wavefront 0 factors the diagonal block in registers (lane c holds
-//       column c; pivots and row entries are broadcast with readlane).  Pivot
-//       test: finite, > K * eps * |a_jj| and > 0, else NOT_SPD;
-//   (2) one thread per column c > J solves R_JJ^T R_Jc = M_Jc (forward
-//       substitution) for the row panel;
-//   (3) the rank-16 update M_ic -= R_Ji^T R_Jc of the trailing upper
-//       triangle, 4 x 4 elements per thread.
-// Inverse: the diagonal blocks are inverted in place, one wavefront each;
-// then for each block row I from the bottom: T = R_I,>I X_>I (the rows of X
-// below are final; a thread owns one column and 4 rows of T), then
-// X_I,>I = -R_II^-1 T; two barriers per block row.  T is kept in the unused
-// strict lower triangle of the matrix.
+//   (1) wavefront 0 factors the diagonal block: lane c holds column c in
+//       registers; the pivot row is broadcast through LDS (one write, then
+//       every lane reads it).  Pivot test: finite, > K * eps * |a_jj| and > 0,
+//       else NOT_SPD.  The same wavefront then inverts the block (column c of
+//       X_JJ by back substitution, columns of R_JJ read from LDS) into XD[J];
+//   (2) row panel R_J,c = X_JJ^T M_J,c (c > J), one 16 x 16 product per
+//       column block on float64 MFMAs;
+//   (3) trailing update M_ib,cb -= R_J,ib^T R_J,cb (J < ib <= cb) on MFMAs.
+// Inverse, for each block row I from the bottom (two barriers per row):
+//   T_I,cb = sum_{I < kb <= cb} R_I,kb X_kb,cb, kept transposed in the unused
+//   strict lower blocks of M, then X_I,cb = -X_II T_I,cb.
+// Column blocks are dealt round-robin to the four wavefronts.  Every sum runs
+// in a fixed order.
 // --------------------------------------------------------------------------
 __device__ inline double bcast_lane(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -42,15 +43,33 @@ __device__ inline double bcast_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// d += A B for 16 x 16 blocks over k = 0..15 on v_mfma_f64_16x16x4f64: A
+// element (i, k) = a(i, k), B element (k, j) = b(k, j).  Lane l supplies
+// A[l % 16][4 kc + l / 16] and B[4 kc + l / 16][l % 16]; d[r] is row
+// l / 16 + 4 r of column l % 16.
+template <typename FA, typename FB>
+__device__ inline f64x4_t mma16(f64x4_t d, FA a, FB b) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc)
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a(i, 4 * kc + g), b(4 * kc + g, i), d, 0, 0, 0);
+  return d;
+}
+
 template <int KM>
 __device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double* __restrict__ R,
                                     double* __restrict__ Rinv, int* status) {
-  constexpr int LDM = KM + 1, BS = 16;   // odd row stride: column reads spread banks
-  __shared__ double M[KM * LDM];
+  constexpr int LDM = KM + 1, BS = 16, NBK = KM / BS, LDX = BS + 1;
+  static_assert(KM % BS == 0 && KM <= 128, "block shape");
+  __shared__ double M[KM * LDM];      // odd row stride: column reads spread banks
+  __shared__ double XD[NBK * BS * LDX];   // inverses of the diagonal blocks
   __shared__ double dg[KM];
-  __shared__ double rcp[KM];         // 1 / r_jj
+  __shared__ double ub[BS];           // pivot row broadcast
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
   // one read of the status word for the whole workgroup (another workgroup of
   // a grouped launch may set it meanwhile)
   if (tid == 0) fail = status_set(status) ? 1 : 0;
@@ -82,39 +101,62 @@ __device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double*
   __syncthreads();
   for (int J = 0; J < nbk; ++J) {
     const int j0 = J * BS;
-    // (1) diagonal block in registers of wavefront 0 (lanes 16..63 idle)
+    // (1) diagonal block and its inverse, wavefront 0 (lanes >= 16 repeat
+    // lanes 0..15 and store nothing)
     if (wave == 0) {
-      const int c = lane & (BS - 1);
-      double col[BS];
+      const int c = l16;
+      double col[BS], rv[BS], tol[BS];
 #pragma unroll
-      for (int i = 0; i < BS; ++i) col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
+      for (int i = 0; i < BS; ++i) {
+        col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
+        tol[i] = (double)K * kEps * fabs(dg[j0 + i]);
+      }
       bool ok = true;
 #pragma unroll
       for (int p = 0; p < BS; ++p) {
-        const double piv = bcast_lane(col[p], p);
-        const int jp = j0 + p;
-        // uniform: every lane holds the same pivot; after a failure the
-        // values are garbage and are not stored
-        ok = ok && isfinite(piv) && piv > (double)K * kEps * fabs(dg[jp]) && piv > 0.0;
-        // one reciprocal square root per pivot; the row is scaled by it
-        // (shorter dependency chain than a square root and a division)
-        const double rinv = rsqrt(fabs(piv));
-        const double rpp = fabs(piv) * rinv;
-        const double u = (c > p) ? col[p] * rinv : 0.0;   // R[p][c]
-        col[p] = (c == p) ? rpp : ((c > p) ? u : col[p]);
-        if (lane == 0) rcp[jp] = rinv;
+        if (lane < BS) ub[lane] = col[p];          // row p of the block (zero left of p)
+        __builtin_amdgcn_wave_barrier();
+        double w[BS];
 #pragma unroll
-        for (int i = p + 1; i < BS; ++i) {
-          const double ui = bcast_lane(u, i);
-          if (i <= c) col[i] = fma(-ui, u, col[i]);
-        }
+        for (int i = p; i < BS; ++i) w[i] = ub[i];
+        __builtin_amdgcn_wave_barrier();
+        const double piv = w[p];
+        // uniform: every lane holds the same pivot; after a failure the
+        // values are garbage and are not stored (no short-circuit: no branch
+        // in the pivot chain)
+        ok = ok & (bool)isfinite(piv) & (piv > tol[p]) & (piv > 0.0);
+        const double rinv = rsqrt(fabs(piv));
+        rv[p] = rinv;
+        const double rpc = (c == p) ? fabs(piv) * rinv : ((c > p) ? col[p] * rinv : 0.0);
+#pragma unroll
+        for (int i = p + 1; i < BS; ++i)
+          if (i <= c) col[i] = fma(-(w[i] * rinv), rpc, col[i]);
+        col[p] = rpc;
       }
       if (!ok) {
         if (lane == 0) fail = 1;
-      } else if (lane < BS) {
+      } else {
+        if (lane < BS) {
 #pragma unroll
-        for (int i = 0; i < BS; ++i)
-          if (i <= c) M[(j0 + i) * LDM + j0 + c] = col[i];
+          for (int i = 0; i < BS; ++i)
+            if (i <= c) M[(j0 + i) * LDM + j0 + c] = col[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // column c of X_JJ: x = e_c, then for p = 15 .. 0: x_p /= r_pp and
+        // x_i -= r_ip x_p (i < p), with column p of R_JJ read from LDS
+        double x[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = BS - 1; p >= 0; --p) {
+          x[p] *= rv[p];
+#pragma unroll
+          for (int i = 0; i < p; ++i) x[i] = fma(-M[(j0 + i) * LDM + j0 + p], x[p], x[i]);
+        }
+        if (lane < BS) {
+#pragma unroll
+          for (int i = 0; i < BS; ++i) XD[J * BS * LDX + i * LDX + c] = (i <= c) ? x[i] : 0.0;
+        }
       }
     }
     __syncthreads();
@@ -122,102 +164,70 @@ __device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double*
       if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
       return;
     }
-    const int n0 = j0 + BS, N = Kp - n0;
-    if (N <= 0) break;
-    // (2) row panel R_J,c for c >= n0: forward substitution with R_JJ^T
-    for (int c = n0 + tid; c < Kp; c += blockDim.x) {
-      double x[BS];
+    if (J == nbk - 1) break;
+    // (2) row panel R_J,cb = X_JJ^T M_J,cb
+    const double* xj = XD + J * BS * LDX;
+    for (int cb = J + 1 + wave; cb < nbk; cb += 4) {
+      f64x4_t d = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      d = mma16(d, [&](int i, int k) { return xj[k * LDX + i]; },
+                [&](int k, int j) { return M[(j0 + k) * LDM + cb * BS + j]; });
 #pragma unroll
-      for (int p = 0; p < BS; ++p) {
-        double sacc = M[(j0 + p) * LDM + c];
-#pragma unroll
-        for (int q = 0; q < p; ++q) sacc = fma(-M[(j0 + q) * LDM + j0 + p], x[q], sacc);
-        x[p] = sacc * rcp[j0 + p];
-        M[(j0 + p) * LDM + c] = x[p];
-      }
+      for (int r = 0; r < 4; ++r) M[(j0 + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
     }
     __syncthreads();
-    // (3) trailing update of the upper triangle, 4 x 4 per thread
-    const int n4 = N / 4;
-    for (int blk = tid; blk < n4 * n4; blk += blockDim.x) {
-      const int bi = blk / n4, bj = blk - bi * n4;
-      if (bi > bj) continue;
-      const int gi = n0 + 4 * bi, gc = n0 + 4 * bj;
-      double acc[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = M[(gi + u) * LDM + gc + v];
-#pragma unroll
-      for (int p = 0; p < BS; ++p) {
-        double ra[4], rb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ra[u] = M[(j0 + p) * LDM + gi + u];
-          rb[u] = M[(j0 + p) * LDM + gc + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(-ra[u], rb[v], acc[u][v]);
+    // (3) trailing update of the upper blocks (ib, cb), J < ib <= cb
+    const int nt = nbk - 1 - J;
+    for (int q = wave; q < nt * (nt + 1) / 2; q += 4) {
+      int ib = 0, rem = q;
+      while (rem >= nt - ib) {
+        rem -= nt - ib;
+        ++ib;
       }
+      const int cb = J + 1 + ib + rem;
+      ib += J + 1;
+      f64x4_t d;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int r = 0; r < 4; ++r) d[r] = M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16];
+      d = mma16(d, [&](int i, int k) { return -M[(j0 + k) * LDM + ib * BS + i]; },
+                [&](int k, int j) { return M[(j0 + k) * LDM + cb * BS + j]; });
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (gi + u <= gc + v) M[(gi + u) * LDM + gc + v] = acc[u][v];
+      for (int r = 0; r < 4; ++r)
+        if (ib != cb || g4 + 4 * r <= l16) M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
     }
     __syncthreads();
   }
-  // R out (upper triangle; the strict lower part of M is scratch from here on)
+  // R out (upper triangle)
   for (int e = tid; e < K * K; e += blockDim.x) {
     const int i = e / K, c = e - i * K;
     R[e] = c >= i ? M[i * LDM + c] : 0.0;
   }
   __syncthreads();   // R is read out before the diagonal blocks are overwritten
-  // diagonal blocks -> their inverses, in place (wave w takes blocks w, w + 4, ..;
-  // lanes 0..15 own columns)
-  for (int Jd = wave; Jd < nbk; Jd += 4) {
-    const int j0 = Jd * BS, c = lane;
-    if (c < BS) {
-      double x[BS];
-#pragma unroll
-      for (int p = BS - 1; p >= 0; --p) {
-        double sacc = (p == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = p + 1; q < BS; ++q) sacc = fma(-M[(j0 + p) * LDM + j0 + q], x[q], sacc);
-        x[p] = (p <= c) ? sacc * rcp[j0 + p] : 0.0;
-      }
-      // every lane of the wave has read the block before any lane writes it
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int p = 0; p < BS; ++p)
-        if (p <= c) M[(j0 + p) * LDM + j0 + c] = x[p];
-    }
+  // diagonal blocks -> their inverses
+  for (int e = tid; e < nbk * BS * BS; e += blockDim.x) {
+    const int J = e / (BS * BS), i = (e / BS) % BS, c = e % BS;
+    if (i <= c) M[(J * BS + i) * LDM + J * BS + c] = XD[J * BS * LDX + i * LDX + c];
   }
   __syncthreads();
   for (int I = nbk - 2; I >= 0; --I) {
-    const int i0 = I * BS, n0 = i0 + BS, N = Kp - n0;
-    // T[r][c] = sum_{k = n0 .. c} R[i0 + r][k] X[k][c], kept transposed at
-    // M[c][i0 + r]; thread (c, r4) owns rows 4 r4 .. 4 r4 + 3 of column c
-    for (int e = tid; e < 4 * N; e += blockDim.x) {
-      const int r4 = e / N, c = n0 + (e - r4 * N);
-      double t4[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int k2 = n0; k2 <= c; ++k2) {
-        const double xk = M[k2 * LDM + c];
+    const int i0 = I * BS;
+    // T_I,cb, stored transposed: T[r][c] at M[c][i0 + r]
+    for (int cb = I + 1 + wave; cb < nbk; cb += 4) {
+      f64x4_t d = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kb = I + 1; kb <= cb; ++kb)
+        d = mma16(d, [&](int i, int k) { return M[(i0 + i) * LDM + kb * BS + k]; },
+                  [&](int k, int j) { return M[(kb * BS + k) * LDM + cb * BS + j]; });
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t4[u] = fma(M[(i0 + 4 * r4 + u) * LDM + k2], xk, t4[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) M[c * LDM + i0 + 4 * r4 + u] = t4[u];
+      for (int r = 0; r < 4; ++r) M[(cb * BS + l16) * LDM + i0 + g4 + 4 * r] = d[r];
     }
     __syncthreads();
-    // X[i0 + r][c] = -sum_{q >= r} Xdiag[r][q] T[q][c]
-    for (int e = tid; e < BS * N; e += blockDim.x) {
-      const int r = e / N, c = n0 + (e - r * N);
-      double sacc = 0.0;
-      for (int q = r; q < BS; ++q) sacc = fma(M[(i0 + r) * LDM + i0 + q], M[c * LDM + i0 + q], sacc);
-      M[(i0 + r) * LDM + c] = -sacc;
+    // X_I,cb = -X_II T_I,cb
+    const double* xi = XD + I * BS * LDX;
+    for (int cb = I + 1 + wave; cb < nbk; cb += 4) {
+      f64x4_t d = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      d = mma16(d, [&](int i, int k) { return -xi[i * LDX + k]; },
+                [&](int k, int j) { return M[(cb * BS + j) * LDM + i0 + k]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) M[(i0 + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
     }
     __syncthreads();
   }

@@ -54,7 +54,6 @@ namespace {
 using namespace dma;
 using dev::status_set;
 
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 template <int NB2, int DCI>
 struct GCls {

@@ -10,8 +10,12 @@
 //   reduce_zg : fixed-order float64 sum of the partials -> Z (f32), G (f64)
 //
 // The projection pass only needs G, so it runs the Y = X V' kernel alone
-// (one read of X, no Y written).  bf16 and fp8 data run on
-// v_mfma_f32_16x16x32_bf16, float32 data on v_mfma_f32_16x16x4_f32.
+// (one read of X, no Y written).  Y = X V' of bf16 data with Kp a multiple
+// of 32 runs on v_mfma_f32_32x32x16_bf16 (with one wave per SIMD it sustains
+// about 2.5 times the rate of the 16x16 shapes); the other products of bf16
+// and fp8 data on v_mfma_f32_16x16x32_bf16 (for X^T Y, whose A operand is a
+// transpose read from LDS, the 32x32 shape measured slower), float32 data on
+// v_mfma_f32_16x16x4_f32.
 // Accumulation inside a workgroup is float32; partials are summed in float64
 // in a fixed order, so results are bitwise reproducible run to run.
 //
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
   __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
   __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
 
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int a = lane & 15, g = lane >> 4;
   const int64_t ntile = (rows + WGR - 1) / WGR;
   const int nk = (int)((d + KS - 1) / KS);
@@ -492,11 +496,23 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
   }
 
-  f32x4_t acc[MW][NB];
+  // bf16 data with 32-row blocks per wave and Kp a multiple of 32, Y only:
+  // 32x32x16 MFMAs (acc2[mb][nb], rows 32 mb of the wave, columns 32 nb);
+  // otherwise 16x16 MFMAs (acc[mb][nb]).  The G accumulators of the
+  // projection variants leave no registers for the 32x32 pipeline.
+  constexpr bool M32 = DT == DT_BF16 && MW % 2 == 0 && NB % 2 == 0 && !WANT_G;
+  constexpr int M2 = M32 ? MW / 2 : 1, N2 = M32 ? NB / 2 : 1;
+  f32x4_t acc[M32 ? 1 : MW][M32 ? 1 : NB];
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb)
+  for (int mb = 0; mb < (M32 ? 1 : MW); ++mb)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < (M32 ? 1 : NB); ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  f32x16_t acc2[M2][N2];
+#pragma unroll
+  for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < N2; ++nb) acc2[mb][nb] = f32x16_t{};
+  const int l32 = lane & 31, hl = lane >> 5;
   f32x4_t accg[NB][NBG];
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb)
@@ -564,6 +580,29 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].w, bf[nb].w, acc[mb][nb], 0, 0, 0);
             }
         }
+      } else if constexpr (M32) {
+        // 16-column substeps: lane (l32, hl) holds row l32 of its block, chunk 2 s4 + hl
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          uint4 af[M2], bf[N2];
+          const int c = 2 * s4 + hl;
+#pragma unroll
+          for (int mb = 0; mb < M2; ++mb) {
+            const int r = w * MW * 16 + mb * 32 + l32;
+            af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int nb = 0; nb < N2; ++nb) {
+            const int r = nb * 32 + l32;
+            bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+          }
+#pragma unroll
+          for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < N2; ++nb)
+              acc2[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  as_bf16x8(af[mb]), as_bf16x8(bf[nb]), acc2[mb][nb], 0, 0, 0);
+        }
       } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -613,8 +652,30 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     // ---- Y tile -> LDS, layout [row/YR][Kp][YR]; rows [0, WGR/2) in st0, the
     // rest in st1.  Rows past the pass are written as zeros.
     const int64_t vrows = rows - row0;        // valid rows of this tile
+    if constexpr (M32) {
+      // element i of acc2[mb][nb]: row 32 mb + 8 (i / 4) + 4 hl + i % 4 of the
+      // wave's block, column 32 nb + l32
 #pragma unroll
-    for (int mb = 0; mb < MW; ++mb) {
+      for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int lr = w * MW * 16 + mb * 32 + 8 * j + 4 * hl;
+          uint8_t* yh = lr < WGR / 2 ? st0 : st1;
+          const int hr = lr & (WGR / 2 - 1);
+#pragma unroll
+          for (int nb = 0; nb < N2; ++nb) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (lr + u < vrows) ? acc2[mb][nb][4 * j + u] : 0.f;
+            uint2 wv;
+            wv.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+            wv.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+            *reinterpret_cast<uint2*>(yh + ((hr >> 3) * Kp + nb * 32 + l32) * 16 + (hr & 7) * 2) = wv;
+          }
+        }
+    }
+#pragma unroll
+    for (int mb = 0; mb < (M32 ? 0 : MW); ++mb) {
       const int lr = w * MW * 16 + mb * 16 + 4 * g;
       uint8_t* yh = lr < WGR / 2 ? st0 : st1;
       const int hr = lr & (WGR / 2 - 1);
@@ -698,9 +759,15 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     // allocator rotate the accumulators through extra registers in the k-loop)
     const float zero = __uint_as_float(~keep);
 #pragma unroll
-    for (int mb = 0; mb < MW; ++mb)
+    for (int mb = 0; mb < (M32 ? 1 : MW); ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
+      for (int nb = 0; nb < (M32 ? 1 : NB); ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
+#pragma unroll
+    for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc2[mb][nb][i] = zero;
     wait_lgkm0();
     raw_barrier();                           // the next tile's DMAs overwrite the Y tile
   }
@@ -781,7 +848,7 @@ __global__ __launch_bounds__(256, 1) void k_xtyd(const uint8_t* x, int64_t n, in
   __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
   __shared__ __attribute__((aligned(16))) uint8_t st3[STB];
 
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int a = lane & 15, g = lane >> 4;
   int tile, split;
   if (!xty_tile_split(ntiles, nsplit, tile, split)) return;
