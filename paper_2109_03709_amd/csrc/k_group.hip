@@ -465,6 +465,7 @@ __global__ __launch_bounds__(256) void k_greduce(const GProb* __restrict__ probs
 // One-workgroup dense float64 helpers (256 threads, K <= 64).
 // ---------------------------------------------------------------------------
 constexpr int kGStg = 64;   // rows staged per step
+constexpr int kGSp = 65;    // LDS row stride of a stage (odd: column reads spread banks)
 
 // 64 x 64 stage of a rows x K block (zero outside): thread t holds elements
 // t + 256 m (row e >> 6, column e & 63).  Loads use clamped indices and no
@@ -482,31 +483,35 @@ __device__ inline void stage_load(Load load, int64_t r0, int64_t rows, int K, do
 }
 __device__ inline void stage_store(const double (&reg)[16], double* stg) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) stg[threadIdx.x + 256 * m] = reg[m];
+  for (int m = 0; m < 16; ++m) {
+    const int e = threadIdx.x + 256 * m;
+    stg[(e >> 6) * kGSp + (e & 63)] = reg[m];
+  }
 }
 
-// out[i][c] = sum_r a(r, i) a(r, c) for a rows x K block, rows in order;
-// thread t owns the 4 x 4 tile t of the upper triangle (tiles of the 16 x 16
-// tile grid of a 64-wide matrix: at most 136 tiles).  out: global K x K, both
-// triangles written.  stg: LDS [kGStg][64]; the next stage is prefetched into
-// registers while the current one is used.
+// out[i][c] = sum_r a(r, i) a(r, c) for a rows x K block on float64 MFMAs:
+// the 16 x 16 blocks (ib <= jb) of the upper triangle are dealt to the four
+// wavefronts (at most 3 each), which keep their accumulators across stages;
+// each stage adds its 64 rows in order, 4 per MFMA.  out: global K x K, both
+// triangles written.  stg: LDS [kGStg][kGSp]; the next stage is prefetched
+// into registers while the current one is used.
 template <typename Load>
 __device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, double* stg) {
-  const int t = threadIdx.x;
-  const int nt = (K + 3) / 4;
-  const int ntile = nt * (nt + 1) / 2;
-  int ti = 0, rem = t;
-  while (ti < nt && rem >= nt - ti) {
-    rem -= nt - ti;
-    ++ti;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, g4 = lane >> 4;
+  const int nbk = (K + 15) / 16, npair = nbk * (nbk + 1) / 2;
+  int pib[3], pjb[3];
+  dev::f64x4_t acc[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    int ib = 0, rem = wave + 4 * s;
+    while (ib < nbk && rem >= nbk - ib) {
+      rem -= nbk - ib;
+      ++ib;
+    }
+    pib[s] = ib;
+    pjb[s] = ib + rem;
+    acc[s] = dev::f64x4_t{0.0, 0.0, 0.0, 0.0};
   }
-  const int tj = ti + rem;
-  const bool act = t < ntile;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   double nxt[16];
   stage_load(load, 0, rows, K, nxt);
   for (int64_t r0 = 0; r0 < rows; r0 += kGStg) {
@@ -514,47 +519,42 @@ __device__ inline void gram_wg(Load load, int64_t rows, int K, double* out, doub
     stage_store(nxt, stg);
     __syncthreads();
     if (r0 + kGStg < rows) stage_load(load, r0 + kGStg, rows, K, nxt);
-    if (act) {
-      for (int rr = 0; rr < kGStg; ++rr) {
-        double av[4], bv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          av[u] = stg[rr * 64 + 4 * ti + u];
-          bv[u] = stg[rr * 64 + 4 * tj + u];
-        }
+    for (int s = 0; s < 3; ++s) {
+      if (wave + 4 * s >= npair) break;
+      const int ci = 16 * pib[s] + l16, cj = 16 * pjb[s] + l16;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+      for (int kc = 0; kc < kGStg / 4; ++kc) {
+        const double* row = stg + (4 * kc + g4) * kGSp;
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[ci], row[cj], acc[s], 0, 0, 0);
       }
     }
   }
-  if (act) {
+  // acc[s][r]: row 16 ib + g4 + 4 r, column 16 jb + l16
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+  for (int s = 0; s < 3; ++s) {
+    if (wave + 4 * s >= npair) break;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * ti + u, c = 4 * tj + v;
-        if (i < K && c < K) {
-          out[i * K + c] = acc[u][v];
-          out[c * K + i] = acc[u][v];
-        }
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * pib[s] + g4 + 4 * r, c = 16 * pjb[s] + l16;
+      if (i < K && c < K && i <= c) {
+        out[i * K + c] = acc[s][r];
+        out[c * K + i] = acc[s][r];
       }
+    }
   }
   __syncthreads();
 }
 
-// out(r, c) = sum_{p <= c} a(r, p) Rinv[p][c] (p ascending) for a rows x K
-// block; Rl: LDS [64][64] copy of Rinv (zero below the diagonal), stg: LDS
-// [kGStg][64].  Thread (c = t % K, g = t / K) computes column c of the stage
-// rows g, g + ng, ... (ng = 256 / K): independent accumulation chains.
+// out(r, c) = sum_{p <= c} a(r, p) Rinv[p][c] for a rows x K block on float64
+// MFMAs; Rl: LDS [64][64] copy of Rinv (zero below the diagonal and past K),
+// stg: LDS [kGStg][kGSp].  Wavefront w takes the 16-row chunk w of every
+// stage and all column blocks cb, summing the blocks p in 16 (cb + 1) in order.
 template <typename Load, typename Store>
 __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rinv, double* Rl,
                                double* stg, Store store) {
-  const int t = threadIdx.x;
-  const int ng = 256 / K;
-  const bool act = t < ng * K;
-  const int c = t % K, g = t / K;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, g4 = lane >> 4;
+  const int nbk = (K + 15) / 16;
   __syncthreads();
   for (int e = t; e < 64 * 64; e += 256) {
     const int i = e >> 6, cc = e & 63;
@@ -567,22 +567,18 @@ __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rin
     stage_store(nxt, stg);
     __syncthreads();
     if (r0 + kGStg < rows) stage_load(load, r0 + kGStg, rows, K, nxt);
-    if (act) {
-      double s[16];
+    const double* arow = stg + (16 * wave) * kGSp;
+    for (int cb = 0; cb < nbk; ++cb) {
+      dev::f64x4_t d = dev::f64x4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kb = 0; kb <= cb; ++kb)
+        d = dev::mma16(d, [&](int i, int k) { return arow[i * kGSp + 16 * kb + k]; },
+                       [&](int k, int j) { return Rl[(16 * kb + k) * 64 + 16 * cb + j]; });
+      // d[r]: stage row 16 wave + g4 + 4 r, column 16 cb + l16
+      const int c = 16 * cb + l16;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s[q] = 0.0;
-      for (int p = 0; p <= c; ++p) {
-        const double rv = Rl[p * 64 + c];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int rr = g + ng * q;
-          if (rr < kGStg) s[q] = fma(stg[rr * 64 + p], rv, s[q]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int rr = g + ng * q;
-        if (rr < kGStg && r0 + rr < rows) store(r0 + rr, c, s[q]);
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = r0 + 16 * wave + g4 + 4 * r;
+        if (rr < rows && c < K) store(rr, c, d[r]);
       }
     }
   }
@@ -595,7 +591,7 @@ __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rin
 __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ probs,
                                                   const int* __restrict__ order, int from_v,
                                                   int want_b, int* status) {
-  __shared__ double stg[kGStg * 64];
+  __shared__ double stg[kGStg * kGSp];
   __shared__ double Rl[64 * 64];
   const GProb& P = probs[order[blockIdx.x]];
   const int64_t d = P.d;
