@@ -167,7 +167,9 @@ int ppca_prime_eigengame(const ppca_matrix* X, int32_t k, int32_t l,
  * Z = X^T Y (d x K float32, float32 accumulation within a row split, float64
  * across splits) and G = Y^T Y (K x K float64).  V' is the operand described
  * at ppca_project_gram; Z and G are unnormalised sums over the rows.
- * 0 <= r0 < n, 1 <= nrows.  Workspace: PPCA_OP_STREAM with batch = nrows. */
+ * G may be NULL: then only Z is computed, by the same kernels as a block
+ * power step.  0 <= r0 < n, 1 <= nrows.  Workspace: PPCA_OP_STREAM with
+ * batch = nrows. */
 int ppca_stream_pass(const ppca_matrix* X, int32_t K, const float* V, int64_t r0,
                      int64_t nrows, float* Z, double* G,
                      void* ws, size_t ws_bytes, void* stream);

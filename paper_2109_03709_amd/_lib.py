@@ -226,17 +226,18 @@ def prime_eigengame(X: Data, k: int, l: int, V: torch.Tensor, **kw) -> torch.Ten
 
 
 def stream_pass(X: Data, K: int, V: torch.Tensor, r0: int = 0, nrows: int | None = None,
-                ws=None):
-    """(Z d x K float32, G K x K float64) of one pass over rows r0.. (mod n)."""
+                ws=None, want_g: bool = True):
+    """(Z d x K float32, G K x K float64) of one pass over rows r0.. (mod n);
+    G is None when want_g is False (Z alone, as in a block power step)."""
     _check_v(V, X.d, K)
     nrows = X.n if nrows is None else nrows
     Z = torch.empty((X.d, K), dtype=torch.float32, device=V.device)
-    G = torch.empty((K, K), dtype=torch.float64, device=V.device)
+    G = torch.empty((K, K), dtype=torch.float64, device=V.device) if want_g else None
     m = X.as_c()
     if ws is None:
         ws = _workspace(workspace_bytes(OP_STREAM, X, K, nrows), V.device)
-    code = lib().ppca_stream_pass(ctypes.byref(m), K, _ptr(V), r0, nrows, _ptr(Z), _ptr(G),
-                                  _ptr(ws), ws.numel(), _stream())
+    code = lib().ppca_stream_pass(ctypes.byref(m), K, _ptr(V), r0, nrows, _ptr(Z),
+                                  _ptr(G), _ptr(ws), ws.numel(), _stream())
     _check(code, "ppca_stream_pass")
     return Z, G
 

@@ -6,15 +6,18 @@
 //               LDS-DMA stages)
 //   k_xv      : the same for fp8 data (register-staged pipeline; fp8 codes
 //               are widened to bf16 exactly when read from LDS)
+//   k_xvy     : Y = X V' of the power pass for bf16 data (one DMA pipeline
+//               over all tiles of a workgroup, Y stored from the accumulators)
 //   k_xtyd    : Z = X^T Y over (256-column tile, row split) pairs (LDS-DMA)
 //   reduce_zg : fixed-order float64 sum of the partials -> Z (f32), G (f64)
 //
 // The projection pass only needs G, so it runs the Y = X V' kernel alone
-// (one read of X, no Y written).  Y = X V' of bf16 data with Kp a multiple
-// of 32 runs on v_mfma_f32_32x32x16_bf16 (with one wave per SIMD it sustains
-// about 2.5 times the rate of the 16x16 shapes); the other products of bf16
-// and fp8 data on v_mfma_f32_16x16x32_bf16 (for X^T Y, whose A operand is a
-// transpose read from LDS, the 32x32 shape measured slower), float32 data on
+// (one read of X, no Y written).  The power pass of bf16 data with Kp a
+// multiple of 32 over 256-row tiles (k_xvy) runs on v_mfma_f32_32x32x16_bf16
+// (with one wave per SIMD it sustains about 2.5 times the rate of the 16x16
+// shapes); the other products of bf16 and fp8 data on
+// v_mfma_f32_16x16x32_bf16 (for X^T Y, whose A operand is a transpose read
+// from LDS, the 32x32 shape measured slower), float32 data on
 // v_mfma_f32_16x16x4_f32.
 // Accumulation inside a workgroup is float32; partials are summed in float64
 // in a fixed order, so results are bitwise reproducible run to run.
@@ -496,23 +499,11 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
   }
 
-  // bf16 data with 32-row blocks per wave and Kp a multiple of 32, Y only:
-  // 32x32x16 MFMAs (acc2[mb][nb], rows 32 mb of the wave, columns 32 nb);
-  // otherwise 16x16 MFMAs (acc[mb][nb]).  The G accumulators of the
-  // projection variants leave no registers for the 32x32 pipeline.
-  constexpr bool M32 = DT == DT_BF16 && MW % 2 == 0 && NB % 2 == 0 && !WANT_G;
-  constexpr int M2 = M32 ? MW / 2 : 1, N2 = M32 ? NB / 2 : 1;
-  f32x4_t acc[M32 ? 1 : MW][M32 ? 1 : NB];
+  f32x4_t acc[MW][NB];
 #pragma unroll
-  for (int mb = 0; mb < (M32 ? 1 : MW); ++mb)
+  for (int mb = 0; mb < MW; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < (M32 ? 1 : NB); ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  f32x16_t acc2[M2][N2];
-#pragma unroll
-  for (int mb = 0; mb < M2; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < N2; ++nb) acc2[mb][nb] = f32x16_t{};
-  const int l32 = lane & 31, hl = lane >> 5;
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   f32x4_t accg[NB][NBG];
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb)
@@ -580,29 +571,6 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb].w, bf[nb].w, acc[mb][nb], 0, 0, 0);
             }
         }
-      } else if constexpr (M32) {
-        // 16-column substeps: lane (l32, hl) holds row l32 of its block, chunk 2 s4 + hl
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          uint4 af[M2], bf[N2];
-          const int c = 2 * s4 + hl;
-#pragma unroll
-          for (int mb = 0; mb < M2; ++mb) {
-            const int r = w * MW * 16 + mb * 32 + l32;
-            af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
-          }
-#pragma unroll
-          for (int nb = 0; nb < N2; ++nb) {
-            const int r = nb * 32 + l32;
-            bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
-          }
-#pragma unroll
-          for (int mb = 0; mb < M2; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < N2; ++nb)
-              acc2[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  as_bf16x8(af[mb]), as_bf16x8(bf[nb]), acc2[mb][nb], 0, 0, 0);
-        }
       } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -652,30 +620,8 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     // ---- Y tile -> LDS, layout [row/YR][Kp][YR]; rows [0, WGR/2) in st0, the
     // rest in st1.  Rows past the pass are written as zeros.
     const int64_t vrows = rows - row0;        // valid rows of this tile
-    if constexpr (M32) {
-      // element i of acc2[mb][nb]: row 32 mb + 8 (i / 4) + 4 hl + i % 4 of the
-      // wave's block, column 32 nb + l32
 #pragma unroll
-      for (int mb = 0; mb < M2; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int lr = w * MW * 16 + mb * 32 + 8 * j + 4 * hl;
-          uint8_t* yh = lr < WGR / 2 ? st0 : st1;
-          const int hr = lr & (WGR / 2 - 1);
-#pragma unroll
-          for (int nb = 0; nb < N2; ++nb) {
-            float v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = (lr + u < vrows) ? acc2[mb][nb][4 * j + u] : 0.f;
-            uint2 wv;
-            wv.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
-            wv.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
-            *reinterpret_cast<uint2*>(yh + ((hr >> 3) * Kp + nb * 32 + l32) * 16 + (hr & 7) * 2) = wv;
-          }
-        }
-    }
-#pragma unroll
-    for (int mb = 0; mb < (M32 ? 0 : MW); ++mb) {
+    for (int mb = 0; mb < MW; ++mb) {
       const int lr = w * MW * 16 + mb * 16 + 4 * g;
       uint8_t* yh = lr < WGR / 2 ? st0 : st1;
       const int hr = lr & (WGR / 2 - 1);
@@ -759,15 +705,9 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     // allocator rotate the accumulators through extra registers in the k-loop)
     const float zero = __uint_as_float(~keep);
 #pragma unroll
-    for (int mb = 0; mb < (M32 ? 1 : MW); ++mb)
+    for (int mb = 0; mb < MW; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < (M32 ? 1 : NB); ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
-#pragma unroll
-    for (int mb = 0; mb < M2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < N2; ++nb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc2[mb][nb][i] = zero;
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{zero, zero, zero, zero};
     wait_lgkm0();
     raw_barrier();                           // the next tile's DMAs overwrite the Y tile
   }
@@ -788,6 +728,190 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
         }
       }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Y = X V' of the power pass (bf16 data, Kp a multiple of 32, 256-row tiles,
+// Y only).  The work split and LDS stages are those of k_xvd, but the DMA
+// pipeline runs without a break over all (tile, k-step) pairs of the
+// workgroup: the DMAs of the next tile's first steps are in flight while the
+// current tile finishes, and the Y tile goes from the 32x32x16 accumulators
+// straight to the blocked staging layout in global memory (no LDS copy, no
+// barrier).  Element i of acc2[mb][nb] of lane (l32, hl) is row
+// w * 64 + 32 mb + 8 (i / 4) + 4 hl + i % 4 of the tile, column 32 nb + l32;
+// its four rows 8 j + 4 hl .. + 3 are one 8-byte piece of a 16-byte Y chunk,
+// so each store writes 512 contiguous bytes per wavefront.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256, 1) void k_xvy(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                                int64_t rstart, int64_t rows, const uint8_t* vop,
+                                                int64_t dp, uint8_t* yb) {
+  static_assert(NB % 2 == 0, "Kp a multiple of 32");
+  constexpr int Kp = NB * 16, N2 = NB / 2, M2 = 2;
+  constexpr int EB = 2, KS = 64, MW = 4, WGR = 64 * MW;
+  constexpr int XSB = WGR * 128, VSB = Kp * 128, STB = XSB + VSB;
+  constexpr int XI = WGR / 32, VBLK = Kp / 8, VI = (VBLK + 3) / 4, DPS = XI + VI;
+  static_assert(2 * DPS < 64, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) uint8_t st[3 * STB];
+
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int l32 = lane & 31, hl = lane >> 5;
+  const int64_t ntile = (rows + WGR - 1) / WGR;
+  const int64_t mytiles = ntile > blockIdx.x ? (ntile - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int nk = (int)((d + KS - 1) / KS);
+  const int64_t nsteps = mytiles * nk;
+  if (nsteps == 0) return;
+  const int64_t klast = (int64_t)(nk - 1) * KS;
+  const int64_t dtail = d % (16 / EB);
+
+  // DMA sources, as in k_xvd
+  const int p8 = lane & 7;
+  int xc[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = 8 * (w * XI + j) + (lane >> 3);
+    xc[j] = (p8 ^ (r & 7)) * (16 / EB);
+  }
+  const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
+  int64_t xrow[XI];
+  const uint8_t* xsrc[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = 8 * (w * XI + j) + (lane >> 3);
+    xrow[j] = (rstart + (int64_t)blockIdx.x * WGR + r) % n;
+    xsrc[j] = x + xrow[j] * ld * EB;
+  }
+  const uint8_t* vsrc[VI];
+  int vblk[VI];
+#pragma unroll
+  for (int j = 0; j < VI; ++j) {
+    const int blk = (w * VI + j) % VBLK;
+    const int r = 8 * blk + (lane >> 3);
+    vblk[j] = blk;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+  }
+  // stage b of the ring (b is wavefront-uniform)
+  auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* { return st + b * STB; };
+  // issue side: next step iss = (tile ordinal, k-step ik); past the last
+  // step the last one is loaded again (every wave issues the same count)
+  int64_t iss = 0;
+  int ik = 0;
+  auto issue = [&](int b) __attribute__((always_inline)) {
+    uint8_t* sb = stage(b);
+    const int64_t k0 = iss < nsteps ? (int64_t)ik * KS : klast;
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int64_t col = k0 + xc[j];
+      dma16(xsrc[j] + (col < d ? col : 0) * EB, sb + (w * XI + j) * 1024);
+    }
+#pragma unroll
+    for (int j = 0; j < VI; ++j) dma16(vsrc[j] + k0 * EB, sb + XSB + vblk[j] * 1024);
+    if (iss < nsteps) {
+      ++iss;
+      if (++ik == nk) {
+        if (iss < nsteps) {
+          ik = 0;
+#pragma unroll
+          for (int j = 0; j < XI; ++j) {
+            const int64_t nr = xrow[j] + tstep;
+            xrow[j] = nr >= n ? nr - n : nr;
+            xsrc[j] = x + xrow[j] * ld * EB;
+          }
+        } else {
+          ik = nk - 1;
+        }
+      }
+    }
+  };
+  auto fix_tail = [&](int b) __attribute__((always_inline)) {
+    uint8_t* sb = stage(b);
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      uint4* slot = reinterpret_cast<uint4*>(sb + (w * XI + j) * 1024 + lane * 16);
+      *slot = and4(*slot, chunk_mask<EB>(klast + xc[j], d));
+    }
+  };
+
+  f32x16_t acc2[M2][N2];
+#pragma unroll
+  for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < N2; ++nb) acc2[mb][nb] = f32x16_t{};
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    const uint8_t* xs = stage(b);
+    const uint8_t* vs = xs + XSB;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      uint4 af[M2], bf[N2];
+      const int c = 2 * s4 + hl;
+#pragma unroll
+      for (int mb = 0; mb < M2; ++mb) {
+        const int r = w * MW * 16 + mb * 32 + l32;
+        af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+      }
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb) {
+        const int r = nb * 32 + l32;
+        bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+      }
+#pragma unroll
+      for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < N2; ++nb)
+          acc2[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(af[mb]), as_bf16x8(bf[nb]),
+                                                                 acc2[mb][nb], 0, 0, 0);
+    }
+  };
+  // Y tile of tile ordinal ct from the accumulators; rows past the pass are zero
+  const uint32_t keep = dp > 0 ? 0xFFFFFFFFu : 0u;   // all ones, opaque to the compiler
+  auto store_y = [&](int64_t ct) __attribute__((always_inline)) {
+    const int64_t row0 = ((int64_t)blockIdx.x + ct * gridDim.x) * WGR;
+    const int64_t vrows = rows - row0;
+    uint8_t* ybase = yb + (row0 / 8) * Kp * 16;
+#pragma unroll
+    for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lr = w * MW * 16 + mb * 32 + 8 * j + 4 * hl;
+#pragma unroll
+        for (int nb = 0; nb < N2; ++nb) {
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = (lr + u < vrows) ? acc2[mb][nb][4 * j + u] : 0.f;
+          uint2 wv;
+          wv.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+          wv.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+          *reinterpret_cast<uint2*>(ybase + ((lr >> 3) * Kp + nb * 32 + l32) * 16 + (lr & 7) * 2) = wv;
+        }
+      }
+    // cleared with a zero the compiler cannot see through (see k_xvd)
+    const float zero = __uint_as_float(~keep);
+#pragma unroll
+    for (int mb = 0; mb < M2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc2[mb][nb][i] = zero;
+  };
+
+  issue(0);
+  issue(1);
+  int b = 0;           // stage of the step being computed
+  for (int64_t ct = 0; ct < mytiles; ++ct) {
+    for (int kk = 0; kk < nk; ++kk) {
+      wait_vmcnt<DPS>();                   // this wave's DMA of the step has landed
+      if (dtail != 0 && kk == nk - 1) {
+        fix_tail(b);
+        wait_lgkm0();                      // the cleared chunks are written before the barrier
+      }
+      raw_barrier();                       // ... and every wave's; stage (b+2)%3 is free
+      issue(b == 0 ? 2 : b - 1);
+      compute(b);
+      b = b == 2 ? 0 : b + 1;
+    }
+    store_y(ct);
+  }
+  wait_vmcnt<0>();
 }
 
 // Block id -> (tile, split).  Block b runs on XCD b mod 8; XCD x takes the
@@ -1152,6 +1276,9 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
       } else {
         if (mw == 1) {
           go(k_xvd<NB, DT, 1, WY, WG>);
+        } else if constexpr (DT == DT_BF16 && NB % 2 == 0 && WY && !WG) {
+          hipLaunchKernelGGL(k_xvy<NB>, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
+                             p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb);
         } else {
           if constexpr (NB > xv_wide_nb(DT)) go(k_xvd<NB, DT, 2, WY, WG>);
           else go(k_xvd<NB, DT, 4, WY, WG>);

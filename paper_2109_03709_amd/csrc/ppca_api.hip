@@ -591,7 +591,7 @@ int ppca_prime_eigengame(const ppca_matrix* X, int32_t k, int32_t l, const ppca_
 int ppca_stream_pass(const ppca_matrix* X, int32_t K, const float* V, int64_t r0, int64_t nrows,
                      float* Z, double* G, void* ws, size_t ws_bytes, void* stream) {
   RET_IF(check_matrix(X));
-  if (!V || !Z || !G || r0 < 0 || r0 >= X->n || nrows < 1) return PPCA_ERR_ARG;
+  if (!V || !Z || r0 < 0 || r0 >= X->n || nrows < 1) return PPCA_ERR_ARG;
   RET_IF(check_k(X, K));
   const Plan p = make_plan(PPCA_OP_STREAM, X->n, X->d, X->dtype, K, nrows);
   RET_IF(check_ws(ws, ws_bytes, p));

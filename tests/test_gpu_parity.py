@@ -106,6 +106,33 @@ def test_stream_pass_elementwise_bound(dtype, n, d, K, r0, rows):
     assert gram_err(G.cpu().numpy(), g_ref) < (2e-5 if dtype == F32 else 4e-3)
 
 
+@pytest.mark.parametrize("dtype,K,want_g", [(BF16, 32, False), (BF16, 64, False), (BF16, 48, False),
+                                             (BF16, 64, True), (F32, 64, False), (FP8, 64, False)])
+def test_stream_pass_wide_tiles(dtype, K, want_g):
+    """Passes of at least 65,536 rows run on 256-row tiles (Y = X V' of the
+    power step: one DMA pipeline over all tiles of a workgroup, Y stored from
+    the accumulators; bf16 with K a multiple of 32 on 32x32x16 MFMAs).
+    n = 140,001 gives every workgroup two or three tiles and a partial last
+    tile; d = 300 ends inside a k-step and inside a 16-byte chunk; the row
+    range wraps.  Same elementwise bound as the shorter passes."""
+    n, d, r0 = 140_001, 300, 70_123
+    p = make_problem(n, d, "pow1.5", seed=7 * K + 1, mode="gaussian")
+    data, xs, scale = device_data(p.x, dtype)
+    v = gaussian_block(d, K, 29, np.float32)
+    Z, G = P().stream_pass(data, K, torch.from_numpy(v).cuda(), r0=r0, nrows=n, want_g=want_g)
+    torch.cuda.synchronize()
+    assert (G is None) == (not want_g)
+    xb = np.roll(xs, -r0, axis=0)
+    veff = operand_basis(v, dtype, scale)
+    y = xb @ veff
+    z_ref = xb.T @ y
+    bound = np.abs(xb).T @ np.abs(y)
+    c = 1e-5 if dtype == F32 else 2.0 ** -8
+    assert np.all(np.abs(Z.cpu().numpy() - z_ref) <= c * bound + 1e-30)
+    if want_g:
+        assert gram_err(G.cpu().numpy(), y.T @ y) < (2e-5 if dtype == F32 else 4e-3)
+
+
 # ---------------------------------------------------------------- power pass
 @pytest.mark.parametrize("dtype", [F32, BF16, FP8])
 @pytest.mark.parametrize("n,d,k,l,spec", [(6007, 300, 8, 8, "exp0.9"),
