@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--spectrum", default="exp0.9")
     ap.add_argument("--seed", type=int, default=1003)
     ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--item-bytes", type=int, default=0,
+                    help="grouped workload: work-item size in bytes of X (0 = autotune)")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=500000)
@@ -523,6 +525,20 @@ def main_grouped(a):
     for p, (n, d, k, l, _) in enumerate(shapes):
         V = vbuf[offs[p]:offs[p + 1]].view(d, k + l)
         probs.append(P.Problem(data[p], k, l, V).alloc())
+    # work-item size of the fused pass: the library's autotuner (one timed
+    # pass per candidate, outside the timed region), or --item-bytes
+    vbuf.copy_(vbuf0)
+    tune = None
+    if a.item_bytes > 0:
+        item_bytes = a.item_bytes
+    else:
+        t_tune = time.perf_counter()
+        item_bytes, tune_ms = P.tune_group_items(probs)
+        tune = {"candidates": list(P.GROUP_ITEM_CANDIDATES), "pass_ms": [round(t, 4) for t in tune_ms],
+                "seconds": round(time.perf_counter() - t_tune, 2)}
+        log(f"autotuned work items: {item_bytes >> 10} KiB "
+            f"(pass ms {', '.join(f'{t:.3f}' for t in tune_ms)})")
+    P.set_group_item_bytes(item_bytes)
     group = P.Group(probs)
     ws = group.workspace()
     xbytes = sum(n * d * 2 for (n, d, _, _, _) in shapes)
@@ -585,7 +601,8 @@ def main_grouped(a):
                       "d": sorted(set(int(x) for x in dims[:, 1])),
                       "k": [int(dims[:, 2].min()), int(dims[:, 2].max())], "l": "k",
                       "power_iters": iters, "x_gbytes": round(xbytes / 1e9, 3),
-                      "x_reads_per_step": passes},
+                      "x_reads_per_step": passes, "item_bytes": int(item_bytes)},
+           "autotune": tune,
            "graph_ms_per_step": round(dtg * 1e3, 3),
            "accuracy": {"max_rel_eig_err": max(rel), "median_rel_eig_err": float(np.median(rel)),
                         "sin_theta_max": max(sin_t), "median_sin_theta": float(np.median(sin_t))},

@@ -240,8 +240,36 @@ int ppca_prime_power_grouped(const ppca_problem* probs, int32_t nprob, int32_t i
 int ppca_rayleigh_ritz_grouped(const ppca_problem* probs, int32_t nprob,
                                void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes of the grouped calls for these problems (0 if invalid). */
+/* Workspace bytes of the grouped calls for these problems (0 if invalid),
+ * at the current work-item size (ppca_set_group_item_bytes). */
 size_t ppca_grouped_workspace_bytes(const ppca_problem* probs, int32_t nprob);
+
+/* The same at work-item size item_bytes (0 if invalid or out of range). */
+size_t ppca_grouped_workspace_bytes_for(const ppca_problem* probs, int32_t nprob,
+                                        int64_t item_bytes);
+
+/* Work split of the grouped calls: the rows of every problem are cut into
+ * work items of about `bytes` bytes of X (whole 16-row tiles), dealt largest
+ * first to one persistent workgroup per CU.  Smaller items balance the end of
+ * a pass better, larger ones write fewer partial sums.  0 restores the default
+ * (3 MiB); otherwise 64 KiB <= bytes <= 1 GiB, else PPCA_ERR_ARG.  Process-
+ * wide; affects the plans (and workspace sizes) of later calls; results differ
+ * between item sizes only in the order of float32 partial sums. */
+int ppca_set_group_item_bytes(int64_t bytes);
+
+/* Autotuner of that work split: for each of the ncand candidate item sizes
+ * (cand == NULL or ncand == 0: 1, 2, 3, 4, 6 and 8 MiB) forms the bf16
+ * operand of every problem's V as it stands, runs the fused power pass once
+ * untimed and once timed with HIP events on `stream`, and returns the fastest
+ * candidate in *best_bytes (each time in times_ms[i] when times_ms is not
+ * NULL).  Nothing the caller owns is written (V is not orthonormalised; the
+ * sums stay in the workspace).  The setting is not changed: pass *best_bytes
+ * to ppca_set_group_item_bytes.  Workspace: the largest of
+ * ppca_grouped_workspace_bytes_for over the candidates (the smallest
+ * candidate needs the most). */
+int ppca_tune_group_items(const ppca_problem* probs, int32_t nprob, const int64_t* cand,
+                          int32_t ncand, void* ws, size_t ws_bytes, void* stream,
+                          int64_t* best_bytes, double* times_ms);
 
 /* Bytes of workspace needed by operation `op` (PPCA_OP_*) for data X with
  * K directions and minibatch `batch` (rows of the pass for PPCA_OP_STREAM;

@@ -26,6 +26,7 @@ EXPORTS = [
     "ppca_stream_pass", "ppca_project_gram", "ppca_rayleigh_ritz", "ppca_workspace_bytes", "ppca_strerror",
     "ppca_set_kernel_timing", "ppca_kernel_stats", "ppca_set_chunk_rows",
     "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
+    "ppca_grouped_workspace_bytes_for", "ppca_set_group_item_bytes", "ppca_tune_group_items",
 ]
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
 
@@ -92,6 +93,11 @@ def lib():
         L.ppca_rayleigh_ritz_grouped.argtypes = [pp, i32, vp, sz, vp]
         L.ppca_grouped_workspace_bytes.argtypes = [pp, i32]
         L.ppca_grouped_workspace_bytes.restype = sz
+        L.ppca_grouped_workspace_bytes_for.argtypes = [pp, i32, i64]
+        L.ppca_grouped_workspace_bytes_for.restype = sz
+        L.ppca_set_group_item_bytes.argtypes = [i64]
+        L.ppca_tune_group_items.argtypes = [pp, i32, ctypes.POINTER(i64), i32, vp, sz, vp,
+                                            ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         _lib = L
     return _lib
 
@@ -362,6 +368,32 @@ def _group(problems) -> Group:
 def grouped_workspace_bytes(problems) -> int:
     arr = _problem_array(problems)
     return int(lib().ppca_grouped_workspace_bytes(arr, len(problems)))
+
+
+GROUP_ITEM_CANDIDATES = (1 << 20, 2 << 20, 3 << 20, 4 << 20, 6 << 20, 8 << 20)
+
+
+def set_group_item_bytes(nbytes: int):
+    """Work-item size (bytes of X) of later grouped calls; 0 = default."""
+    _check(lib().ppca_set_group_item_bytes(int(nbytes)), "ppca_set_group_item_bytes")
+
+
+def tune_group_items(problems, candidates=GROUP_ITEM_CANDIDATES, ws=None):
+    """Time one fused power pass of these problems per candidate work-item
+    size; returns (fastest size, [ms per candidate]).  The setting is not
+    changed (see set_group_item_bytes)."""
+    g = _group(problems)
+    cand = (ctypes.c_int64 * len(candidates))(*[int(c) for c in candidates])
+    if ws is None:
+        need = max(int(lib().ppca_grouped_workspace_bytes_for(g.arr, len(g.problems), int(c)))
+                   for c in candidates)
+        ws = _workspace(need, g.problems[0].V.device)
+    best = ctypes.c_int64(0)
+    times = (ctypes.c_double * len(candidates))()
+    code = lib().ppca_tune_group_items(g.arr, len(g.problems), cand, len(candidates), _ptr(ws),
+                                       ws.numel(), _stream(), ctypes.byref(best), times)
+    _check(code, "ppca_tune_group_items")
+    return int(best.value), [float(t) for t in times]
 
 
 def prime_power_grouped(problems, iters: int, graph: bool = False, ws=None):

@@ -585,6 +585,23 @@ __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rin
   __syncthreads();
 }
 
+// operand vop[c][j] = bf16(V[j][c]) of one problem (zero for j >= d or
+// c >= K, up to Kp x dc), by one workgroup of 256 threads
+__device__ inline void write_operand(const GProb& P, const float* V) {
+  const int64_t d = P.d;
+  const int K = P.K, Kp = P.Kp, dc = P.dc;
+  for (int e = threadIdx.x; e < Kp * dc; e += 256) {
+    const int c = e / dc, j = e - c * dc;
+    P.vop[e] = (j < d && c < K) ? (uint16_t)f32_to_bf16_bits(V[(int64_t)j * K + c]) : 0;
+  }
+}
+
+// the operand of problem blockIdx.x from its V as it stands
+__global__ __launch_bounds__(256) void k_goperand(const GProb* __restrict__ probs) {
+  const GProb& P = probs[blockIdx.x];
+  write_operand(P, P.V);
+}
+
 // CholeskyQR2 of Z (or of V when from_v) for problem blockIdx.x: V = Q, the
 // operand vop[c][j] = bf16(V[j][c]) (zero for j >= d or c >= K, up to Kp x dc)
 // and, with want_b, B = V'^T V' of the bf16 values.
@@ -610,11 +627,7 @@ __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ prob
   trmm_wg([&](int64_t r, int c) { return q1[r * K + c]; }, d, K, P.Rinv, Rl, stg,
           [&](int64_t r, int c, double v) { V[r * K + c] = (float)v; });
   // operand (V was written by this workgroup before the barrier above)
-  const int Kp = P.Kp, dc = P.dc;
-  for (int e = threadIdx.x; e < Kp * dc; e += 256) {
-    const int c = e / dc, j = e - c * dc;
-    P.vop[e] = (j < d && c < K) ? (uint16_t)f32_to_bf16_bits(V[(int64_t)j * K + c]) : 0;
-  }
+  write_operand(P, V);
   if (want_b)
     gram_wg([&](int64_t r, int c) {
       return (double)bf16_bits_to_f32(f32_to_bf16_bits(V[r * K + c]));
@@ -754,6 +767,11 @@ hipError_t launch_group_cholqr2(const GProb* probs, const int* order, int nprob,
                                 bool want_b, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_gcholqr2, dim3(nprob), dim3(256), 0, s, probs, order, from_v ? 1 : 0,
                      want_b ? 1 : 0, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_operand(const GProb* probs, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_goperand, dim3(nprob), dim3(256), 0, s, probs);
   return hipGetLastError();
 }
 

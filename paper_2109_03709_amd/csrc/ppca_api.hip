@@ -304,7 +304,9 @@ int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipSt
 
 
 // ---------------------------------------------------------- grouped problems
-constexpr int64_t kGroupItemBytes = 3 << 20;   // X bytes per work item (target)
+constexpr int64_t kGroupItemBytes = 3 << 20;   // X bytes per work item (default target)
+constexpr int64_t kGroupItemMin = 1 << 16, kGroupItemMax = 1LL << 30;
+std::atomic<int64_t> g_group_item_bytes{kGroupItemBytes};
 
 struct GroupPlan {
   size_t status = 0, probs = 0, items = 0, blk_z = 0, blk_g = 0, order = 0, zpart = 0, gpart = 0;
@@ -326,7 +328,8 @@ int check_group_problem(const ppca_problem& q) {
   return PPCA_OK;
 }
 
-int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
+int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp,
+                    int64_t item_bytes = g_group_item_bytes.load()) {
   if (!pr || nprob < 1) return PPCA_ERR_ARG;
   Carve c;
   gp.status = c.take(256);
@@ -357,9 +360,9 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp) {
     P.cls = dci * 2 + Kp / 32 - 1;
     P.dc = dc;
     P.wr = wr;
-    // work items: about kGroupItemBytes of X each, whole 16-row tiles of every row group
+    // work items: about item_bytes of X each, whole 16-row tiles of every row group
     const int64_t step = 16 * wr;
-    int64_t rt = round_up(std::max<int64_t>(cdiv(kGroupItemBytes, d * 2), step), step);
+    int64_t rt = round_up(std::max<int64_t>(cdiv(item_bytes, d * 2), step), step);
     int64_t ni = cdiv(n, rt);
     rt = round_up(cdiv(n, ni), step);
     ni = cdiv(n, rt);
@@ -725,6 +728,86 @@ size_t ppca_grouped_workspace_bytes(const ppca_problem* probs, int32_t nprob) {
   GroupPlan gp;
   if (make_group_plan(probs, nprob, gp) != PPCA_OK) return 0;
   return gp.total;
+}
+
+size_t ppca_grouped_workspace_bytes_for(const ppca_problem* probs, int32_t nprob,
+                                        int64_t item_bytes) {
+  if (item_bytes < kGroupItemMin || item_bytes > kGroupItemMax) return 0;
+  GroupPlan gp;
+  if (make_group_plan(probs, nprob, gp, item_bytes) != PPCA_OK) return 0;
+  return gp.total;
+}
+
+int ppca_set_group_item_bytes(int64_t bytes) {
+  if (bytes == 0) bytes = kGroupItemBytes;
+  if (bytes < kGroupItemMin || bytes > kGroupItemMax) return PPCA_ERR_ARG;
+  g_group_item_bytes.store(bytes);
+  return PPCA_OK;
+}
+
+int ppca_tune_group_items(const ppca_problem* probs, int32_t nprob, const int64_t* cand,
+                          int32_t ncand, void* ws, size_t ws_bytes, void* stream,
+                          int64_t* best_bytes, double* times_ms) {
+  static const int64_t kDefault[] = {1 << 20, 2 << 20, 3 << 20, 4 << 20, 6 << 20, 8 << 20};
+  if (!cand || ncand == 0) {
+    cand = kDefault;
+    ncand = (int32_t)(sizeof(kDefault) / sizeof(kDefault[0]));
+  }
+  if (ncand < 0 || !best_bytes || !probs || nprob < 1) return PPCA_ERR_ARG;
+  for (int i = 0; i < ncand; ++i)
+    if (cand[i] < kGroupItemMin || cand[i] > kGroupItemMax) return PPCA_ERR_ARG;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].V) return PPCA_ERR_ARG;
+  // every candidate's plan must fit before anything runs
+  for (int i = 0; i < ncand; ++i) {
+    GroupPlan gp;
+    RET_IF(make_group_plan(probs, nprob, gp, cand[i]));
+    RET_IF(check_group_ws(ws, ws_bytes, gp));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return PPCA_ERR_HIP;
+  }
+  int rc = PPCA_OK;
+  double best = 0.0;
+  for (int i = 0; i < ncand && rc == PPCA_OK; ++i) {
+    GroupPlan gp;
+    rc = make_group_plan(probs, nprob, gp, cand[i]);
+    if (rc != PPCA_OK) break;
+    bind_group_plan(gp, probs, ws);
+    rc = upload_group_plan(gp, ws, s);
+    if (rc != PPCA_OK) break;
+    const GProb* dP = at<GProb>(ws, gp.probs);
+    const int nitems = (int)gp.hi.size();
+    auto pass = [&] {
+      return launch_group_pass(dP, at<GItem>(ws, gp.items), nitems, std::min(nitems, kNumCU),
+                               at<float>(ws, gp.zpart), at<float>(ws, gp.gpart), true, s);
+    };
+    // the operand of V as it stands, one untimed pass, then the timed one
+    if (launch_group_operand(dP, nprob, s) != hipSuccess || pass() != hipSuccess ||
+        hipEventRecord(e0, s) != hipSuccess || pass() != hipSuccess ||
+        hipEventRecord(e1, s) != hipSuccess) {
+      rc = PPCA_ERR_HIP;
+      break;
+    }
+    rc = finish_group(gp, ws, s);   // synchronises: the host tables outlive their copies
+    if (rc != PPCA_OK) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = PPCA_ERR_HIP;
+      break;
+    }
+    if (times_ms) times_ms[i] = ms;
+    if (i == 0 || ms < best) {
+      best = ms;
+      *best_bytes = cand[i];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
 }
 
 size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch) {

@@ -174,6 +174,8 @@ hipError_t launch_group_reduce(const GProb* probs, int nprob, const int* blk0, i
                                const float* zpart, const float* gpart, bool want_z, int* status,
                                hipStream_t s);
 // order: problem indices, largest first (workgroup b takes problem order[b])
+// bf16 operand of every problem from its V as it stands (V is not changed)
+hipError_t launch_group_operand(const GProb* probs, int nprob, hipStream_t s);
 hipError_t launch_group_cholqr2(const GProb* probs, const int* order, int nprob, bool from_v,
                                 bool want_b, int* status, hipStream_t s);
 hipError_t launch_group_rr(const GProb* probs, const int* order, int nprob, int max_sweeps,

@@ -199,3 +199,31 @@ def test_grouped_argument_errors(cases):
     with pytest.raises(P().PPCAError) as e:
         P().prime_power_grouped([good], 1, ws=ws)
     assert e.value.code == -6
+
+
+def test_grouped_item_autotuner(cases):
+    """The autotuner times the fused pass per work-item size, returns one of
+    the candidates and writes nothing the caller owns; a different item size
+    changes only the order of float32 partial sums (same one-step bound)."""
+    probs = []
+    for (data, _, v0), (n, d, k, l, _) in zip(cases, SHAPES):
+        probs.append(P().Problem(data, k, l, torch.from_numpy(v0.copy()).cuda()).alloc())
+    before = [p.V.clone() for p in probs]
+    cands = [256 << 10, 1 << 20, 3 << 20]
+    best, times = P().tune_group_items(probs, cands)
+    torch.cuda.synchronize()
+    assert best in cands and len(times) == 3 and all(t > 0 for t in times)
+    assert times[cands.index(best)] == min(times)
+    assert all(torch.equal(a, p.V) for a, p in zip(before, probs))
+    with pytest.raises(P().PPCAError) as e:
+        P().set_group_item_bytes(1024)
+    assert e.value.code == -1
+    try:
+        P().set_group_item_bytes(256 << 10)
+        small = _run(cases, 1)
+    finally:
+        P().set_group_item_bytes(0)
+    for (data, xs, v0), (n, d, k, l, _), p in zip(cases, SHAPES, small):
+        v = O.cholqr2(v0.astype(np.float64))[0]
+        z, _ = O.stream_pass(xs, operand_basis(v.astype(np.float32), BF16, None))
+        assert sin_theta(p.V.cpu().numpy(), O.cholqr2(z)[0]) < 2e-2, f"n={n} d={d}"
