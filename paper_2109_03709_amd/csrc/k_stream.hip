@@ -437,12 +437,13 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
 // epilogue.  A last step that ends inside a 16-byte chunk has the chunk's
 // columns past d cleared in LDS by the lane that loaded it.
 // ---------------------------------------------------------------------------
-template <int NB, int DT, int MW, bool WANT_Y, bool WANT_G>
-__global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
-                                                int64_t rstart, int64_t rows, const uint8_t* vop,
+template <int NB, int DT, int MW, bool WANT_Y, bool WANT_G, bool PART = false>
+__global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, int64_t d_, int64_t ld,
+                                                int64_t rstart, int64_t rows, const uint8_t* vop_,
                                                 int64_t dp, uint8_t* yb, float* gpart,
-                                                int accumulate) {
+                                                int accumulate, float* ypart, int64_t yrows) {
   static_assert(DT == DT_F32 || DT == DT_BF16, "bf16 or f32 data");
+  static_assert(!PART || (!WANT_Y && !WANT_G), "partial mode writes only float32 Y partials");
   constexpr int Kp = NB * 16;
   constexpr int NBG = (NB + 3) / 4;                    // G column blocks per wave
   constexpr int EB = DT == DT_F32 ? 4 : 2;             // bytes per X / V' / Y element
@@ -463,6 +464,21 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
   __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
   __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
 
+  // partial mode (split of the columns, blockIdx.y = split): the split's
+  // k-steps [kper y, kper (y + 1)) as a matrix of its own; the host picks the
+  // split count so that every split has at least one k-step
+  const uint8_t* x = x_;
+  const uint8_t* vop = vop_;
+  int64_t d = d_;
+  if constexpr (PART) {
+    const int nk_all = (int)((d_ + KS - 1) / KS);
+    const int kper = (nk_all + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int64_t c0 = (int64_t)blockIdx.y * kper * KS;
+    if (c0 >= d_) return;                    // uniform; excluded by the split count
+    x += c0 * EB;
+    vop += c0 * EB;
+    d = d_ - c0 < (int64_t)kper * KS ? d_ - c0 : (int64_t)kper * KS;
+  }
   const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int a = lane & 15, g = lane >> 4;
   const int64_t ntile = (rows + WGR - 1) / WGR;
@@ -617,6 +633,17 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
     wait_vmcnt<0>();
     raw_barrier();                           // every DMA landed, every stage read
 
+    if constexpr (PART) {
+      // float32 partial of this split: ypart[split][row0 + lr][c]
+      float* yp = ypart + ((int64_t)blockIdx.y * yrows + row0) * Kp;
+#pragma unroll
+      for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            yp[(int64_t)(w * MW * 16 + mb * 16 + 4 * g + u) * Kp + nb * 16 + a] = acc[mb][nb][u];
+    } else {
     // ---- Y tile -> LDS, layout [row/YR][Kp][YR]; rows [0, WGR/2) in st0, the
     // rest in st1.  Rows past the pass are written as zeros.
     const int64_t vrows = rows - row0;        // valid rows of this tile
@@ -700,6 +727,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
         }
       }
     }
+    }   // !PART
     // clear the accumulators for the next tile with a zero the compiler cannot
     // see through (a literal zero at the top of the tile makes the register
     // allocator rotate the accumulators through extra registers in the k-loop)
@@ -728,6 +756,87 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x, int64_t n, int
         }
       }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Sum of the column-split partials of a short pass (k_xvd in partial mode):
+// workgroup w takes rows [64 w, 64 w + 64) of the pass; Y = sum over the
+// splits in split order (float32), rows past the pass zero, rounded to bf16
+// for bf16 data; written to the Y staging buffer (blocked layout) when
+// want_y; G_w = Y^T Y over the 64 rows (float32, rows in order) into
+// gpart[w] when want_g (workgroups past the last tile write zeros, so that
+// all ngpart partials are defined).
+// ---------------------------------------------------------------------------
+template <int NB, int DT>
+__global__ __launch_bounds__(1024) void k_ysum(const float* __restrict__ ypart, int ksplit,
+                                               int64_t yrows, int64_t rows, uint8_t* yb,
+                                               float* gpart, int want_y, int want_g,
+                                               int accumulate) {
+  constexpr int Kp = NB * 16, LDY = Kp + 1, NT = Kp / 4;
+  static_assert(DT == DT_F32 || DT == DT_BF16, "bf16 or f32 data");
+  __shared__ float ys[64 * LDY];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const bool act = row0 < rows;             // uniform
+  if (act) {
+    for (int e = t; e < 64 * Kp; e += 1024) {
+      const int r = e / Kp, c = e - r * Kp;
+      const float* p = ypart + (row0 + r) * Kp + c;
+      const int64_t ss = yrows * Kp;          // split stride
+      float sum = 0.f;
+      int sp = 0;
+      for (; sp + 8 <= ksplit; sp += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(sp + u) * ss];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+      }
+      for (; sp < ksplit; ++sp) sum += p[(int64_t)sp * ss];
+      const int64_t gr = row0 + r;
+      float y = gr < rows ? sum : 0.f;
+      if constexpr (DT == DT_BF16) y = bf16_bits_to_f32(f32_to_bf16_bits(y));
+      ys[r * LDY + c] = y;
+      if (want_y) {
+        if constexpr (DT == DT_F32)
+          reinterpret_cast<float*>(yb)[((gr >> 2) * Kp + c) * 4 + (gr & 3)] = y;
+        else
+          reinterpret_cast<uint16_t*>(yb)[((gr >> 3) * Kp + c) * 8 + (gr & 7)] =
+              (uint16_t)f32_to_bf16_bits(y);
+      }
+    }
+  }
+  __syncthreads();
+  if (!want_g || t >= NT * NT) return;
+  const int ti = t / NT, tj = t - ti * NT;
+  float acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+  if (act) {
+    for (int r = 0; r < 64; ++r) {
+      float ra[4], rb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ra[u] = ys[r * LDY + 4 * ti + u];
+        rb[u] = ys[r * LDY + 4 * tj + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(ra[u], rb[v], acc[u][v]);
+    }
+  }
+  float* gp = gpart + (int64_t)blockIdx.x * Kp * Kp;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float* q = gp + (int64_t)(4 * ti + u) * Kp + 4 * tj + v;
+      if (accumulate) *q += acc[u][v];
+      else *q = acc[u][v];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1248,6 +1357,21 @@ static int xv_mw(int32_t dtype, int Kp, int64_t rows_cap) {
 // spill free with at least two stages in flight at each wait).
 constexpr int xv_stages(int dt, int nb, int mw) { return 6; }
 
+// Column splits of a short pass (64-row tiles, bf16 or f32 data): with few
+// tiles the Y = X V' kernel runs on a few CUs, so the k-steps are split over
+// up to 16 workgroups per tile (at most 256 in all, every split at least one
+// k-step) and a second kernel sums the float32 partials.  1 = no split.
+int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
+  if (dtype == PPCA_FP8_E4M3 || xv_mw(dtype, Kp, rows_cap) != 1) return 1;
+  const int64_t ntile = cdiv(rows_cap, 64);
+  if (ntile > 128) return 1;
+  const int64_t nk = cdiv(d, dtype == PPCA_F32 ? 32 : 64);
+  int64_t target = std::min<int64_t>(16, std::min<int64_t>(kNumCU / ntile, nk));
+  if (target < 2) return 1;
+  const int64_t kper = cdiv(nk, target);
+  return (int)cdiv(nk, kper);
+}
+
 int xv_grid(int32_t dtype, int Kp, int64_t rows_cap) {
   const int64_t tiles = cdiv(rows_cap, 64 * xv_mw(dtype, Kp, rows_cap));
   return (int)(tiles < kNumCU ? tiles : kNumCU);
@@ -1266,6 +1390,24 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
                          p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
                          accumulate ? 1 : 0);
     };
+    auto go_xvd = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d,
+                         p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
+                         accumulate ? 1 : 0, (float*)nullptr, (int64_t)0);
+    };
+    // short pass with a column split: partial products, then their sum
+    auto go_split = [&](auto dtc) {
+      constexpr int DT = decltype(dtc)::value;
+      const int64_t ntile = cdiv(rows, 64);
+      const int64_t yrows = round_up(b.rows_cap, 64);
+      hipLaunchKernelGGL((k_xvd<NB, DT, 1, false, false, true>), dim3(ntile, b.ksplit), dim3(256),
+                         0, s, (const uint8_t*)p.x, p.n, p.d, p.ld, rstart, rows,
+                         (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr, (float*)nullptr, 0,
+                         b.ypart, yrows);
+      hipLaunchKernelGGL((k_ysum<NB, DT>), dim3(b.ngpart), dim3(1024), 0, s, b.ypart, b.ksplit,
+                         yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
+                         accumulate ? 1 : 0);
+    };
     // bf16 / f32 data: LDS-DMA kernel; fp8 data: register-staged kernel
     auto by_mw = [&](auto dtc, auto yc, auto gc) {
       constexpr int DT = decltype(dtc)::value;
@@ -1274,14 +1416,16 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
         if (mw == 1) go(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), WY, WG>);
         else go(k_xv<NB, DT, 4, xv_stages(DT, NB, 4), WY, WG>);
       } else {
-        if (mw == 1) {
-          go(k_xvd<NB, DT, 1, WY, WG>);
+        if (mw == 1 && b.ksplit > 1) {
+          go_split(dtc);
+        } else if (mw == 1) {
+          go_xvd(k_xvd<NB, DT, 1, WY, WG>);
         } else if constexpr (DT == DT_BF16 && NB % 2 == 0 && WY && !WG) {
           hipLaunchKernelGGL(k_xvy<NB>, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
                              p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb);
         } else {
-          if constexpr (NB > xv_wide_nb(DT)) go(k_xvd<NB, DT, 2, WY, WG>);
-          else go(k_xvd<NB, DT, 4, WY, WG>);
+          if constexpr (NB > xv_wide_nb(DT)) go_xvd(k_xvd<NB, DT, 2, WY, WG>);
+          else go_xvd(k_xvd<NB, DT, 4, WY, WG>);
         }
       }
     };

@@ -97,8 +97,9 @@ struct Plan {
   int K = 0, Kp = 0;
   int64_t dp = 0;
   int64_t rows_cap = 0;   // rows of the Y staging buffer
-  int ntiles = 0, nsplit = 0, ngpart = 0;
+  int ntiles = 0, nsplit = 0, ngpart = 0, ksplit = 1;
   // offsets
+  size_t ypart = 0;
   size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
          a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
          sums = 0, cmax = 0, mean = 0;
@@ -163,6 +164,9 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
                       : (size_t)p.ntiles * p.nsplit * p.Kp * xty_cols(p.Kp) * sizeof(float));
   p.ngpart = xv_grid(dtype, p.Kp, p.rows_cap);
   p.gpart = c.take((size_t)p.ngpart * p.Kp * p.Kp * sizeof(float));
+  p.ksplit = xv_ksplit(dtype, p.Kp, d, p.rows_cap);
+  p.ypart = c.take(p.ksplit > 1 ? (size_t)p.ksplit * round_up(p.rows_cap, 64) * p.Kp * sizeof(float)
+                                : 16);
   p.z = c.take((size_t)d * K * sizeof(float));
   p.g = c.take(kk);
   p.b = c.take(kk);
@@ -235,6 +239,8 @@ StreamBufs bufs_of(const Plan& p, void* ws) {
   b.nsplit = p.nsplit;
   b.ngpart = p.ngpart;
   b.Kp = p.Kp;
+  b.ksplit = p.ksplit;
+  b.ypart = at<float>(ws, p.ypart);
   return b;
 }
 

@@ -71,9 +71,12 @@ struct StreamBufs {
   int nsplit;           // row splits of the X^T Y kernel
   int ngpart;           // workgroups of k_xv (fixed for all chunks of a pass)
   int Kp;               // K padded to 16
+  int ksplit;           // column splits of a short pass (1 = none)
+  float* ypart;         // float32 Y partials [ksplit][rows_cap rounded to 64][Kp]
 };
 
 // stream kernels (k_stream.hip)
+int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap);   // column splits
 int xty_cols(int Kp);              // columns per tile of the X^T Y kernel
 int xty_blocks_per_cu(int Kp);     // resident workgroups per CU of the X^T Y kernel
 constexpr int kNumCU = 256;        // compute units of an MI355X

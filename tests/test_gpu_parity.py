@@ -107,14 +107,16 @@ def test_stream_pass_elementwise_bound(dtype, n, d, K, r0, rows):
 
 
 @pytest.mark.parametrize("dtype,K,want_g", [(BF16, 32, False), (BF16, 64, False), (BF16, 48, False),
-                                             (BF16, 64, True), (F32, 64, False), (FP8, 64, False)])
+                                             (BF16, 64, True), (F32, 64, False), (FP8, 64, False),
+                                             (F32, 32, True), (BF16, 16, True), (F32, 80, False)])
 def test_stream_pass_wide_tiles(dtype, K, want_g):
     """Passes of at least 65,536 rows run on 256-row tiles (Y = X V' of the
     power step: one DMA pipeline over all tiles of a workgroup, Y stored from
     the accumulators; bf16 with K a multiple of 32 on 32x32x16 MFMAs).
     n = 140,001 gives every workgroup two or three tiles and a partial last
     tile; d = 300 ends inside a k-step and inside a 16-byte chunk; the row
-    range wraps.  Same elementwise bound as the shorter passes."""
+    range wraps.  Small K gives 4- or 5-stage LDS rings (128-row tiles for
+    f32 with K > 64).  Same elementwise bound as the shorter passes."""
     n, d, r0 = 140_001, 300, 70_123
     p = make_problem(n, d, "pow1.5", seed=7 * K + 1, mode="gaussian")
     data, xs, scale = device_data(p.x, dtype)
