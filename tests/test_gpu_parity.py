@@ -115,8 +115,8 @@ def test_stream_pass_wide_tiles(dtype, K, want_g):
     the accumulators; bf16 with K a multiple of 32 on 32x32x16 MFMAs).
     n = 140,001 gives every workgroup two or three tiles and a partial last
     tile; d = 300 ends inside a k-step and inside a 16-byte chunk; the row
-    range wraps.  Small K gives 4- or 5-stage LDS rings (128-row tiles for
-    f32 with K > 64).  Same elementwise bound as the shorter passes."""
+    range wraps.  Small K with G and f32 data with K > 64 (128-row tiles)
+    are covered too.  Same elementwise bound as the shorter passes."""
     n, d, r0 = 140_001, 300, 70_123
     p = make_problem(n, d, "pow1.5", seed=7 * K + 1, mode="gaussian")
     data, xs, scale = device_data(p.x, dtype)
