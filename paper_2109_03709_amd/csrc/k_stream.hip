@@ -105,11 +105,12 @@ __device__ __attribute__((always_inline)) inline void unroll_seq(std::integer_se
 // The streamed pointers are deliberately not __restrict__: loads through
 // restrict-qualified read-only kernel arguments may be moved down to their
 // use, which would collapse the pipeline.
-template <int NB, int DT, int MW, int PSX, bool WANT_Y, bool WANT_G>
-__global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
-                                               int64_t rstart, int64_t rows, const uint8_t* vop,
+template <int NB, int DT, int MW, int PSX, bool WANT_Y, bool WANT_G, bool PART = false>
+__global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x_, int64_t n, int64_t d_, int64_t ld,
+                                               int64_t rstart, int64_t rows, const uint8_t* vop_,
                                                int64_t dp, uint8_t* yb, float* gpart,
-                                               int accumulate) {
+                                               int accumulate, float* ypart, int64_t yrows) {
+  static_assert(!PART || (!WANT_Y && !WANT_G), "partial mode writes only float32 Y partials");
   constexpr int Kp = NB * 16;
   constexpr int NBG = (NB + 3) / 4;                               // G column blocks per wave
   constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
@@ -134,6 +135,19 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
   uint8_t* const ylds = lds;
   f32x4_t* const gslot = reinterpret_cast<f32x4_t*>(lds + REGA);
 
+  // partial mode (split of the columns, blockIdx.y = split), as in k_xvd
+  const uint8_t* x = x_;
+  const uint8_t* vop = vop_;
+  int64_t d = d_;
+  if constexpr (PART) {
+    const int nk_all = (int)((d_ + KS - 1) / KS);
+    const int kper = (nk_all + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int64_t c0 = (int64_t)blockIdx.y * kper * KS;
+    if (c0 >= d_) return;                    // uniform; excluded by the split count
+    x += c0 * EB;
+    vop += c0 * OB;
+    d = d_ - c0 < (int64_t)kper * KS ? d_ - c0 : (int64_t)kper * KS;
+  }
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = lane & 15, g = lane >> 4;
   const uint32_t keep = dp > 0 ? 0xFFFFFFFFu : 0u;   // all ones, opaque to the compiler
@@ -303,6 +317,17 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
       });
     }
 
+    if constexpr (PART) {
+      // float32 partial of this split: ypart[split][row0 + lr][c]
+      float* yp = ypart + ((int64_t)blockIdx.y * yrows + row0) * Kp;
+#pragma unroll
+      for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            yp[(int64_t)(wave * MW * 16 + mb * 16 + 4 * g + u) * Kp + nb * 16 + a] = acc[mb][nb][u];
+    } else {
     // ---- Y tile -> LDS (over the pipeline buffers: the last barrier of the
     // k-loop ended every read of them), layout [row/YR][Kp][YR].
     // D[i][j]: lane (j = a, g) holds rows 4g..4g+3 of each 16-row block.
@@ -385,6 +410,7 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x, int64_t n, int6
 #pragma unroll
       for (int q = 0; q < NBG; ++q) gs(mb, q) = accg[mb][q];
     }
+    }   // !PART
     // clear the accumulators for the next tile with a zero the compiler cannot
     // see through (a literal zero at the top of the tile makes the register
     // allocator rotate the accumulators through extra registers in the k-loop)
@@ -1357,15 +1383,16 @@ static int xv_mw(int32_t dtype, int Kp, int64_t rows_cap) {
 // spill free with at least two stages in flight at each wait).
 constexpr int xv_stages(int dt, int nb, int mw) { return 6; }
 
-// Column splits of a short pass (64-row tiles, bf16 or f32 data): with few
-// tiles the Y = X V' kernel runs on a few CUs, so the k-steps are split over
-// up to 16 workgroups per tile (at most 256 in all, every split at least one
-// k-step) and a second kernel sums the float32 partials.  1 = no split.
+// Column splits of a short pass (64-row tiles): with few tiles the Y = X V'
+// kernel runs on a few CUs, so the k-steps are split over up to 16
+// workgroups per tile (at most 256 in all, every split at least one k-step)
+// and a second kernel sums the float32 partials.  1 = no split.
 int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
-  if (dtype == PPCA_FP8_E4M3 || xv_mw(dtype, Kp, rows_cap) != 1) return 1;
+  if (xv_mw(dtype, Kp, rows_cap) != 1) return 1;
   const int64_t ntile = cdiv(rows_cap, 64);
   if (ntile > 128) return 1;
-  const int64_t nk = cdiv(d, dtype == PPCA_F32 ? 32 : 64);
+  // columns per k-step: k_xvd 128 bytes of a row (f32 32, bf16 64), k_xv (fp8) 32
+  const int64_t nk = cdiv(d, dtype == PPCA_BF16 ? 64 : 32);
   int64_t target = std::min<int64_t>(16, std::min<int64_t>(kNumCU / ntile, nk));
   if (target < 2) return 1;
   const int64_t kper = cdiv(nk, target);
@@ -1388,23 +1415,23 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d,
                          p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
-                         accumulate ? 1 : 0);
-    };
-    auto go_xvd = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d,
-                         p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb, b.gpart,
                          accumulate ? 1 : 0, (float*)nullptr, (int64_t)0);
     };
-    // short pass with a column split: partial products, then their sum
+    // short pass with a column split: partial products, then their sum (Y of
+    // fp8 data is rounded to bf16 like that of bf16 data)
     auto go_split = [&](auto dtc) {
       constexpr int DT = decltype(dtc)::value;
       const int64_t ntile = cdiv(rows, 64);
       const int64_t yrows = round_up(b.rows_cap, 64);
-      hipLaunchKernelGGL((k_xvd<NB, DT, 1, false, false, true>), dim3(ntile, b.ksplit), dim3(256),
-                         0, s, (const uint8_t*)p.x, p.n, p.d, p.ld, rstart, rows,
-                         (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr, (float*)nullptr, 0,
-                         b.ypart, yrows);
-      hipLaunchKernelGGL((k_ysum<NB, DT>), dim3(b.ngpart), dim3(1024), 0, s, b.ypart, b.ksplit,
+      auto part = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(ntile, b.ksplit), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
+                           p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr,
+                           (float*)nullptr, 0, b.ypart, yrows);
+      };
+      if constexpr (DT == DT_FP8) part(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), false, false, true>);
+      else part(k_xvd<NB, DT, 1, false, false, true>);
+      constexpr int DY = DT == DT_F32 ? DT_F32 : DT_BF16;
+      hipLaunchKernelGGL((k_ysum<NB, DY>), dim3(b.ngpart), dim3(1024), 0, s, b.ypart, b.ksplit,
                          yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
                          accumulate ? 1 : 0);
     };
@@ -1412,20 +1439,20 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
     auto by_mw = [&](auto dtc, auto yc, auto gc) {
       constexpr int DT = decltype(dtc)::value;
       constexpr bool WY = decltype(yc)::value, WG = decltype(gc)::value;
-      if constexpr (DT == DT_FP8) {
+      if (mw == 1 && b.ksplit > 1) {
+        go_split(dtc);
+      } else if constexpr (DT == DT_FP8) {
         if (mw == 1) go(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), WY, WG>);
         else go(k_xv<NB, DT, 4, xv_stages(DT, NB, 4), WY, WG>);
       } else {
-        if (mw == 1 && b.ksplit > 1) {
-          go_split(dtc);
-        } else if (mw == 1) {
-          go_xvd(k_xvd<NB, DT, 1, WY, WG>);
+        if (mw == 1) {
+          go(k_xvd<NB, DT, 1, WY, WG>);
         } else if constexpr (DT == DT_BF16 && NB % 2 == 0 && WY && !WG) {
           hipLaunchKernelGGL(k_xvy<NB>, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
                              p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)b.yb);
         } else {
-          if constexpr (NB > xv_wide_nb(DT)) go_xvd(k_xvd<NB, DT, 2, WY, WG>);
-          else go_xvd(k_xvd<NB, DT, 4, WY, WG>);
+          if constexpr (NB > xv_wide_nb(DT)) go(k_xvd<NB, DT, 2, WY, WG>);
+          else go(k_xvd<NB, DT, 4, WY, WG>);
         }
       }
     };
