@@ -785,42 +785,58 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
-// Sum of the column-split partials of a short pass (k_xvd in partial mode):
-// workgroup w takes rows [64 w, 64 w + 64) of the pass; Y = sum over the
-// splits in split order (float32), rows past the pass zero, rounded to bf16
-// for bf16 data; written to the Y staging buffer (blocked layout) when
-// want_y; G_w = Y^T Y over the 64 rows (float32, rows in order) into
-// gpart[w] when want_g (workgroups past the last tile write zeros, so that
-// all ngpart partials are defined).
+// Sum of the column-split partials of a short pass (k_xvd / k_xv in partial
+// mode): workgroup w takes rows [16 w, 16 w + 16) of the pass; Y = sum over
+// the splits in split order (float32), rows past the pass zero, rounded to
+// bf16 for bf16/fp8 data; written to the Y staging buffer (blocked layout)
+// when want_y; G_w = Y^T Y over the 16 rows (float32, rows in order) into
+// gpart[w] when want_g (thread (i, j) of a 16 x 16 grid owns the NB x NB
+// tile (i, j)).  Workgroups past the pass write zero G partials and zero Y
+// rows: the grid covers the whole staging buffer (rows_cap rows), whose rows
+// past the pass the X^T Y kernel reads in its last k-step.
 // ---------------------------------------------------------------------------
+constexpr int kYsumRows = 16;
+
 template <int NB, int DT>
-__global__ __launch_bounds__(1024) void k_ysum(const float* __restrict__ ypart, int ksplit,
-                                               int64_t yrows, int64_t rows, uint8_t* yb,
-                                               float* gpart, int want_y, int want_g,
-                                               int accumulate) {
-  constexpr int Kp = NB * 16, LDY = Kp + 1, NT = Kp / 4;
+__global__ __launch_bounds__(256) void k_ysum(const float* __restrict__ ypart, int ksplit,
+                                              int64_t yrows, int64_t rows, uint8_t* yb,
+                                              float* gpart, int want_y, int want_g,
+                                              int accumulate) {
+  constexpr int Kp = NB * 16, RB = kYsumRows, LDY = Kp + 1, EPT = RB * Kp / 256;
   static_assert(DT == DT_F32 || DT == DT_BF16, "bf16 or f32 data");
-  __shared__ float ys[64 * LDY];
+  static_assert(EPT * 256 == RB * Kp, "elements per thread");
+  __shared__ float ys[RB * LDY];
   const int t = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * RB;
   const bool act = row0 < rows;             // uniform
   if (act) {
-    for (int e = t; e < 64 * Kp; e += 1024) {
-      const int r = e / Kp, c = e - r * Kp;
-      const float* p = ypart + (row0 + r) * Kp + c;
-      const int64_t ss = yrows * Kp;          // split stride
-      float sum = 0.f;
-      int sp = 0;
-      for (; sp + 8 <= ksplit; sp += 8) {
-        float v[8];
+    // thread t sums elements t + 256 j over the splits, in split order; the
+    // loads of 8 splits of all its elements are in flight together
+    const int64_t ss = yrows * Kp;            // split stride
+    const float* base = ypart + row0 * Kp;
+    float sum[EPT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(sp + u) * ss];
+    for (int j = 0; j < EPT; ++j) sum[j] = 0.f;
+    for (int sp = 0; sp < ksplit; sp += 8) {
+      float v[8][EPT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sum += v[u];
+      for (int u = 0; u < 8; ++u) {
+        const int spu = sp + u < ksplit ? sp + u : ksplit - 1;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) v[u][j] = base[(int64_t)spu * ss + t + 256 * j];
       }
-      for (; sp < ksplit; ++sp) sum += p[(int64_t)sp * ss];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (sp + u < ksplit) sum[j] += v[u][j];
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = t + 256 * j;
+      const int r = e / Kp, c = e - r * Kp;
       const int64_t gr = row0 + r;
-      float y = gr < rows ? sum : 0.f;
+      float y = gr < rows ? sum[j] : 0.f;
       if constexpr (DT == DT_BF16) y = bf16_bits_to_f32(f32_to_bf16_bits(y));
       ys[r * LDY + c] = y;
       if (want_y) {
@@ -831,35 +847,48 @@ __global__ __launch_bounds__(1024) void k_ysum(const float* __restrict__ ypart, 
               (uint16_t)f32_to_bf16_bits(y);
       }
     }
+  } else if (want_y) {
+    // rows past the pass: the X^T Y kernel's last k-step reads them, as zeros
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = t + 256 * j;
+      const int r = e / Kp, c = e - r * Kp;
+      const int64_t gr = row0 + r;
+      if constexpr (DT == DT_F32)
+        reinterpret_cast<float*>(yb)[((gr >> 2) * Kp + c) * 4 + (gr & 3)] = 0.f;
+      else
+        reinterpret_cast<uint16_t*>(yb)[((gr >> 3) * Kp + c) * 8 + (gr & 7)] = 0;
+    }
   }
   __syncthreads();
-  if (!want_g || t >= NT * NT) return;
-  const int ti = t / NT, tj = t - ti * NT;
-  float acc[4][4];
+  if (!want_g) return;
+  const int ti = t >> 4, tj = t & 15;
+  float acc[NB][NB];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < NB; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+    for (int v = 0; v < NB; ++v) acc[u][v] = 0.f;
   if (act) {
-    for (int r = 0; r < 64; ++r) {
-      float ra[4], rb[4];
+#pragma unroll 4
+    for (int r = 0; r < RB; ++r) {
+      float ra[NB], rb[NB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ra[u] = ys[r * LDY + 4 * ti + u];
-        rb[u] = ys[r * LDY + 4 * tj + u];
+      for (int u = 0; u < NB; ++u) {
+        ra[u] = ys[r * LDY + NB * ti + u];
+        rb[u] = ys[r * LDY + NB * tj + u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < NB; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(ra[u], rb[v], acc[u][v]);
+        for (int v = 0; v < NB; ++v) acc[u][v] = fmaf(ra[u], rb[v], acc[u][v]);
     }
   }
   float* gp = gpart + (int64_t)blockIdx.x * Kp * Kp;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < NB; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float* q = gp + (int64_t)(4 * ti + u) * Kp + 4 * tj + v;
+    for (int v = 0; v < NB; ++v) {
+      float* q = gp + (int64_t)(NB * ti + u) * Kp + NB * tj + v;
       if (accumulate) *q += acc[u][v];
       else *q = acc[u][v];
     }
@@ -1305,7 +1334,16 @@ __global__ __launch_bounds__(256) void k_reduce_zg(const float* __restrict__ par
       const int64_t c = e / d, j = e % d;
       const float* p = part + (j / TC) * tile_stride + c * TC + (j % TC);
       double s = 0.0;
-      for (int t = 0; t < nsplit; ++t) s += (double)p[(int64_t)t * split_stride];
+      // splits in order, eight loads in flight
+      int t = 0;
+      for (; t + 8 <= nsplit; t += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(t + u) * split_stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += (double)v[u];
+      }
+      for (; t < nsplit; ++t) s += (double)p[(int64_t)t * split_stride];
       if (scale) s *= (double)scale[j];
       const float zf = (float)s;
       if (!isfinite(zf)) bad = true;
@@ -1320,8 +1358,18 @@ __global__ __launch_bounds__(256) void k_reduce_zg(const float* __restrict__ par
     const int t0 = w * per, t1 = min(ngpart, t0 + per);
     double s = 0.0;
     if (act) {
+      // partials in order, eight loads in flight
       const float* p = gpart + i * Kp + c;
-      for (int t = t0; t < t1; ++t) s += (double)p[(int64_t)t * Kp * Kp];
+      const int64_t st = (int64_t)Kp * Kp;
+      int t = t0;
+      for (; t + 8 <= t1; t += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(t + u) * st];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += (double)v[u];
+      }
+      for (; t < t1; ++t) s += (double)p[(int64_t)t * st];
     }
     gsum[w][lane] = s;
     __syncthreads();
@@ -1399,7 +1447,9 @@ int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   return (int)cdiv(nk, kper);
 }
 
-int xv_grid(int32_t dtype, int Kp, int64_t rows_cap) {
+int xv_grid(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
+  // split short passes: one G partial per k_ysum workgroup (16 rows)
+  if (xv_ksplit(dtype, Kp, d, rows_cap) > 1) return (int)cdiv(rows_cap, kYsumRows);
   const int64_t tiles = cdiv(rows_cap, 64 * xv_mw(dtype, Kp, rows_cap));
   return (int)(tiles < kNumCU ? tiles : kNumCU);
 }
@@ -1431,7 +1481,7 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
       if constexpr (DT == DT_FP8) part(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), false, false, true>);
       else part(k_xvd<NB, DT, 1, false, false, true>);
       constexpr int DY = DT == DT_F32 ? DT_F32 : DT_BF16;
-      hipLaunchKernelGGL((k_ysum<NB, DY>), dim3(b.ngpart), dim3(1024), 0, s, b.ypart, b.ksplit,
+      hipLaunchKernelGGL((k_ysum<NB, DY>), dim3(b.ngpart), dim3(256), 0, s, b.ypart, b.ksplit,
                          yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
                          accumulate ? 1 : 0);
     };

@@ -162,7 +162,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.part = c.take(op == PPCA_OP_PROJECT
                       ? 16
                       : (size_t)p.ntiles * p.nsplit * p.Kp * xty_cols(p.Kp) * sizeof(float));
-  p.ngpart = xv_grid(dtype, p.Kp, p.rows_cap);
+  p.ngpart = xv_grid(dtype, p.Kp, d, p.rows_cap);
   p.gpart = c.take((size_t)p.ngpart * p.Kp * p.Kp * sizeof(float));
   p.ksplit = xv_ksplit(dtype, p.Kp, d, p.rows_cap);
   p.ypart = c.take(p.ksplit > 1 ? (size_t)p.ksplit * round_up(p.rows_cap, 64) * p.Kp * sizeof(float)

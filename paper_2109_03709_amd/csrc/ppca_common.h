@@ -67,7 +67,7 @@ struct StreamBufs {
   void* yb;             // Y staging buffer (blocked rows), sized for chunk rows
   int64_t rows_cap;     // rows the staging buffer holds (largest chunk of a pass)
   float* part;          // Z partials [ntiles][nsplit][Kp][xty_cols(Kp)]
-  float* gpart;         // G partials [ngpart][Kp][Kp], one per k_xv workgroup
+  float* gpart;         // G partials [ngpart][Kp][Kp], one per k_xv (or k_ysum) workgroup
   int nsplit;           // row splits of the X^T Y kernel
   int ngpart;           // workgroups of k_xv (fixed for all chunks of a pass)
   int Kp;               // K padded to 16
@@ -81,7 +81,7 @@ int xty_cols(int Kp);              // columns per tile of the X^T Y kernel
 int xty_blocks_per_cu(int Kp);     // resident workgroups per CU of the X^T Y kernel
 constexpr int kNumCU = 256;        // compute units of an MI355X
 int xty_tiles(int64_t d, int Kp);  // column tiles of X in the X^T Y kernel
-int xv_grid(int32_t dtype, int Kp, int64_t rows_cap);   // workgroups of k_xv
+int xv_grid(int32_t dtype, int Kp, int64_t d, int64_t rows_cap);   // workgroups of k_xv
 hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
                      bool want_y, bool want_g, bool accumulate, hipStream_t s);
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,

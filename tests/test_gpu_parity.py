@@ -86,7 +86,8 @@ def test_project_gram(dtype, n, d, K, pad):
 # ------------------------------------------------------- the streaming pass
 @pytest.mark.parametrize("dtype", [F32, BF16, FP8])
 @pytest.mark.parametrize("n,d,K,r0,rows", [(5003, 300, 64, 0, 5003), (4000, 1024, 128, 3900, 1024),
-                                            (1500, 77, 5, 17, 999), (20000, 512, 32, 123, 20000)])
+                                            (1500, 77, 5, 17, 999), (20000, 512, 32, 123, 20000),
+                                            (3000, 200, 70, 11, 2500)])
 def test_stream_pass_elementwise_bound(dtype, n, d, K, r0, rows):
     """Z = X^T (X V') and G on a (wrapping) row range.  Elementwise bound:
     |Z - Z_ref| <= c |X|^T |Y| with c = 2^-8 when Y is rounded to bf16 before
