@@ -8,6 +8,9 @@
 //               are widened to bf16 exactly when read from LDS)
 //   k_xvy     : Y = X V' of the power pass for bf16 data (one DMA pipeline
 //               over all tiles of a workgroup, Y stored from the accumulators)
+//   k_ysum    : short passes (few 64-row tiles) split their columns over
+//               several workgroups of k_xvd / k_xv in partial mode; this sums
+//               the float32 Y partials, writes Y and the G partials
 //   k_xtyd    : Z = X^T Y over (256-column tile, row split) pairs (LDS-DMA)
 //   reduce_zg : fixed-order float64 sum of the partials -> Z (f32), G (f64)
 //
@@ -32,7 +35,8 @@
 //         bf16: yb[row/8][Kp][8], f32: yb[row/4][Kp][4].
 //   part  [tile][split][Kp][256] float32: column c of tile t is column
 //         t*256 + c of X.
-//   gpart [workgroup of the Y = X V' kernel][Kp][Kp] float32.
+//   gpart [workgroup of the Y = X V' kernel, or of k_ysum][Kp][Kp] float32.
+//   ypart [split][rows rounded to 64][Kp] float32 (short passes only).
 #include "lds_dma.h"
 
 namespace ppca {
