@@ -72,7 +72,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; run with --gpus 1"}))
         sys.exit(2)
     if a.workload == "grouped-bf16":
         return main_grouped(a)
