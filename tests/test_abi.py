@@ -66,3 +66,36 @@ def test_host_only_calls():
                               ctypes.c_void_p(256), 1 << 30, None) == -1   # k = 0
     assert L.ppca_prime_power(ctypes.byref(ok), 64, 1, 1, ctypes.c_void_p(16), None, None,
                               ctypes.c_void_p(256), 1 << 30, None) == -1   # K > d
+
+
+def test_grouped_work_split_host_calls():
+    """Work-item size of the grouped calls: range check of the setter, and the
+    workspace of a plan grows as the items shrink (more partial sums); a
+    too-small workspace is rejected by the tuner before anything runs."""
+    from paper_2109_03709_amd import _lib
+    L = _lib.lib()
+    probs = (_lib._Problem * 2)()
+    for p, (n, d, k) in enumerate([(50_000, 256, 8), (20_000, 768, 16)]):
+        probs[p].X = _lib._Matrix(16, n, d, d, _lib.BF16, 0)
+        probs[p].k, probs[p].l = k, k
+        probs[p].V = probs[p].G = probs[p].B = 16
+    assert L.ppca_set_group_item_bytes(1024) == -1
+    assert L.ppca_set_group_item_bytes(1 << 31) == -1
+    small = L.ppca_grouped_workspace_bytes_for(probs, 2, 1 << 20)
+    large = L.ppca_grouped_workspace_bytes_for(probs, 2, 8 << 20)
+    assert small > large > 0
+    assert L.ppca_grouped_workspace_bytes_for(probs, 2, 1024) == 0    # out of range
+    try:
+        assert L.ppca_set_group_item_bytes(1 << 20) == 0
+        assert L.ppca_grouped_workspace_bytes(probs, 2) == small
+    finally:
+        assert L.ppca_set_group_item_bytes(0) == 0
+    assert L.ppca_grouped_workspace_bytes(probs, 2) == L.ppca_grouped_workspace_bytes_for(
+        probs, 2, 3 << 20)
+    cand = (ctypes.c_int64 * 2)(1 << 20, 4 << 20)
+    best = ctypes.c_int64(0)
+    assert L.ppca_tune_group_items(probs, 2, cand, 2, ctypes.c_void_p(256), 4096, None,
+                                   ctypes.byref(best), None) == -6
+    bad = (ctypes.c_int64 * 1)(100)
+    assert L.ppca_tune_group_items(probs, 2, bad, 1, ctypes.c_void_p(256), 1 << 40, None,
+                                   ctypes.byref(best), None) == -1
