@@ -26,7 +26,7 @@
 //   dci 1: dc 128, WD 1, CW 2  (four independent row groups; two waves per
 //          row tile measured slower: their exchange costs as much as the
 //          64 columns each wave reads)
-//   dci 2: dc 256, WD 4, CW 1
+//   dci 2: dc 256, WD 2, CW 2  (two row groups)
 //   dci 3: dc 512, WD 4, CW 2
 //   dci 4: dc 768, WD 4, CW 3
 // combined with NB2 = Kp / 32 in 1..2 (K padded to 32): 10 code paths in one
@@ -44,7 +44,7 @@ int group_class_width(int dci) {
   static const int w[kGroupClasses] = {64, 128, 256, 512, 768};
   return w[dci];
 }
-int group_row_groups(int dci) { return dci <= 1 ? 4 : 1; }
+int group_row_groups(int dci) { return dci <= 1 ? 4 : (dci == 2 ? 2 : 1); }
 int group_dci(int64_t d) {
   for (int i = 0; i < kGroupClasses; ++i)
     if (d <= group_class_width(i)) return i;
@@ -59,8 +59,8 @@ using dev::status_set;
 
 template <int NB2, int DCI>
 struct GCls {
-  static constexpr int WD = DCI <= 1 ? 1 : 4;                    // waves sharing a row tile
-  static constexpr int CW = DCI == 1 ? 2 : (DCI <= 2 ? 1 : DCI - 1);   // 64-column groups per wave
+  static constexpr int WD = DCI <= 1 ? 1 : (DCI == 2 ? 2 : 4);   // waves sharing a row tile
+  static constexpr int CW = DCI <= 2 ? (DCI == 0 ? 1 : 2) : DCI - 1;   // 64-column groups per wave
   static constexpr int WR = 4 / WD;                              // row groups
   static constexpr int DW = 64 * CW;                             // columns per wave
   static constexpr int DC = WD * DW;                             // class width
