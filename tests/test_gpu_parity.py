@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the float64 oracle on
 the same seeded inputs.  Sizes span several tiles and ragged tails.
 
-Tolerances (derived in the design doc):
+Tolerances (each derived from the arithmetic of the step it bounds):
 * centring / storage codes: bit-exact (integer results);
 * Gram of the projected data: f32 data 2e-5, bf16/fp8 data 4e-3 of
   sqrt(G_ii G_jj) (the bf16 rounding of Y before the Gram bounds it by 2^-8);
