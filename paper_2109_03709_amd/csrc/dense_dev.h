@@ -58,15 +58,22 @@ __device__ inline f64x4_t mma16(f64x4_t d, FA a, FB b) {
   return d;
 }
 
+// LDS doubles chol_inv_dev<KM> works in (passed in by the caller, so that a
+// kernel can reuse the area for its other phases)
 template <int KM>
-__device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double* __restrict__ R,
-                                    double* __restrict__ Rinv, int* status) {
+constexpr int chol_lds_doubles() {
+  return KM * (KM + 1) + (KM / 16) * 16 * 17 + KM + 16;
+}
+
+template <int KM>
+__device__ __attribute__((always_inline)) inline void chol_inv_dev(const double* __restrict__ A, int K, double* __restrict__ R,
+                                    double* __restrict__ Rinv, int* status, double* lds) {
   constexpr int LDM = KM + 1, BS = 16, NBK = KM / BS, LDX = BS + 1;
   static_assert(KM % BS == 0 && KM <= 128, "block shape");
-  __shared__ double M[KM * LDM];      // odd row stride: column reads spread banks
-  __shared__ double XD[NBK * BS * LDX];   // inverses of the diagonal blocks
-  __shared__ double dg[KM];
-  __shared__ double ub[BS];           // pivot row broadcast
+  double* const M = lds;                     // [KM][LDM]; odd row stride: column reads spread banks
+  double* const XD = M + KM * LDM;           // [NBK][BS][LDX]: inverses of the diagonal blocks
+  double* const dg = XD + NBK * BS * LDX;    // [KM]
+  double* const ub = dg + KM;                // [BS]: pivot row broadcast
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g4 = lane >> 4;
@@ -105,12 +112,9 @@ __device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double*
     // lanes 0..15 and store nothing)
     if (wave == 0) {
       const int c = l16;
-      double col[BS], rv[BS], tol[BS];
+      double col[BS], rv[BS];
 #pragma unroll
-      for (int i = 0; i < BS; ++i) {
-        col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
-        tol[i] = (double)K * kEps * fabs(dg[j0 + i]);
-      }
+      for (int i = 0; i < BS; ++i) col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
       bool ok = true;
 #pragma unroll
       for (int p = 0; p < BS; ++p) {
@@ -124,7 +128,8 @@ __device__ inline void chol_inv_dev(const double* __restrict__ A, int K, double*
         // uniform: every lane holds the same pivot; after a failure the
         // values are garbage and are not stored (no short-circuit: no branch
         // in the pivot chain)
-        ok = ok & (bool)isfinite(piv) & (piv > tol[p]) & (piv > 0.0);
+        const double tol = (double)K * kEps * fabs(dg[j0 + p]);
+        ok = ok & (bool)isfinite(piv) & (piv > tol) & (piv > 0.0);
         const double rinv = rsqrt(fabs(piv));
         rv[p] = rinv;
         const double rpc = (c == p) ? fabs(piv) * rinv : ((c > p) ? col[p] * rinv : 0.0);

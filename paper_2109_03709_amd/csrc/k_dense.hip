@@ -124,7 +124,8 @@ __global__ __launch_bounds__(256) void k_sum_gram(const double* __restrict__ par
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ A, int K,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv, int* status) {
-  dev::chol_inv_dev<kMaxK>(A, K, R, Rinv, status);
+  __shared__ double lds[dev::chol_lds_doubles<kMaxK>()];
+  dev::chol_inv_dev<kMaxK>(A, K, R, Rinv, status, lds);
 }
 
 // --------------------------------------------------------------------------

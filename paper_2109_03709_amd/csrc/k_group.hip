@@ -607,11 +607,20 @@ __global__ __launch_bounds__(256) void k_goperand(const GProb* __restrict__ prob
 // CholeskyQR2 of Z (or of V when from_v) for problem blockIdx.x: V = Q, the
 // operand vop[c][j] = bf16(V[j][c]) (zero for j >= d or c >= K, up to Kp x dc)
 // and, with want_b, B = V'^T V' of the bf16 values.
+//
+// The staging area and the R^-1 copy of the block products share one LDS
+// array with the Cholesky (the phases are separated by barriers): 66 KB per
+// workgroup.  Registers still allow one workgroup per CU; bounding the kernel
+// to two per CU spills and measured slower, as the time of a call is the
+// chain of its largest problems rather than the number of resident ones.
+constexpr int kGCholLds = kGStg * kGSp + 64 * 64;
 __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ probs,
-                                                  const int* __restrict__ order, int from_v,
-                                                  int want_b, int* status) {
-  __shared__ double stg[kGStg * kGSp];
-  __shared__ double Rl[64 * 64];
+                                                     const int* __restrict__ order, int from_v,
+                                                     int want_b, int* status) {
+  static_assert(dev::chol_lds_doubles<kGroupMaxK>() <= kGCholLds, "Cholesky area");
+  __shared__ double lds[kGCholLds];
+  double* const stg = lds;
+  double* const Rl = lds + kGStg * kGSp;
   const GProb& P = probs[order[blockIdx.x]];
   const int64_t d = P.d;
   const int K = P.K;
@@ -619,12 +628,12 @@ __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ prob
   double* q1 = P.q1;
   float* V = P.V;
   gram_wg([&](int64_t r, int c) { return (double)src[r * K + c]; }, d, K, P.A, stg);
-  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status);
+  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status, lds);
   __syncthreads();
   trmm_wg([&](int64_t r, int c) { return (double)src[r * K + c]; }, d, K, P.Rinv, Rl, stg,
           [&](int64_t r, int c, double v) { q1[r * K + c] = v; });
   gram_wg([&](int64_t r, int c) { return q1[r * K + c]; }, d, K, P.A, stg);
-  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status);
+  dev::chol_inv_dev<kGroupMaxK>(P.A, K, P.R, P.Rinv, status, lds);
   __syncthreads();
   trmm_wg([&](int64_t r, int c) { return q1[r * K + c]; }, d, K, P.Rinv, Rl, stg,
           [&](int64_t r, int c, double v) { V[r * K + c] = (float)v; });
@@ -639,12 +648,15 @@ __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ prob
 // Rayleigh-Ritz, part 1: R = chol(B), T = G R^-1, H = (R^-T T) / n.
 __global__ __launch_bounds__(256) void k_grr_h(const GProb* __restrict__ probs,
                                                const int* __restrict__ order, int* status) {
-  __shared__ double Rl[64 * 64];
-  __shared__ double Gl[64 * 64];
-  __shared__ double Tl[64 * 64];
+  __shared__ double sh[3 * 64 * 64];
+  double* const Rl = sh;
+  double* const Gl = sh + 64 * 64;
+  double* const Tl = sh + 2 * 64 * 64;
   const GProb& P = probs[order[blockIdx.x]];
   const int K = P.K, t = threadIdx.x;
-  dev::chol_inv_dev<kGroupMaxK>(P.B, K, P.R, P.Rinv, status);
+  // the Cholesky works in the area of Gl and Tl, which are filled after it
+  static_assert(dev::chol_lds_doubles<kGroupMaxK>() <= 2 * 64 * 64, "Cholesky area");
+  dev::chol_inv_dev<kGroupMaxK>(P.B, K, P.R, P.Rinv, status, Gl);
   __syncthreads();
   for (int e = t; e < K * K; e += 256) {
     Rl[e] = P.Rinv[e];
