@@ -40,11 +40,22 @@
 
 namespace ppca {
 
-int group_class_width(int dci) {
-  static const int w[kGroupClasses] = {64, 128, 256, 512, 768};
-  return w[dci];
+// The class table above, the one definition that both the kernel (its wave
+// layout) and the host plan (the number of partials per item) use.
+constexpr int kClassWidth[kGroupClasses] = {64, 128, 256, 512, 768};
+constexpr int kClassWD[kGroupClasses] = {1, 1, 2, 4, 4};   // waves sharing a row tile
+constexpr int kClassCW[kGroupClasses] = {1, 2, 2, 2, 3};   // 64-column groups per wave
+constexpr bool class_table_ok() {
+  for (int i = 0; i < kGroupClasses; ++i)
+    if (64 * kClassWD[i] * kClassCW[i] != kClassWidth[i] || 4 % kClassWD[i] != 0 ||
+        (i > 0 && kClassWidth[i] <= kClassWidth[i - 1]))
+      return false;
+  return true;
 }
-int group_row_groups(int dci) { return dci <= 1 ? 4 : (dci == 2 ? 2 : 1); }
+static_assert(class_table_ok(), "class widths, wave split and order");
+
+int group_class_width(int dci) { return kClassWidth[dci]; }
+int group_row_groups(int dci) { return 4 / kClassWD[dci]; }
 int group_dci(int64_t d) {
   for (int i = 0; i < kGroupClasses; ++i)
     if (d <= group_class_width(i)) return i;
@@ -59,8 +70,8 @@ using dev::status_set;
 
 template <int NB2, int DCI>
 struct GCls {
-  static constexpr int WD = DCI <= 1 ? 1 : (DCI == 2 ? 2 : 4);   // waves sharing a row tile
-  static constexpr int CW = DCI <= 2 ? (DCI == 0 ? 1 : 2) : DCI - 1;   // 64-column groups per wave
+  static constexpr int WD = kClassWD[DCI];                       // waves sharing a row tile
+  static constexpr int CW = kClassCW[DCI];                       // 64-column groups per wave
   static constexpr int WR = 4 / WD;                              // row groups
   static constexpr int DW = 64 * CW;                             // columns per wave
   static constexpr int DC = WD * DW;                             // class width
