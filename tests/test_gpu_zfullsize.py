@@ -13,6 +13,8 @@ brought to the host in row chunks:
   exact spectrum of the data: eigenvalue relative error 2e-3, orthonormal
   Ritz vectors, and the subspace within the 1e-2 quantisation bound of the
   scaled bf16 case.
+The minibatch workloads (Oja on f32 data, EigenGame on fp8 data) are checked
+at their full sizes on the steps whose rows wrap past the end of the data.
 """
 import numpy as np
 import pytest
@@ -21,7 +23,7 @@ import torch
 from oracle import ppca_oracle as O
 from synthdata import gaussian_block, make_problem_device
 
-from ._gpu_util import BF16, gram_err, operand_basis, sin_theta
+from ._gpu_util import BF16, F32, FP8, gram_err, operand_basis, sin_theta, stored_values
 
 pytestmark = pytest.mark.gpu
 
@@ -98,3 +100,69 @@ def test_full_size_ppca_against_exact_spectrum(workload):
     assert np.max(O.rel_eig_error(evh, lam[:KK])) < 2e-3
     assert np.max(np.abs(Eh.T @ Eh - np.eye(KK))) < 1e-5
     assert sin_theta(Eh, q[:, :KK]) < 1e-2
+
+
+# ------------------------------------------------ minibatch primings, full size
+def _stored_rows(X, rows: np.ndarray, dtype: int) -> np.ndarray:
+    """float64 values of the given rows of the device data (codes x scales)."""
+    codes = X.x[torch.from_numpy(rows).cuda()].cpu()
+    if codes.dtype == torch.bfloat16:
+        codes = codes.view(torch.int16)
+    scale = None if X.col_scale is None else X.col_scale.cpu().numpy()
+    return stored_values(codes.numpy(), dtype, scale)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["eigengame-fp8", "oja-f32"])
+def test_full_size_minibatch_steps_across_the_wrap(name):
+    """The minibatch workloads at their full size (EigenGame: 8,000,000 x 2048
+    fp8, batch 4096, K = 64; Oja: 1,000,000 x 1024 f32, batch 1024, K = 64),
+    three steps resumed from the step whose rows wrap past the end of the
+    data.  The oracle replays the same steps on the rows the schedule names
+    (fetched from the device as stored), with the same bounds as the
+    trajectory tests."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03709_amd as P
+    P.lib()
+    cfg = {"eigengame-fp8": dict(n=8_000_000, d=2048, spec="exp0.97+1e-5", dtype=FP8, k=32,
+                                 l=32, b=4096, eta0=0.2, t0=0.0, seed=1004),
+           "oja-f32": dict(n=1_000_000, d=1024, spec="pow1.2+1e-4", dtype=F32, k=32, l=32,
+                           b=1024, eta0=0.5, t0=1000.0, seed=1002)}[name]
+    n, d, b, dtype = cfg["n"], cfg["d"], cfg["b"], cfg["dtype"]
+    K = cfg["k"] + cfg["l"]
+    t_first = n // b - 1                  # the next step's rows wrap past row n - 1
+    assert (t_first + 1) * b < n < (t_first + 2) * b
+    steps = 3
+    print(f"[fullsize] {name}: generating X {n} x {d}", flush=True)
+    xraw, _, _ = make_problem_device(n, d, cfg["spec"], cfg["seed"], device=torch.device("cuda:0"))
+    X, _ = P.center_quantize(xraw, dtype, out=xraw if dtype == F32 else None)
+    if dtype != F32:
+        del xraw
+    v0 = gaussian_block(d, K, cfg["seed"] + 1000, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    fn = P.prime_eigengame if dtype == FP8 else P.prime_oja
+    fn(X, cfg["k"], cfg["l"], V, batch=b, steps=steps, eta0=cfg["eta0"], t0=cfg["t0"],
+       start_step=t_first)
+    torch.cuda.synchronize()
+    scale = None if X.col_scale is None else X.col_scale.cpu().numpy()
+
+    v = O.cholqr2(v0.astype(np.float64))[0]
+    for t in range(t_first, t_first + steps):
+        xb = _stored_rows(X, O.minibatch_rows(n, b, t), dtype)
+        veff = operand_basis(v.astype(np.float32), dtype, scale)
+        z, g = O.stream_pass(xb, veff)
+        if dtype == FP8:
+            grad = O.eigengame_grad(z, g, b)
+            grad = grad - v * np.sum(v * grad, axis=0)[None, :]
+            v = v + cfg["eta0"] * grad
+            v = v / np.linalg.norm(v, axis=0)[None, :]
+        else:
+            v = v + O.learning_rate(cfg["eta0"], cfg["t0"], t) * O.sanger_direction(z, g, v, b)
+    vg = V.cpu().numpy()
+    del X
+    torch.cuda.empty_cache()
+    if dtype == FP8:
+        assert np.max(np.abs(vg - v)) < 3e-2
+    else:
+        assert np.max(np.abs(vg - v)) / np.max(np.abs(v)) < 1e-4
