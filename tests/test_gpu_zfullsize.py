@@ -14,7 +14,9 @@ brought to the host in row chunks:
   Ritz vectors, and the subspace within the 1e-2 quantisation bound of the
   scaled bf16 case.
 The minibatch workloads (Oja on f32 data, EigenGame on fp8 data) are checked
-at their full sizes on the steps whose rows wrap past the end of the data.
+at their full sizes on the steps whose rows wrap past the end of the data, and
+the 512-problem grouped workload on one step of sampled problems and on every
+problem's result against its exact spectrum.
 """
 import numpy as np
 import pytest
@@ -166,3 +168,82 @@ def test_full_size_minibatch_steps_across_the_wrap(name):
         assert np.max(np.abs(vg - v)) < 3e-2
     else:
         assert np.max(np.abs(vg - v)) / np.max(np.abs(v)) < 1e-4
+
+
+# ---------------------------------------------- grouped problems, full size
+@pytest.fixture(scope="module")
+def grouped_workload():
+    """The 512-problem grouped workload of the benchmark (15.4 GB of bf16
+    data: n from 2,000 to 200,000, d in {64, ..., 768}, k = l in 4..32), same
+    shape, data and start seeds."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import bench
+    import paper_2109_03709_amd as P
+    P.lib()
+    c = bench.GROUPED
+    shapes = bench.grouped_shapes(c)
+    print(f"[fullsize] generating {len(shapes)} grouped problems", flush=True)
+    data, refs, v0s = [], [], []
+    for p, (n, d, k, l, spec) in enumerate(shapes):
+        xraw, lam, q = make_problem_device(n, d, spec, c["data_seed"] + p,
+                                           device=torch.device("cuda:0"))
+        X, _ = P.center_quantize(xraw, BF16)
+        del xraw
+        data.append(X)
+        refs.append((lam[:k].copy(), q[:, :k].copy()))
+        v0s.append(gaussian_block(d, k + l, c["v0_seed"] + p, np.float32))
+    torch.cuda.synchronize()
+    yield P, c, shapes, data, refs, v0s
+    P.set_group_item_bytes(0)
+    del data
+    torch.cuda.empty_cache()
+
+
+def _grouped_problems(P, shapes, data, v0s):
+    return [P.Problem(X, k, l, torch.from_numpy(v0.copy()).cuda()).alloc()
+            for X, (n, d, k, l, _), v0 in zip(data, shapes, v0s)]
+
+
+@pytest.mark.timeout(600)
+def test_full_size_grouped_one_step_sampled(grouped_workload):
+    """One fused power step over all 512 problems; the smallest, the tallest
+    and the widest-and-deepest problems against the oracle's step on their
+    stored data (sin theta 2e-2, the bound of the small grouped cases)."""
+    P, _, shapes, data, _, v0s = grouped_workload
+    probs = _grouped_problems(P, shapes, data, v0s)
+    P.prime_power_grouped(probs, 1)
+    torch.cuda.synchronize()
+    dims = np.array([(n, d, k + l) for (n, d, k, l, _) in shapes], dtype=np.int64)
+    picks = sorted({int(np.argmin(dims[:, 0] * dims[:, 1])), int(np.argmax(dims[:, 0])),
+                    int(np.argmax(dims[:, 1] * 1000 + dims[:, 2]))})
+    for i in picks:
+        n, d, k, l, _ = shapes[i]
+        xs = stored_values(data[i].x.cpu().view(torch.int16).numpy(), BF16, None)
+        v = O.cholqr2(v0s[i].astype(np.float64))[0]
+        z, _ = O.stream_pass(xs, operand_basis(v.astype(np.float32), BF16, None))
+        v1 = O.cholqr2(z)[0]
+        s1 = sin_theta(probs[i].V.cpu().numpy(), v1)
+        assert s1 < 2e-2, f"problem {i}: n={n} d={d} K={k + l}: {s1:.2e}"
+
+
+@pytest.mark.timeout(600)
+def test_full_size_grouped_against_exact_spectra(grouped_workload):
+    """The benchmark's whole grouped step (work split from the autotuner, 12
+    iterations, projection, Rayleigh-Ritz): every problem's eigenvalues within
+    2e-3 of its exact spectrum, orthonormal Ritz vectors, and subspaces within
+    the 1e-2 quantisation bound."""
+    P, c, shapes, data, refs, v0s = grouped_workload
+    probs = _grouped_problems(P, shapes, data, v0s)
+    best, _ = P.tune_group_items(probs)
+    P.set_group_item_bytes(best)
+    P.prime_power_grouped(probs, c["iters"])
+    P.rayleigh_ritz_grouped(probs)
+    torch.cuda.synchronize()
+    for i, (p, (lam_k, q_k)) in enumerate(zip(probs, refs)):
+        ev = p.evals.cpu().numpy()
+        E = p.E.cpu().numpy().astype(np.float64)
+        k = lam_k.size
+        assert np.max(O.rel_eig_error(ev, lam_k)) < 2e-3, f"problem {i}"
+        assert np.max(np.abs(E.T @ E - np.eye(k))) < 1e-5, f"problem {i}"
+        assert sin_theta(E, q_k) < 1e-2, f"problem {i}"
