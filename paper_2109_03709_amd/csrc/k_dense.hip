@@ -112,8 +112,19 @@ __global__ __launch_bounds__(256) void k_sum_gram(const double* __restrict__ par
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / K), j = (int)(e % K);
     const int64_t src = (i / kGT <= j / kGT) ? e : (int64_t)j * K + i;   // lower tiles: mirror
+    // chunks in order, eight loads in flight at a time (the same sum as one
+    // load per step, without a dependent L2 round trip per chunk)
+    const double* q = parts + src;
     double sacc = 0.0;
-    for (int p = 0; p < nparts; ++p) sacc += parts[(int64_t)p * count + src];
+    int p = 0;
+    for (; p + 8 <= nparts; p += 8) {
+      double v[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[w] = q[(int64_t)(p + w) * count];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) sacc += v[w];
+    }
+    for (; p < nparts; ++p) sacc += q[(int64_t)p * count];
     if (!isfinite(sacc)) bad = true;
     out[e] = sacc;
   }
