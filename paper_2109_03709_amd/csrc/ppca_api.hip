@@ -395,11 +395,26 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp,
     gp.pq[p] = c.take((size_t)d * K * sizeof(double));
     gp.pk[p] = c.take(5 * kk + (size_t)K * sizeof(double));
   }
-  // largest items first (X bytes), ties by problem and row: a fixed order
-  std::stable_sort(gp.hi.begin(), gp.hi.end(), [&](const GItem& a, const GItem& b) {
-    const int64_t ca = a.rows * gp.hp[a.prob].d, cb = b.rows * gp.hp[b.prob].d;
-    return ca > cb;
-  });
+  // Order of the items, which workgroup w of the pass takes at positions w,
+  // w + G, w + 2G, ... (G = min(items, CUs)).  Largest estimated cost first:
+  // X bytes, times 1.2 for Kp = 64, whose MFMA work doubles (the measured rate
+  // per class is about 5.4 TB/s at Kp = 32 and 4.5 at Kp = 64); ties by
+  // problem and row, so the order is fixed.  Then every second round of G
+  // items is reversed, so that the workgroups taking the largest item of one
+  // round take the smallest of the next.  Results do not depend on this
+  // order: an item's partial slot and the order of the reduction follow its
+  // position within its problem.
+  auto cost = [&](const GItem& a) {
+    const GProb& P = gp.hp[a.prob];
+    return (a.rows * P.d) * (P.Kp > 32 ? 6 : 5);
+  };
+  std::stable_sort(gp.hi.begin(), gp.hi.end(),
+                   [&](const GItem& a, const GItem& b) { return cost(a) > cost(b); });
+  {
+    const size_t G = std::min<size_t>(gp.hi.size(), (size_t)kNumCU);
+    for (size_t r0 = G; r0 < gp.hi.size(); r0 += 2 * G)
+      std::reverse(gp.hi.begin() + r0, gp.hi.begin() + std::min(gp.hi.size(), r0 + G));
+  }
   gp.ord.resize(nprob);
   for (int p = 0; p < nprob; ++p) gp.ord[p] = p;
   std::stable_sort(gp.ord.begin(), gp.ord.end(), [&](int a, int b) {
