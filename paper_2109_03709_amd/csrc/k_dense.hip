@@ -269,7 +269,12 @@ __global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ E, int64_t
     }
     __syncthreads();
   }
-  const bool flip = E[bi[0] * k + c] < 0.f;
+  // One thread reads the pivot and publishes the decision; every thread
+  // waits for it before any row is negated (the pivot row belongs to one of
+  // the threads, which would otherwise negate it before the others read it).
+  __shared__ int flip;
+  if (threadIdx.x == 0) flip = E[bi[0] * k + c] < 0.f;
+  __syncthreads();
   if (flip)
     for (int64_t j = threadIdx.x; j < d; j += blockDim.x) E[j * k + c] = -E[j * k + c];
 }
