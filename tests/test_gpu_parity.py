@@ -18,8 +18,8 @@ import torch
 from oracle import ppca_oracle as O
 from synthdata import gaussian_block, make_problem
 
-from ._gpu_util import (BF16, F32, FP8, col_cos, device_data, gram_err, host, operand_basis,
-                        sin_theta)
+from ._gpu_util import (BF16, F32, FP8, TRAJ_REL, col_cos, device_data, gram_err, host,
+                        operand_basis, oracle_replay, sin_theta, trajectory_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -214,6 +214,30 @@ def test_rayleigh_ritz_vs_oracle(K, k):
     assert np.linalg.norm(e.T @ e - np.eye(k)) < 1e-5
 
 
+@pytest.mark.parametrize("d,K,k", [(1000, 32, 16), (4099, 64, 64), (513, 8, 3)])
+def test_rayleigh_ritz_sign_rule_wide(d, K, k):
+    """Ritz vectors with more rows than the sign-fix workgroup has threads:
+    every column must equal the oracle's sign-normalised column with the same
+    sign in every row (a column negated only in part would fail), and its
+    largest-magnitude entry must be positive."""
+    p = make_problem(3000, d, "exp0.9", seed=d + K, mode="exact")
+    data, xs, _ = device_data(p.x, F32)
+    v = gaussian_block(d, K, 5, np.float32) + p.q[:, :K].astype(np.float32)
+    vd = torch.from_numpy(v).cuda()
+    G, B = P().project_gram(data, K, vd)
+    for _ in range(3):
+        ev, E = P().rayleigh_ritz(data, K, k, G, B, vd)
+        torch.cuda.synchronize()
+        _, e_ref, _ = O.rayleigh_ritz(G.cpu().numpy(), B.cpu().numpy(), v.astype(np.float64),
+                                      data.n, k)
+        e = E.cpu().numpy().astype(np.float64)
+        signed = np.sum(e * e_ref, axis=0) / (np.linalg.norm(e, axis=0) *
+                                              np.linalg.norm(e_ref, axis=0))
+        assert np.min(signed) > 1 - 1e-9
+        piv = np.argmax(np.abs(e), axis=0)
+        assert np.all(e[piv, np.arange(k)] > 0)
+
+
 def test_counterexample_on_gpu():
     """Sec. 4.1 worked example through the GPU Rayleigh-Ritz: the order swap."""
     eps = 0.1
@@ -298,14 +322,14 @@ def test_oja_trajectory(dtype):
     steps, eta0 = 5, 0.5
     P().prime_oja(data, k, l, V, batch=b, steps=steps, eta0=eta0, t0=1000.0)
     torch.cuda.synchronize()
-    v = O.cholqr2(v0.astype(np.float64))[0]
-    for t in range(steps):
-        veff = operand_basis(v.astype(np.float32), dtype, scale)
-        xb = xs[O.minibatch_rows(n, b, t)]
-        z, g = O.stream_pass(xb, veff)
-        v = v + O.learning_rate(eta0, 1000.0, t) * O.sanger_direction(z, g, v, b)
-    err = np.max(np.abs(V.cpu().numpy() - v)) / np.max(np.abs(v))
-    assert err < (1e-4 if dtype == F32 else 2e-2)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    v = oracle_replay("oja", lambda t: xs[O.minibatch_rows(n, b, t)], v_start, range(steps), b,
+                      eta0, 1000.0, lambda u: operand_basis(u.astype(np.float32), dtype, scale))
+    vg = V.cpu().numpy()
+    if dtype == F32:
+        assert np.max(np.abs(vg - v)) / np.max(np.abs(v)) < 1e-4
+    else:
+        assert trajectory_error(vg, v, v_start) < TRAJ_REL
 
 
 @pytest.mark.parametrize("dtype", [F32, FP8])
@@ -318,17 +342,14 @@ def test_eigengame_trajectory(dtype):
     steps, eta0 = 4, 0.5
     P().prime_eigengame(data, k, l, V, batch=b, steps=steps, eta0=eta0)
     torch.cuda.synchronize()
-    v = O.cholqr2(v0.astype(np.float64))[0]
-    for t in range(steps):
-        veff = operand_basis(v.astype(np.float32), dtype, scale)
-        xb = xs[O.minibatch_rows(n, b, t)]
-        z, g = O.stream_pass(xb, veff)
-        grad = O.eigengame_grad(z, g, b)
-        grad = grad - v * np.sum(v * grad, axis=0)[None, :]
-        v = v + eta0 * grad
-        v = v / np.linalg.norm(v, axis=0)[None, :]
-    err = np.max(np.abs(V.cpu().numpy() - v))
-    assert err < (1e-4 if dtype == F32 else 3e-2)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    v = oracle_replay("eigengame", lambda t: xs[O.minibatch_rows(n, b, t)], v_start, range(steps),
+                      b, eta0, 0.0, lambda u: operand_basis(u.astype(np.float32), dtype, scale))
+    vg = V.cpu().numpy()
+    if dtype == F32:
+        assert np.max(np.abs(vg - v)) < 1e-4
+    else:
+        assert trajectory_error(vg, v, v_start) < TRAJ_REL
 
 
 def test_momentum_and_resume():
