@@ -305,13 +305,14 @@ def stream_pass(x: np.ndarray, v: np.ndarray):
     return x.T @ y, y.T @ y
 
 
-def prime_power(x: np.ndarray, v0: np.ndarray, iters: int):
+def prime_power(x: np.ndarray, v0: np.ndarray, iters: int, operand=None):
     """V_0 = orth(V0); for t = 1..iters: (Z, G_{t-1}) = pass(X, V_{t-1}),
-    V_t = CholQR2(Z).  Returns (V_iters, [G_0 .. G_{iters-1}])."""
+    V_t = CholQR2(Z).  Returns (V_iters, [G_0 .. G_{iters-1}]).
+    ``operand`` as in prime_oja."""
     v, _ = cholqr2(v0)
     grams = []
     for _ in range(iters):
-        z, g = stream_pass(x, v)
+        z, g = stream_pass(x, v if operand is None else operand(v))
         grams.append(g)
         v, _ = cholqr2(z)
     return v, grams
@@ -363,15 +364,19 @@ def _momentum_step(grad, buf, momentum, nesterov):
 def prime_oja(x: np.ndarray, v0: np.ndarray, *, batch: int, steps: int,
               eta0: float, t0: float = 1000.0, momentum: float = 0.0,
               nesterov: bool = False, start_step: int = 0, mom_buf=None,
-              orthonormalise_start: bool = True):
-    """Minibatch Sanger priming.  Returns (V, momentum buffer)."""
+              orthonormalise_start: bool = True, operand=None):
+    """Minibatch Sanger priming.  Returns (V, momentum buffer).
+
+    ``operand`` (optional) maps V to the basis the minibatch is multiplied
+    with in the pass (default: V itself); a low-precision store multiplies
+    with a rounded copy of V while the update acts on V."""
     x = np.asarray(x, np.float64)
     n = x.shape[0]
     v = cholqr2(v0)[0] if orthonormalise_start else np.asarray(v0, np.float64).copy()
     buf = np.zeros_like(v) if mom_buf is None else np.asarray(mom_buf, np.float64).copy()
     for t in range(start_step, start_step + steps):
         xb = x[minibatch_rows(n, batch, t)]
-        z, g = stream_pass(xb, v)
+        z, g = stream_pass(xb, v if operand is None else operand(v))
         step, buf = _momentum_step(sanger_direction(z, g, v, batch), buf, momentum, nesterov)
         v = v + learning_rate(eta0, t0, t) * step
     return v, buf
@@ -406,17 +411,18 @@ def eigengame_grad(z: np.ndarray, g: np.ndarray, b: int) -> np.ndarray:
 def prime_eigengame(x: np.ndarray, v0: np.ndarray, *, batch: int, steps: int,
                     eta0: float, t0: float = 0.0, momentum: float = 0.0,
                     nesterov: bool = False, start_step: int = 0, mom_buf=None,
-                    orthonormalise_start: bool = True):
+                    orthonormalise_start: bool = True, operand=None):
     """All players step together on the same minibatch: Riemannian gradient
     (grad_j - (v_j . grad_j) v_j), optional momentum, ascent step, then each
-    v_j is put back on the unit sphere.  Returns (V, momentum buffer)."""
+    v_j is put back on the unit sphere.  Returns (V, momentum buffer).
+    ``operand`` as in prime_oja."""
     x = np.asarray(x, np.float64)
     n = x.shape[0]
     v = cholqr2(v0)[0] if orthonormalise_start else np.asarray(v0, np.float64).copy()
     buf = np.zeros_like(v) if mom_buf is None else np.asarray(mom_buf, np.float64).copy()
     for t in range(start_step, start_step + steps):
         xb = x[minibatch_rows(n, batch, t)]
-        z, g = stream_pass(xb, v)
+        z, g = stream_pass(xb, v if operand is None else operand(v))
         grad = eigengame_grad(z, g, batch)
         grad = grad - v * np.sum(v * grad, axis=0)[None, :]
         step, buf = _momentum_step(grad, buf, momentum, nesterov)

@@ -139,6 +139,77 @@ def test_eigengame_fixed_point():
     assert np.allclose(np.abs(np.sum(v * u, axis=0)), 1.0, atol=1e-12)
 
 
+def _sphere_fd_gradient(m, v, j, h=1e-5):
+    """Riemannian gradient of U_j (Sec. 2.3, eq. (3)) at the unit vector v_j
+    by central differences of U_j(normalise(v_j + h t)) along an orthonormal
+    basis t of the tangent space {t : t . v_j = 0}; the other players fixed."""
+    d = v.shape[0]
+    vj = v[:, j]
+    q, _ = np.linalg.qr(np.column_stack([vj, np.eye(d)]))
+    tangents = q[:, 1:d]
+    g = np.zeros(d)
+    for t in tangents.T:
+        vp = v.copy()
+        vp[:, j] = (vj + h * t) / np.linalg.norm(vj + h * t)
+        vm = v.copy()
+        vm[:, j] = (vj - h * t) / np.linalg.norm(vj - h * t)
+        g += (O.eigengame_utility(m, vp, j) - O.eigengame_utility(m, vm, j)) / (2 * h) * t
+    return g
+
+
+def _eigengame_step_error(step_fn, seed):
+    """One step V1 = step_fn(V0) with unit columns, full batch, constant rate
+    eta.  A step normalise(v + eta g) with g tangent to the sphere at v has
+    (I - v v^T) v1 / (eta (v1 . v)) = g exactly; the result is compared with
+    the finite-difference Riemannian gradient.  Returns the largest relative
+    deviation over the players and whether every player's own utility rose
+    (the others held at V0) and every column stayed on the unit sphere."""
+    rng = np.random.default_rng(seed)
+    b, d, kk, eta = 13, 7, 4, 0.05
+    xb = rng.standard_normal((b, d)) * np.sqrt(np.linspace(3.0, 0.2, d))[None, :]
+    v0 = rng.standard_normal((d, kk))
+    v0 /= np.linalg.norm(v0, axis=0)[None, :]
+    m = xb.T @ xb / b
+    v1 = step_fn(xb, v0, batch=b, steps=1, eta0=eta, t0=0.0, orthonormalise_start=False)[0]
+    worst, rises = 0.0, True
+    for j in range(kk):
+        vj, wj = v0[:, j], v1[:, j]
+        g_step = (wj - vj * (vj @ wj)) / (eta * (vj @ wj))
+        g_fd = _sphere_fd_gradient(m, v0, j)
+        worst = max(worst, float(np.linalg.norm(g_step - g_fd) / np.linalg.norm(g_fd)))
+        vt = v0.copy()
+        vt[:, j] = wj
+        rises &= O.eigengame_utility(m, vt, j) > O.eigengame_utility(m, v0, j)
+    on_sphere = bool(np.allclose(np.linalg.norm(v1, axis=0), 1.0, atol=1e-14))
+    return worst, rises, on_sphere
+
+
+def _eigengame_mutant_without_projection():
+    """The oracle's EigenGame loop with the tangent projection deleted (a
+    plausible bug: stepping along the Euclidean gradient, then renormalising)."""
+    import inspect
+    src = inspect.getsource(O.prime_eigengame).splitlines()
+    kept = [line for line in src if "grad - v * np.sum(v * grad" not in line]
+    assert len(kept) == len(src) - 1
+    ns = dict(vars(O))
+    exec("\n".join(kept), ns)
+    return ns["prime_eigengame"]
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_eigengame_step_on_the_sphere(seed):
+    """Sec. 2.3: each player ascends its utility on the unit sphere.  One
+    oracle step moves every v_j along the finite-difference Riemannian
+    gradient of eq. (3) (rel 1e-6), raises every U_j and keeps |v_j| = 1.
+    The same check run on a copy without the tangent projection fails: the
+    radial part of the Euclidean gradient shrinks every step by a factor
+    1 / (1 + eta v_j . grad_j)."""
+    worst, rises, on_sphere = _eigengame_step_error(O.prime_eigengame, seed)
+    assert worst < 1e-6 and rises and on_sphere
+    worst_m, _, _ = _eigengame_step_error(_eigengame_mutant_without_projection(), seed)
+    assert worst_m > 1e-3
+
+
 def test_momentum_matches_torch_sgd_nesterov():
     """Sec. 5 trains with SGD + Nesterov momentum 0.9; the oracle's update is
     pinned to torch.optim.SGD (ascent: the gradient handed to torch is -g)."""
