@@ -85,3 +85,40 @@ def device_data(x32: np.ndarray, dtype: int, ld: int | None = None):
     scale = None if data.col_scale is None else data.col_scale.cpu().numpy()
     codes = host(data.x.contiguous())
     return data, stored_values(codes, dtype, scale), scale
+
+
+# ---------------------------------------------------- minibatch trajectories
+# On low-precision data the GPU multiplies X by the rounded operand V' (which
+# the oracle models through its `operand` hook) and rounds Y = X V' to bf16
+# before the second product (which the oracle does not model: it is part of
+# the kernel's arithmetic, not of the method).  That rounding, unit roundoff
+# 2^-9, perturbs each step's direction to first order, so the distance between
+# the two trajectories is bounded relative to how far V moved:
+#     |V_gpu - V_or|_F <= TRAJ_REL |V_or - V_start|_F.
+# tests/test_trajectory_bounds.py shows on the CPU that a replay of the GPU's
+# roundings stays an order of magnitude inside it, while a step that does
+# nothing, a halved rate, a dropped tangent projection (EigenGame) or a dropped
+# triangular term (Sanger) all fail it, at the full-size fp8 EigenGame shape.
+TRAJ_REL = 2.0 ** -9
+
+
+def trajectory_error(v_gpu, v_or, v_start) -> float:
+    """|V_gpu - V_or|_F / |V_or - V_start|_F."""
+    v_or = np.asarray(v_or, np.float64)
+    return float(np.linalg.norm(np.asarray(v_gpu, np.float64) - v_or) /
+                 np.linalg.norm(v_or - np.asarray(v_start, np.float64)))
+
+
+def oracle_replay(method: str, rows_of_step, v_start, steps, batch: int, eta0: float,
+                  t0: float, operand=None):
+    """The oracle's own minibatch loop (prime_oja / prime_eigengame), one step
+    at a time on the rows the schedule names: rows_of_step(t) returns the
+    float64 rows of step t, and the step's rate eta_t = eta0 / (1 + t/t0) is
+    passed as a constant rate.  ``steps`` is an iterable of global step
+    indices.  Returns V after the last step."""
+    fn = {"oja": O.prime_oja, "eigengame": O.prime_eigengame}[method]
+    v = np.asarray(v_start, np.float64)
+    for t in steps:
+        v = fn(rows_of_step(t), v, batch=batch, steps=1, eta0=O.learning_rate(eta0, t0, t),
+               t0=0.0, orthonormalise_start=False, operand=operand)[0]
+    return v

@@ -25,7 +25,8 @@ import torch
 from oracle import ppca_oracle as O
 from synthdata import gaussian_block, make_problem_device
 
-from ._gpu_util import BF16, F32, FP8, gram_err, operand_basis, sin_theta, stored_values
+from ._gpu_util import (BF16, F32, FP8, TRAJ_REL, gram_err, operand_basis, oracle_replay,
+                        sin_theta, stored_values, trajectory_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -149,23 +150,16 @@ def test_full_size_minibatch_steps_across_the_wrap(name):
     torch.cuda.synchronize()
     scale = None if X.col_scale is None else X.col_scale.cpu().numpy()
 
-    v = O.cholqr2(v0.astype(np.float64))[0]
-    for t in range(t_first, t_first + steps):
-        xb = _stored_rows(X, O.minibatch_rows(n, b, t), dtype)
-        veff = operand_basis(v.astype(np.float32), dtype, scale)
-        z, g = O.stream_pass(xb, veff)
-        if dtype == FP8:
-            grad = O.eigengame_grad(z, g, b)
-            grad = grad - v * np.sum(v * grad, axis=0)[None, :]
-            v = v + cfg["eta0"] * grad
-            v = v / np.linalg.norm(v, axis=0)[None, :]
-        else:
-            v = v + O.learning_rate(cfg["eta0"], cfg["t0"], t) * O.sanger_direction(z, g, v, b)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    v = oracle_replay("eigengame" if dtype == FP8 else "oja",
+                      lambda t: _stored_rows(X, O.minibatch_rows(n, b, t), dtype), v_start,
+                      range(t_first, t_first + steps), b, cfg["eta0"], cfg["t0"],
+                      lambda u: operand_basis(u.astype(np.float32), dtype, scale))
     vg = V.cpu().numpy()
     del X
     torch.cuda.empty_cache()
     if dtype == FP8:
-        assert np.max(np.abs(vg - v)) < 3e-2
+        assert trajectory_error(vg, v, v_start) < TRAJ_REL
     else:
         assert np.max(np.abs(vg - v)) / np.max(np.abs(v)) < 1e-4
 
