@@ -220,7 +220,8 @@ def test_rayleigh_ritz_sign_rule_wide(d, K, k):
     every column must equal the oracle's sign-normalised column with the same
     sign in every row (a column negated only in part would fail), and its
     largest-magnitude entry must be positive."""
-    p = make_problem(3000, d, "exp0.9", seed=d + K, mode="exact")
+    # the Ritz values only need the projected Gram: Gaussian rows suffice at n < d
+    p = make_problem(3000, d, "exp0.9", seed=d + K, mode="gaussian")
     data, xs, _ = device_data(p.x, F32)
     v = gaussian_block(d, K, 5, np.float32) + p.q[:, :K].astype(np.float32)
     vd = torch.from_numpy(v).cuda()
