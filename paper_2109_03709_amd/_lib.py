@@ -27,7 +27,9 @@ EXPORTS = [
     "ppca_set_kernel_timing", "ppca_kernel_stats", "ppca_set_chunk_rows",
     "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
     "ppca_grouped_workspace_bytes_for", "ppca_set_group_item_bytes", "ppca_tune_group_items",
+    "ppca_rayleigh_ritz_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 16 << 20
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
 
 
@@ -79,6 +81,7 @@ def lib():
         L.ppca_stream_pass.argtypes = [mp, i32, vp, i64, i64, vp, vp, vp, sz, vp]
         L.ppca_project_gram.argtypes = [mp, i32, vp, vp, vp, vp, sz, vp]
         L.ppca_rayleigh_ritz.argtypes = [mp, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.ppca_rayleigh_ritz_noalloc.argtypes = [mp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.ppca_workspace_bytes.argtypes = [i32, mp, i32, i32]
         L.ppca_workspace_bytes.restype = sz
         L.ppca_strerror.argtypes = [ctypes.c_int]
@@ -277,6 +280,25 @@ def rayleigh_ritz(X: Data, K: int, k: int, G: torch.Tensor, B: torch.Tensor, V: 
     code = lib().ppca_rayleigh_ritz(ctypes.byref(m), K, k, _ptr(G), _ptr(B), _ptr(V), _ptr(E),
                                     _ptr(ev), _ptr(ws), ws.numel(), _stream())
     _check(code, "ppca_rayleigh_ritz")
+    return ev, E
+
+
+def rayleigh_ritz_noalloc(X: Data, K: int, k: int, G: torch.Tensor, B: torch.Tensor,
+                          V: torch.Tensor, ev: torch.Tensor, E: torch.Tensor | None = None):
+    """Rayleigh-Ritz into caller-allocated ev (k float64) and E (d x k float32,
+    or None) with no workspace: the library's fixed device scratch is used."""
+    _check_v(V, X.d, K)
+    for t in (G, B):
+        if t.dtype != torch.float64 or t.shape != (K, K) or not t.is_contiguous():
+            raise TypeError("G and B must be contiguous K x K float64")
+    if ev.dtype != torch.float64 or ev.numel() < k or not ev.is_contiguous():
+        raise TypeError("ev must be a contiguous float64 tensor of at least k entries")
+    if E is not None and (E.dtype != torch.float32 or E.shape != (X.d, k) or not E.is_contiguous()):
+        raise TypeError(f"E must be a contiguous ({X.d}, {k}) float32 tensor")
+    m = X.as_c()
+    code = lib().ppca_rayleigh_ritz_noalloc(ctypes.byref(m), K, k, _ptr(G), _ptr(B), _ptr(V),
+                                            _ptr(E), _ptr(ev), _stream())
+    _check(code, "ppca_rayleigh_ritz_noalloc")
     return ev, E
 
 

@@ -15,6 +15,13 @@
 
 using namespace ppca;
 
+// Fixed device scratch of ppca_rayleigh_ritz_noalloc: one copy per GPU the
+// library runs on, held until the process ends, shared by every call on that
+// GPU (calls that overlap on one GPU race on it).
+constexpr size_t kStaticScratchBytes = PPCA_NOALLOC_SCRATCH_BYTES;
+static_assert(kStaticScratchBytes % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 // ------------------------------------------------------------------ knobs
@@ -308,6 +315,70 @@ int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipSt
     if (_rc != PPCA_OK) return _rc; \
   } while (0)
 
+
+int check_rr(const ppca_matrix* X, int K, int k, const double* G, const double* B,
+             const float* V, const float* E, const double* evals) {
+  if (!X || X->n < 1 || X->d < 1) return PPCA_ERR_ARG;
+  if (X->dtype != PPCA_F32 && X->dtype != PPCA_BF16 && X->dtype != PPCA_FP8_E4M3)
+    return PPCA_ERR_DTYPE;
+  if ((X->dtype == PPCA_FP8_E4M3) != (X->col_scale != nullptr)) return PPCA_ERR_DTYPE;
+  if (K < 1 || K > PPCA_MAX_K || K > X->d || k < 1 || k > K) return PPCA_ERR_ARG;
+  if (!G || !B || !evals || (E && !V)) return PPCA_ERR_ARG;
+  return PPCA_OK;
+}
+
+// Rayleigh-Ritz (Alg. 1 step 4) on a validated workspace of plan p.
+int rayleigh_ritz_on(const ppca_matrix* X, int K, int k, const double* G, const double* B,
+                     const float* V, float* E, double* evals, const Plan& p, void* ws,
+                     hipStream_t s) {
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  double* R = at<double>(ws, p.r);
+  double* Ri = at<double>(ws, p.rinv);
+  double* T = at<double>(ws, p.t);
+  double* H = at<double>(ws, p.h);
+  double* W = at<double>(ws, p.w);
+  double* ev = at<double>(ws, p.ev);
+  double* M = at<double>(ws, p.m);
+  HIP_TRY(launch_chol_inv(B, K, R, Ri, st, s));
+  HIP_TRY(launch_small_gemm(G, false, Ri, T, K, K, K, K, K, K, 1.0, st, s));
+  HIP_TRY(launch_small_gemm(Ri, true, T, H, K, K, K, K, K, K, 1.0 / (double)X->n, st, s));
+  HIP_TRY(launch_jacobi(H, K, W, ev, 60, st, s));
+  HIP_TRY(launch_copy_f64(ev, evals, k, s));
+  if (E) {
+    RET_IF(make_operand(X, V, p, ws, s));
+    HIP_TRY(launch_small_gemm(Ri, false, W, M, K, k, K, K, K, k, 1.0, st, s));
+    HIP_TRY(launch_rotate(at<double>(ws, p.veff), X->d, p.Kp, K, M, k, E, st, s));
+    HIP_TRY(launch_sign_fix(E, X->d, k, st, s));
+  }
+  return finish(p, ws, s);
+}
+
+// ------------------------------------------------------- fixed device scratch
+// Per-device address of the file-scope scratch array (host code must not
+// pass the array's own name to a kernel: on the host it is only a stand-in
+// for the symbol).  Looked up once per device, with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(hipStream_t s, void** out) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur < 0 || cur >= kMaxDevices) return PPCA_ERR_HIP;
+  hipDevice_t sdev = -1;
+  if (hipStreamGetDevice(s, &sdev) != hipSuccess) return PPCA_ERR_HIP;
+  if (sdev != cur) return PPCA_ERR_ARG;   // the stream must belong to the current device
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[cur]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return PPCA_ERR_HIP;
+    if ((reinterpret_cast<uintptr_t>(ptr) % kAlign) != 0) return PPCA_ERR_HIP;
+    g_scratch_ptr[cur] = ptr;
+  }
+  *out = g_scratch_ptr[cur];
+  return PPCA_OK;
+}
 
 // ---------------------------------------------------------- grouped problems
 constexpr int64_t kGroupItemBytes = 3 << 20;   // X bytes per work item (default target)
@@ -644,36 +715,21 @@ int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V, double* G
 int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k, const double* G,
                        const double* B, const float* V, float* E, double* evals, void* ws,
                        size_t ws_bytes, void* stream) {
-  if (!X || X->n < 1 || X->d < 1) return PPCA_ERR_ARG;
-  if (X->dtype != PPCA_F32 && X->dtype != PPCA_BF16 && X->dtype != PPCA_FP8_E4M3)
-    return PPCA_ERR_DTYPE;
-  if ((X->dtype == PPCA_FP8_E4M3) != (X->col_scale != nullptr)) return PPCA_ERR_DTYPE;
-  if (K < 1 || K > PPCA_MAX_K || K > X->d || k < 1 || k > K) return PPCA_ERR_ARG;
-  if (!G || !B || !evals || (E && !V)) return PPCA_ERR_ARG;
+  RET_IF(check_rr(X, K, k, G, B, V, E, evals));
   const Plan p = make_plan(PPCA_OP_RR, X->n, X->d, X->dtype, K, 0);
   RET_IF(check_ws(ws, ws_bytes, p));
-  hipStream_t s = (hipStream_t)stream;
-  int* st = at<int>(ws, p.status);
-  HIP_TRY(launch_zero(st, 256, s));
-  double* R = at<double>(ws, p.r);
-  double* Ri = at<double>(ws, p.rinv);
-  double* T = at<double>(ws, p.t);
-  double* H = at<double>(ws, p.h);
-  double* W = at<double>(ws, p.w);
-  double* ev = at<double>(ws, p.ev);
-  double* M = at<double>(ws, p.m);
-  HIP_TRY(launch_chol_inv(B, K, R, Ri, st, s));
-  HIP_TRY(launch_small_gemm(G, false, Ri, T, K, K, K, K, K, K, 1.0, st, s));
-  HIP_TRY(launch_small_gemm(Ri, true, T, H, K, K, K, K, K, K, 1.0 / (double)X->n, st, s));
-  HIP_TRY(launch_jacobi(H, K, W, ev, 60, st, s));
-  HIP_TRY(launch_copy_f64(ev, evals, k, s));
-  if (E) {
-    RET_IF(make_operand(X, V, p, ws, s));
-    HIP_TRY(launch_small_gemm(Ri, false, W, M, K, k, K, K, K, k, 1.0, st, s));
-    HIP_TRY(launch_rotate(at<double>(ws, p.veff), X->d, p.Kp, K, M, k, E, st, s));
-    HIP_TRY(launch_sign_fix(E, X->d, k, st, s));
-  }
-  return finish(p, ws, s);
+  return rayleigh_ritz_on(X, K, k, G, B, V, E, evals, p, ws, (hipStream_t)stream);
+}
+
+int ppca_rayleigh_ritz_noalloc(const ppca_matrix* X, int32_t K, int32_t k, const double* G,
+                               const double* B, const float* V, float* E, double* evals,
+                               void* stream) {
+  RET_IF(check_rr(X, K, k, G, B, V, E, evals));
+  const Plan p = make_plan(PPCA_OP_RR, X->n, X->d, X->dtype, K, 0);
+  if (p.total > kStaticScratchBytes) return PPCA_ERR_WORKSPACE;
+  void* ws = nullptr;
+  RET_IF(static_scratch((hipStream_t)stream, &ws));
+  return rayleigh_ritz_on(X, K, k, G, B, V, E, evals, p, ws, (hipStream_t)stream);
 }
 
 int ppca_prime_power_grouped(const ppca_problem* probs, int32_t nprob, int32_t iters,

@@ -99,3 +99,25 @@ def test_grouped_work_split_host_calls():
     bad = (ctypes.c_int64 * 1)(100)
     assert L.ppca_tune_group_items(probs, 2, bad, 1, ctypes.c_void_p(256), 1 << 40, None,
                                    ctypes.byref(best), None) == -1
+
+
+def test_noalloc_rayleigh_ritz_host_checks():
+    """The allocation-free Rayleigh-Ritz validates on the host before touching
+    the device: bad arguments, and a problem whose workspace exceeds the fixed
+    scratch, are rejected with no GPU call."""
+    from paper_2109_03709_amd import _lib
+    L = _lib.lib()
+    assert _lib.NOALLOC_SCRATCH_BYTES == 16 << 20
+    p = ctypes.c_void_p(256)
+    big = _lib._Matrix(16, 1000, 100_000, 100_000, _lib.F32, 0)
+    need = L.ppca_workspace_bytes(_lib.OP_RR, ctypes.byref(big), 128, 0)
+    assert need > _lib.NOALLOC_SCRATCH_BYTES
+    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(big), 128, 8, p, p, p, p, p, None) == -6
+    ok = _lib._Matrix(16, 1000, 64, 64, _lib.F32, 0)
+    assert L.ppca_workspace_bytes(_lib.OP_RR, ctypes.byref(ok), 16, 0) < _lib.NOALLOC_SCRATCH_BYTES
+    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(ok), 0, 1, p, p, p, p, p, None) == -1
+    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(ok), 16, 17, p, p, p, p, p, None) == -1
+    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(ok), 16, 4, None, p, p, p, p, None) == -1
+    fp8_no_scale = _lib._Matrix(16, 1000, 64, 64, _lib.FP8_E4M3, 0)
+    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(fp8_no_scale), 16, 4, p, p, p, p, p,
+                                        None) == -2
