@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--spectrum", default="exp0.9")
     ap.add_argument("--seed", type=int, default=1003)
     ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--single-read", action="store_true",
+                    help="run the power passes with the single-read kernel (ppca_set_fused_pass) "
+                         "instead of the default two kernels (Y = X V', then Z = X^T Y)")
     ap.add_argument("--item-bytes", type=int, default=0,
                     help="grouped workload: work-item size in bytes of X (0 = autotune)")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
@@ -89,6 +92,7 @@ def main():
     n, d, k, l, iters = a.n, a.d, a.k, a.l, a.iters
     K = k + l
     P.set_chunk_rows(a.chunk_rows)
+    P.set_fused_pass(a.single_read)
 
     log(f"generating X: n={n} d={d} spectrum={a.spectrum}")
     t0 = time.perf_counter()
@@ -129,7 +133,8 @@ def main():
         ev, E = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    P_stats = [P.kernel_stats(0), P.kernel_stats(1)]
+    slots = (0, 1, 3)
+    P_stats = {sl: P.kernel_stats(sl) for sl in slots}
     P.set_kernel_timing(False)
     ms_per_step = dt * 1e3 / a.steps
     # each pass over X counts once: one per power iteration and one for the
@@ -137,7 +142,10 @@ def main():
     passes = iters + 1
     xbytes = n * d * es
     value = passes * xbytes / (ms_per_step * 1e-3) / 1e9
-    x_reads = 2 * iters + 1      # reads of X the two-kernel power step actually makes
+    fused = P_stats[3][0] > 0
+    # reads of X the kernels actually make per step: one per power iteration
+    # with the single-read pass, two with the two-kernel pass; one projection
+    x_reads = iters + 1 if fused else 2 * iters + 1
     log(f"{ms_per_step:.2f} ms/step, X-stream {value:.1f} GB/s")
 
     # accuracy of the timed result against the exact spectrum of the data
@@ -148,28 +156,32 @@ def main():
     sin_t = float(np.linalg.norm(qe - q[:, :k] @ (q[:, :k].T @ qe), 2))
 
     # roofline of the dominant streaming kernel: algorithmic bytes of all its
-    # timed launches over their summed duration (HIP events on the launch stream).
-    # The algorithmic bytes of a launch are the X bytes it streams (n d s);
-    # the Y staging traffic is reported beside them, not counted.
-    names = ["ppca_xv (Y = X V', G = Y^T Y)", "ppca_xty (Z = X^T Y)"]
+    # timed launches over their summed duration (HIP events on the launch
+    # stream).  Every launch of these kernels streams X once: its algorithmic
+    # bytes are n d s; the Y staging traffic of the two-kernel pass is
+    # reported beside them, not counted.
+    names = {0: "ppca_xv (Y = X V', G = Y^T Y)", 1: "ppca_xty (Z = X^T Y)",
+             3: "ppca_xxv (single-read power pass, Z = X^T bf16(X V'))"}
+    per = {}
+    for sl in slots:
+        nl, tot = P_stats[sl]
+        if nl:
+            per[sl] = {"kernel": names[sl], "launches": nl, "avg_ms": round(tot / nl, 4),
+                       "achieved_GBs": round(nl * xbytes / (tot * 1e-3) / 1e9, 1)}
+    dom = max(per, key=lambda sl: P_stats[sl][1])
     Kp = int(math.ceil(K / 16) * 16)
     ybytes = n * Kp * (4 if a.storage == "f32" else 2)
-    alg_step = [(iters + 1) * xbytes, iters * xbytes]
-    launches_step = [iters + 1, iters]
-    avg = [s[1] / max(s[0], 1) for s in P_stats]
-    achieved_all = [alg_step[i] * a.steps / max(P_stats[i][1] * 1e-3, 1e-12) / 1e9 for i in range(2)]
-    dom = int(np.argmax([s[1] for s in P_stats]))
-    traffic = measured_traffic(n, d, K, a.storage, iters)
-    roofline = {"bound": "hbm", "achieved": round(achieved_all[dom], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved_all[dom] / HBM_PEAK_GBS, 4),
-                "traffic": traffic[dom] if traffic else None,
+    traffic = measured_traffic(n, d, K, a.storage, iters, fused)
+    roofline = {"bound": "hbm", "achieved": per[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(per[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic.get(dom) if traffic else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                "kernel": names[dom], "avg_ms": round(avg[dom], 4),
-                "alg_bytes_per_launch": alg_step[dom] / launches_step[dom],
-                "y_staging_bytes_per_launch": ybytes,
-                "launches": P_stats[dom][0],
-                "other_kernel": {"kernel": names[1 - dom], "avg_ms": round(avg[1 - dom], 4),
-                                 "achieved_GBs": round(achieved_all[1 - dom], 1)}}
+                "kernel": names[dom], "avg_ms": per[dom]["avg_ms"],
+                "alg_bytes_per_launch": xbytes,
+                "launches": per[dom]["launches"],
+                "other_kernels": [per[sl] for sl in per if sl != dom]}
+    if not fused:
+        roofline["y_staging_bytes_per_launch"] = ybytes
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -177,7 +189,8 @@ def main():
            "dtype": a.storage, "data": "synthetic",
            "config": {"workload": f"ppca-power-{a.storage}", "n": n, "d": d, "k": k, "l": l,
                       "power_iters": iters, "spectrum": a.spectrum, "x_passes_per_step": passes,
-                      "x_reads_per_step": x_reads, "chunk_rows": a.chunk_rows},
+                      "x_reads_per_step": x_reads, "single_read_pass": fused,
+                      "chunk_rows": a.chunk_rows},
            "x_reads_GBs": round(x_reads * xbytes / (ms_per_step * 1e-3) / 1e9, 2),
            "accuracy": {"max_rel_eig_err": rel, "sin_theta_max": sin_t},
            "prep_ms": round(prep_ms, 2),
@@ -198,29 +211,48 @@ def main():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_kernels_bf16_2Mx2048_K128.txt")
+FUSED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_power_fused_bf16_2Mx2048_K128.txt")
 
 
-def measured_traffic(n, d, K, storage, iters):
-    """HBM bytes per launch of [k_xv, k_xty] from the committed counter
-    summary, or None when the workload differs or the kernels' source has
-    changed since the counters were taken."""
+def _counter_file(path, src_name, key, workload):
+    """key = value lines of a committed counter summary, or None when the
+    workload differs or the kernel source changed since it was taken."""
     import hashlib
-    try:
-        kv = {}
-        for line in open(TRAFFIC_FILE):
-            if "=" in line and not line.startswith("#"):
-                key, val = line.split("=", 1)
-                kv[key.strip()] = val.strip()
-        src = os.path.join(ROOT, "paper_2109_03709_amd", "csrc", "k_stream.hip")
-        if hashlib.sha1(open(src, "rb").read()).hexdigest() != kv["k_stream_sha1"]:
-            return None
-        if kv["workload"] != f"n={n} d={d} K={K} {storage}":
-            return None
-        f = lambda k: int(kv[k + ".fetch_bytes"]) + int(kv[k + ".write_bytes"])
-        xv = (iters * f("xv_power") + f("xv_project")) / (iters + 1)
-        return [int(xv), f("xty")]
-    except (OSError, KeyError, ValueError):
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k_, v_ = line.split("=", 1)
+            kv[k_.strip()] = v_.strip()
+    src = os.path.join(ROOT, "paper_2109_03709_amd", "csrc", src_name)
+    if hashlib.sha1(open(src, "rb").read()).hexdigest() != kv[key]:
         return None
+    if kv["workload"] != workload:
+        return None
+    return kv
+
+
+def measured_traffic(n, d, K, storage, iters, fused):
+    """HBM bytes per launch, by timing slot (0: X V', 1: X^T Y, 3: single-read
+    pass), from the committed counter summaries; a slot is missing when its
+    workload differs or its kernel source changed since the counters were taken."""
+    wl = f"n={n} d={d} K={K} {storage}"
+    out = {}
+    try:
+        kv = _counter_file(TRAFFIC_FILE, "k_stream.hip", "k_stream_sha1", wl)
+        if kv:
+            f = lambda k: int(kv[k + ".fetch_bytes"]) + int(kv[k + ".write_bytes"])
+            out[0] = f("xv_project") if fused else int(
+                (iters * f("xv_power") + f("xv_project")) / (iters + 1))
+            out[1] = f("xty")
+    except (OSError, KeyError, ValueError):
+        pass
+    try:
+        kv = _counter_file(FUSED_TRAFFIC_FILE, "k_fused.hip", "k_fused_sha1", wl)
+        if kv:
+            out[3] = int(kv["xxv.fetch_bytes"]) + int(kv["xxv.write_bytes"])
+    except (OSError, KeyError, ValueError):
+        pass
+    return out or None
 
 
 def _timed(torch, fn, reps=3):

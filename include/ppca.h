@@ -66,6 +66,8 @@ extern "C" {
 #define PPCA_ERR_WORKSPACE      (-6)  /* ws is NULL, misaligned or smaller than required */
 #define PPCA_ERR_HIP            (-7)  /* a HIP runtime call failed */
 #define PPCA_ERR_ALIGN          (-8)  /* X base or row stride violates the 16-byte rule */
+#define PPCA_ERR_PLACEMENT      (-9)  /* single-read pass: a cluster's workgroups were not on one XCD */
+#define PPCA_ERR_TIMEOUT       (-10)  /* single-read pass: a bounded wait between workgroups expired */
 
 /* ---- storage types of X ------------------------------------------------- */
 #define PPCA_F32       0   /* float32 */
@@ -302,7 +304,7 @@ const char* ppca_strerror(int status);
  * launch of each streaming kernel and accumulates their elapsed times.
  * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty),
  * 2 = fused grouped pass (power and projection passes of the grouped calls,
- * eager mode only).
+ * eager mode only), 3 = single-read power pass (ppca_set_fused_pass).
  * ppca_kernel_stats returns the number of launches and the total ms since
  * the last reset.  Not thread safe; meant for benchmarks. */
 void ppca_set_kernel_timing(int32_t enable);
@@ -312,6 +314,23 @@ int  ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms);
  * one launch pair).  Chunks bound the size of the Y staging buffer and keep
  * a chunk of X resident in the last-level cache between the two kernels. */
 void ppca_set_chunk_rows(int64_t rows);
+
+/* Single-read power pass (Sec. 2.1 power step): for bf16 data with K padded
+ * to a multiple of 32 (K <= 128) and d <= 8192, the Z-only passes of
+ * ppca_prime_power and ppca_stream_pass (G == NULL) compute Z = X^T bf16(X V')
+ * in one read of X: clusters of workgroups on one XCD split the columns of X,
+ * exchange their float32 partials of Y through the XCD's L2 and keep their
+ * column slice of Z on chip (kernel timing slot 3).  enable = 0 (the
+ * default) runs these passes as two kernels (Y = X V', then Z = X^T Y) like
+ * every other pass: at 2,000,000 x 2048, K = 128 on an MI355X the single-read
+ * pass measured 5.4 ms against 3.35 ms for the two kernels (its 32-row tiles
+ * are bound by L2 round trips of the exchange and by the MFMA latency of two
+ * accumulators, not by HBM).  The setting is process-wide and enters the workspace
+ * plans of later calls (the single-read pass needs its own exchange buffers:
+ * query ppca_workspace_bytes after changing it).  Results of the two forms
+ * differ only in the order of the float32 sums that form Y before its bf16
+ * rounding. */
+void ppca_set_fused_pass(int32_t enable);
 
 #ifdef __cplusplus
 }

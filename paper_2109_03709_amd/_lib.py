@@ -27,7 +27,7 @@ EXPORTS = [
     "ppca_set_kernel_timing", "ppca_kernel_stats", "ppca_set_chunk_rows",
     "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
     "ppca_grouped_workspace_bytes_for", "ppca_set_group_item_bytes", "ppca_tune_group_items",
-    "ppca_rayleigh_ritz_noalloc",
+    "ppca_rayleigh_ritz_noalloc", "ppca_set_fused_pass",
 ]
 NOALLOC_SCRATCH_BYTES = 16 << 20
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
@@ -91,6 +91,8 @@ def lib():
         L.ppca_kernel_stats.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
         L.ppca_set_chunk_rows.argtypes = [i64]
         L.ppca_set_chunk_rows.restype = None
+        L.ppca_set_fused_pass.argtypes = [i32]
+        L.ppca_set_fused_pass.restype = None
         pp = ctypes.POINTER(_Problem)
         L.ppca_prime_power_grouped.argtypes = [pp, i32, i32, i32, vp, sz, vp]
         L.ppca_rayleigh_ritz_grouped.argtypes = [pp, i32, vp, sz, vp]
@@ -327,6 +329,11 @@ def kernel_stats(kernel: int):
 
 def set_chunk_rows(rows: int):
     lib().ppca_set_chunk_rows(int(rows))
+
+
+def set_fused_pass(enable: bool):
+    """Single-read power pass on (True) or off (False, the default: two kernels)."""
+    lib().ppca_set_fused_pass(1 if enable else 0)
 
 
 # --------------------------------------------------------------- grouped

@@ -26,13 +26,15 @@ namespace {
 
 // ------------------------------------------------------------------ knobs
 std::atomic<int64_t> g_chunk_rows{0};
+std::atomic<int> g_fused_enabled{0};
+constexpr int kFusedSpinLimit = 1 << 22;   // polls of one bounded wait (about 0.2 s)
 std::mutex g_tmu;
 bool g_timing = false;
 struct KStat {
   int64_t launches = 0;
   double ms = 0.0;
 };
-KStat g_stats[3];
+KStat g_stats[4];
 struct Pending {
   hipEvent_t a, b;
   int kernel;
@@ -105,6 +107,9 @@ struct Plan {
   int64_t dp = 0;
   int64_t rows_cap = 0;   // rows of the Y staging buffer
   int ntiles = 0, nsplit = 0, ngpart = 0, ksplit = 1;
+  bool fused = false;     // power passes (Z only) run the single-read kernel
+  int fnsplit = 0;
+  size_t fex = 0, fyb = 0, fflags = 0, fdummy = 0, fpart = 0;
   // offsets
   size_t ypart = 0;
   size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
@@ -130,6 +135,15 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.K = K;
   p.Kp = (int)round_up(K, 16);
   p.dp = round_up(d, 64);   // whole 64-column k-steps of the streaming kernels
+  // power and stream passes of bf16 data take the single-read pass, whose
+  // products run on 32-column blocks: K is padded to 32 for the whole plan
+  const int64_t chunk_knob = g_chunk_rows.load();
+  const int64_t zrows = op == PPCA_OP_POWER ? n : batch;
+  const bool fused = (op == PPCA_OP_POWER || op == PPCA_OP_STREAM) &&
+                     g_fused_enabled.load() != 0 && K <= PPCA_MAX_K &&
+                     fused_eligible(dtype, d, (int)round_up(K, 32)) &&
+                     !(chunk_knob > 0 && chunk_knob < zrows);
+  if (fused) p.Kp = (int)round_up(K, 32);
   Carve c;
   p.status = c.take(256);
   if (op == PPCA_OP_CENTER) {
@@ -182,6 +196,16 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.r = c.take(kk);
   p.rinv = c.take(kk);
   p.q1 = c.take((size_t)d * K * sizeof(double));
+  if (fused) {
+    const FusedSizes fz = fused_sizes(d, p.Kp);
+    p.fused = true;
+    p.fnsplit = fz.nsplit;
+    p.fex = c.take(fz.ex_bytes);
+    p.fyb = c.take(fz.yb_bytes);
+    p.fflags = c.take(fz.flag_bytes);
+    p.fdummy = c.take(fz.dummy_bytes);
+    p.fpart = c.take(fz.part_bytes);
+  }
   if (op == PPCA_OP_EIGENGAME) {
     const int64_t nblk = eigengame_blocks(d, K);
     p.egs = c.take((size_t)(2 * d * K + 2 * nblk * K) * sizeof(double));
@@ -265,6 +289,22 @@ int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t 
   pd.r0 = r0;
   pd.nrows = nrows;
   StreamBufs b = bufs_of(p, ws);
+  if (p.fused && !gram_only && G == nullptr) {
+    // Z = X^T bf16(X V') in one read of X, then the fixed-order float64 sum of
+    // the (slice, cluster) partials
+    FusedBufs fb{at<float>(ws, p.fex), at<uint16_t>(ws, p.fyb), at<int>(ws, p.fflags),
+                 at<float>(ws, p.fdummy), at<float>(ws, p.fpart)};
+    HIP_TRY(timed(3, s, [&] {
+      return launch_fused_pass(pd, b.vop, b.dp, p.Kp, fb, at<int>(ws, p.status), kFusedSpinLimit,
+                               s);
+    }));
+    StreamBufs bz = b;
+    bz.part = fb.part;
+    bz.nsplit = p.fnsplit;
+    HIP_TRY(launch_reduce_zg(bz, X->d, p.K, nullptr, Z, nullptr, nullptr, false,
+                             at<int>(ws, p.status), s));
+    return PPCA_OK;
+  }
   const int64_t chunk = (p.rows_cap < nrows) ? p.rows_cap : nrows;
   for (int64_t i0 = 0; i0 < nrows; i0 += chunk) {
     const int64_t rows = (nrows - i0) < chunk ? (nrows - i0) : chunk;
@@ -908,6 +948,8 @@ const char* ppca_strerror(int status) {
     case PPCA_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case PPCA_ERR_HIP: return "HIP runtime error";
     case PPCA_ERR_ALIGN: return "X base pointer or row stride not 16-byte aligned";
+    case PPCA_ERR_PLACEMENT: return "single-read pass: workgroups of a cluster not on one XCD";
+    case PPCA_ERR_TIMEOUT: return "single-read pass: a bounded wait between workgroups expired";
     default: return "unknown status";
   }
 }
@@ -919,7 +961,7 @@ void ppca_set_kernel_timing(int32_t enable) {
 }
 
 int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
-  if (kernel < 0 || kernel > 2) return PPCA_ERR_ARG;
+  if (kernel < 0 || kernel > 3) return PPCA_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (launches) *launches = g_stats[kernel].launches;
   if (total_ms) *total_ms = g_stats[kernel].ms;
@@ -927,5 +969,7 @@ int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
 }
 
 void ppca_set_chunk_rows(int64_t rows) { g_chunk_rows.store(rows < 0 ? 0 : rows); }
+
+void ppca_set_fused_pass(int32_t enable) { g_fused_enabled.store(enable != 0 ? 1 : 0); }
 
 }  // extern "C"

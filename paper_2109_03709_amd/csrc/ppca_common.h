@@ -90,6 +90,26 @@ hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* 
                             float* Z, double* G, double* G_copy, bool gram_only, int* status,
                             hipStream_t s);
 
+// single-read power pass (k_fused.hip): bf16 data, Kp a multiple of 32 up to
+// 128, d <= 8192; clusters of C = fused_cluster(d) workgroups on one XCD
+// (a cooperative launch of 256 workgroups, one per CU)
+struct FusedSizes {
+  int cluster, nsplit;
+  size_t ex_bytes, yb_bytes, flag_bytes, dummy_bytes, part_bytes;
+};
+struct FusedBufs {
+  float* ex;
+  uint16_t* yb;
+  int* flags;
+  float* dummy;
+  float* part;   // Z partials [C][nsplit][Kp][256]
+};
+int fused_cluster(int64_t d);
+FusedSizes fused_sizes(int64_t d, int Kp);
+bool fused_eligible(int32_t dtype, int64_t d, int Kp);
+hipError_t launch_fused_pass(const PassDesc& p, const void* vop, int64_t dp, int Kp,
+                             const FusedBufs& fb, int* status, int spin_limit, hipStream_t s);
+
 // dense float64 kernels (k_dense.hip)
 hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp,
                                int32_t dtype, const float* col_scale, void* vop,

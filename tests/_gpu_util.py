@@ -122,3 +122,62 @@ def oracle_replay(method: str, rows_of_step, v_start, steps, batch: int, eta0: f
         v = fn(rows_of_step(t), v, batch=batch, steps=1, eta0=O.learning_rate(eta0, t0, t),
                t0=0.0, orthonormalise_start=False, operand=operand)[0]
     return v
+
+
+# ------------------------------------------------------ exact-arithmetic data
+# Inputs on which every rounding of the GPU path is exact: codes in {-1, 0, 1}
+# (fp8: times a power-of-two column scale), and directions with at most two
+# nonzeros per column, each in {+-1, +-1/2}, on a small set of rows.  Then
+# V' = bf16(V) (fp8: bf16(s_j V_jc)) equals V, every Y = X V' is a multiple of
+# 1/2 of magnitude <= 1 (exact in bf16), and every float32 partial of Z and G
+# is a multiple of 1/4 below 2^21 (n <= 2^21 rows), so Z and G must equal
+# their float64 values exactly.
+E4M3_ONE, E4M3_MINUS_ONE = 0x38, 0xB8
+
+
+def exact_codes(n: int, d: int, dtype: int, seed: int, device="cuda"):
+    """(Data on the device, per-column scale or None).  Codes drawn on the
+    device (so that multi-GB cases need no host copy of X)."""
+    import paper_2109_03709_amd as P
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    ld = aligned_ld(d, dtype)              # 16-byte row stride; X is the view [:, :d]
+    c = torch.randint(-1, 2, (n, ld), generator=g, device=device, dtype=torch.int8)
+    if dtype == F32:
+        return P.Data(c.float()[:, :d], F32), None
+    if dtype == BF16:
+        return P.Data(c.to(torch.bfloat16)[:, :d], BF16), None
+    codes = torch.where(c > 0, torch.tensor(E4M3_ONE, dtype=torch.uint8, device=device),
+                        torch.where(c < 0, torch.tensor(E4M3_MINUS_ONE, dtype=torch.uint8,
+                                                        device=device),
+                                    torch.tensor(0, dtype=torch.uint8, device=device)))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    scale = np.ldexp(1.0, rng.integers(-3, 1, d)).astype(np.float32)
+    return P.Data(codes[:, :d], FP8, torch.from_numpy(scale).to(device)), scale
+
+
+def exact_directions(d: int, K: int, seed: int, rows_used: int = 48) -> np.ndarray:
+    """d x K float32 with at most two nonzeros per column, in {+-1, +-1/2},
+    on a set of at most rows_used rows."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows = rng.choice(d, size=min(rows_used, d), replace=False)
+    v = np.zeros((d, K), np.float32)
+    vals = np.array([1.0, -1.0, 0.5, -0.5], np.float32)
+    for c in range(K):
+        nz = rng.choice(rows, size=min(2, len(rows)), replace=False)
+        v[nz, c] = rng.choice(vals, size=len(nz))
+        if not np.any(v[:, c]):
+            v[nz[0], c] = 1.0
+    return v
+
+
+def host_columns(data, cols: np.ndarray, scale, chunk: int = 1 << 18) -> np.ndarray:
+    """float64 values of the stored matrix at the given columns (all rows)."""
+    out = np.empty((data.n, len(cols)), np.float64)
+    idx = torch.from_numpy(np.asarray(cols, np.int64)).to(data.x.device)
+    for r0 in range(0, data.n, chunk):
+        r1 = min(data.n, r0 + chunk)
+        sub = data.x[r0:r1].index_select(1, idx)
+        out[r0:r1] = stored_values(host(sub.contiguous()), data.dtype,
+                                   None if scale is None else scale[cols])
+    return out
