@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_make_operand(const float* __restrict__ 
                                                       int Kp, int64_t dp, int dtype,
                                                       const float* __restrict__ scale,
                                                       void* __restrict__ vop,
-                                                      double* __restrict__ veff) {
+                                                      double* __restrict__ veff, int split) {
   const int64_t total = (int64_t)Kp * dp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -41,6 +41,12 @@ __global__ __launch_bounds__(256) void k_make_operand(const float* __restrict__ 
       const uint32_t h = f32_to_bf16_bits(sv);
       reinterpret_cast<uint16_t*>(vop)[e] = (uint16_t)h;
       ve = (double)bf16_bits_to_f32(h);
+      if (split) {
+        // sv - hi has at most 16 significant bits: exact in float32
+        const uint32_t lo = f32_to_bf16_bits(sv - bf16_bits_to_f32(h));
+        reinterpret_cast<uint16_t*>(vop)[total + e] = (uint16_t)lo;
+        ve += (double)bf16_bits_to_f32(lo);
+      }
       if (dtype == PPCA_FP8_E4M3 && in) ve = ve / (double)scale[j];
     }
     if (j < d) veff[j * Kp + c] = ve;
@@ -300,9 +306,10 @@ inline int64_t grid_for(int64_t n, int64_t cap = 4096) {
 }  // namespace
 
 hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp, int32_t dtype,
-                               const float* col_scale, void* vop, double* veff, hipStream_t s) {
+                               const float* col_scale, void* vop, double* veff, bool split,
+                               hipStream_t s) {
   hipLaunchKernelGGL(k_make_operand, dim3(grid_for((int64_t)Kp * dp)), dim3(256), 0, s, V, d, K,
-                     Kp, dp, (int)dtype, col_scale, vop, veff);
+                     Kp, dp, (int)dtype, col_scale, vop, veff, split ? 1 : 0);
   return hipGetLastError();
 }
 

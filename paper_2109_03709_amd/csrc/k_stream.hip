@@ -1082,6 +1082,237 @@ __global__ __launch_bounds__(256, 1) void k_xvy(const uint8_t* x, int64_t n, int
   wait_vmcnt<0>();
 }
 
+// ---------------------------------------------------------------------------
+// Projection pass with a two-term operand (Alg. 1 steps 2-3; bf16 data, Kp a
+// multiple of 32): V' = hi + lo with hi = bf16(V), lo = bf16(V - hi), so that
+// the projected span is that of V to about 2^-16 instead of 2^-9.
+// Y = X hi + X lo accumulates both products in one float32 accumulator
+// (v_mfma_f32_32x32x16_bf16), is rounded to bf16, and G += Y^T Y is formed
+// from the accumulators themselves: elements 0..7 and 8..15 of a lane's 32x32
+// result block are rows {8 (e / 4) + 4 hl + e % 4} of one column, and serve
+// as that lane's eight k-slots of two 32x32x16 products (the same rows for
+// the A and the B operand), so Y never leaves the registers.
+// Work split: persistent workgroups over 128-row tiles (each wave 32 rows),
+// one DMA pipeline over all (tile, k-step) pairs as in k_xvy, three LDS
+// stages of X (16 KB) + hi + lo (Kp x 128 bytes each).  The waves' G blocks
+// are summed in LDS in wave order; one float32 partial per workgroup.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256, 1) void k_xvg(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
+                                                int64_t rstart, int64_t rows, const uint8_t* vop,
+                                                int64_t dp, float* gpart, int accumulate) {
+  static_assert(NB % 2 == 0, "Kp a multiple of 32");
+  constexpr int Kp = NB * 16, N2 = NB / 2;
+  constexpr int EB = 2, KS = 64, WGR = 128;
+  constexpr int XSB = WGR * 128, VSB = Kp * 128, STB = XSB + 2 * VSB;
+  constexpr int XI = WGR / 32, VBLK = Kp / 8, VI = (VBLK + 3) / 4, DPS = XI + 2 * VI;
+  constexpr int NG = N2 * (N2 + 1) / 2;            // upper 32 x 32 blocks of G
+  static_assert(2 * DPS < 64, "vmcnt range");
+  static_assert(3 * STB <= 160 * 1024 && Kp * Kp * 4 <= 3 * STB, "LDS");
+  __shared__ __attribute__((aligned(16))) uint8_t st[3 * STB];
+
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int l32 = lane & 31, hl = lane >> 5;
+  const int64_t ntile = (rows + WGR - 1) / WGR;
+  const int64_t mytiles = ntile > blockIdx.x ? (ntile - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int nk = (int)((d + KS - 1) / KS);
+  const int64_t nsteps = mytiles * nk;
+  const int64_t klast = (int64_t)(nk - 1) * KS;
+  const int64_t dtail = d % (16 / EB);
+
+  // DMA sources, as in k_xvy
+  const int p8 = lane & 7;
+  int xc[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = 8 * (w * XI + j) + (lane >> 3);
+    xc[j] = (p8 ^ (r & 7)) * (16 / EB);
+  }
+  const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
+  int64_t xrow[XI];
+  const uint8_t* xsrc[XI];
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int r = 8 * (w * XI + j) + (lane >> 3);
+    xrow[j] = (rstart + (int64_t)blockIdx.x * WGR + r) % n;
+    xsrc[j] = x + xrow[j] * ld * EB;
+  }
+  const int64_t lo_off = (int64_t)Kp * dp * EB;     // lo follows hi
+  const uint8_t* vsrc[VI];
+  int vblk[VI];
+#pragma unroll
+  for (int j = 0; j < VI; ++j) {
+    const int blk = (w * VI + j) % VBLK;
+    const int r = 8 * blk + (lane >> 3);
+    vblk[j] = blk;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+  }
+  auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* { return st + b * STB; };
+  int64_t iss = 0;
+  int ik = 0;
+  auto issue = [&](int b) __attribute__((always_inline)) {
+    uint8_t* sb = stage(b);
+    const int64_t k0 = iss < nsteps ? (int64_t)ik * KS : klast;
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int64_t col = k0 + xc[j];
+      dma16(xsrc[j] + (col < d ? col : 0) * EB, sb + (w * XI + j) * 1024);
+    }
+#pragma unroll
+    for (int j = 0; j < VI; ++j) {
+      dma16(vsrc[j] + k0 * EB, sb + XSB + vblk[j] * 1024);
+      dma16(vsrc[j] + lo_off + k0 * EB, sb + XSB + VSB + vblk[j] * 1024);
+    }
+    if (iss < nsteps) {
+      ++iss;
+      if (++ik == nk) {
+        if (iss < nsteps) {
+          ik = 0;
+#pragma unroll
+          for (int j = 0; j < XI; ++j) {
+            const int64_t nr = xrow[j] + tstep;
+            xrow[j] = nr >= n ? nr - n : nr;
+            xsrc[j] = x + xrow[j] * ld * EB;
+          }
+        } else {
+          ik = nk - 1;
+        }
+      }
+    }
+  };
+  auto fix_tail = [&](int b) __attribute__((always_inline)) {
+    uint8_t* sb = stage(b);
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      uint4* slot = reinterpret_cast<uint4*>(sb + (w * XI + j) * 1024 + lane * 16);
+      *slot = and4(*slot, chunk_mask<EB>(klast + xc[j], d));
+    }
+  };
+
+  f32x16_t acc[N2], gacc[NG];
+#pragma unroll
+  for (int nb = 0; nb < N2; ++nb) acc[nb] = f32x16_t{};
+#pragma unroll
+  for (int i = 0; i < NG; ++i) gacc[i] = f32x16_t{};
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    const uint8_t* xs = stage(b);
+    const uint8_t* vh = xs + XSB;
+    const uint8_t* vl = vh + VSB;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int c = 2 * s4 + hl;
+      const int r = w * 32 + l32;
+      const uint4 af = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+      uint4 bh[N2], bl[N2];
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb) {
+        const int rv = nb * 32 + l32;
+        bh[nb] = *reinterpret_cast<const uint4*>(vh + rv * 128 + ((c ^ (rv & 7)) * 16));
+        bl[nb] = *reinterpret_cast<const uint4*>(vl + rv * 128 + ((c ^ (rv & 7)) * 16));
+      }
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(af), as_bf16x8(bh[nb]), acc[nb],
+                                                          0, 0, 0);
+#pragma unroll
+      for (int nb = 0; nb < N2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(af), as_bf16x8(bl[nb]), acc[nb],
+                                                          0, 0, 0);
+    }
+  };
+  // G += Y^T Y of tile ordinal ct from the accumulators; rows past the pass are zero
+  const uint32_t keep = dp > 0 ? 0xFFFFFFFFu : 0u;   // all ones, opaque to the compiler
+  auto gram_tile = [&](int64_t ct) __attribute__((always_inline)) {
+    const int64_t row0 = ((int64_t)blockIdx.x + ct * gridDim.x) * WGR;
+    const int64_t vrows = rows - row0;
+    uint4 yb[N2][2];
+#pragma unroll
+    for (int nb = 0; nb < N2; ++nb)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t wv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e0 = 8 * h + 2 * q, e1 = e0 + 1;
+          const int r0 = w * 32 + 8 * (e0 / 4) + 4 * hl + e0 % 4;
+          const int r1 = w * 32 + 8 * (e1 / 4) + 4 * hl + e1 % 4;
+          const float v0 = r0 < vrows ? acc[nb][e0] : 0.f;
+          const float v1 = r1 < vrows ? acc[nb][e1] : 0.f;
+          wv[q] = f32_to_bf16_bits(v0) | (f32_to_bf16_bits(v1) << 16);
+        }
+        yb[nb][h] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+      }
+    int idx = 0;
+#pragma unroll
+    for (int na = 0; na < N2; ++na)
+#pragma unroll
+      for (int nb = na; nb < N2; ++nb) {
+        gacc[idx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(yb[na][0]),
+                                                            as_bf16x8(yb[nb][0]), gacc[idx], 0, 0, 0);
+        gacc[idx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(yb[na][1]),
+                                                            as_bf16x8(yb[nb][1]), gacc[idx], 0, 0, 0);
+        ++idx;
+      }
+    // cleared with a zero the compiler cannot see through (see k_xvd)
+    const float zero = __uint_as_float(~keep);
+#pragma unroll
+    for (int nb = 0; nb < N2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[nb][i] = zero;
+  };
+
+  if (nsteps > 0) {
+    issue(0);
+    issue(1);
+    int b = 0;
+    for (int64_t ct = 0; ct < mytiles; ++ct) {
+      for (int kk = 0; kk < nk; ++kk) {
+        wait_vmcnt<DPS>();
+        if (dtail != 0 && kk == nk - 1) {
+          fix_tail(b);
+          wait_lgkm0();
+        }
+        raw_barrier();
+        issue(b == 0 ? 2 : b - 1);
+        compute(b);
+        b = b == 2 ? 0 : b + 1;
+      }
+      gram_tile(ct);
+    }
+  }
+  wait_vmcnt<0>();
+  raw_barrier();
+  // sum the waves' G blocks in LDS, wave 0 first; element e of block (na, nb)
+  // of lane (l32, hl) is G[32 na + 8 (e / 4) + 4 hl + e % 4][32 nb + l32]
+  float* gl = reinterpret_cast<float*>(st);
+#pragma unroll
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      int idx = 0;
+#pragma unroll
+      for (int na = 0; na < N2; ++na)
+#pragma unroll
+        for (int nb = na; nb < N2; ++nb) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int i = 32 * na + 8 * (e / 4) + 4 * hl + e % 4, c = 32 * nb + l32;
+            gl[i * Kp + c] = (ww == 0 ? 0.f : gl[i * Kp + c]) + gacc[idx][e];
+          }
+          ++idx;
+        }
+    }
+    __syncthreads();
+  }
+  // the reduction reads the entries i <= c of every partial; chunked passes
+  // add their chunks in order
+  float* gp = gpart + (int64_t)blockIdx.x * Kp * Kp;
+  for (int e = t; e < Kp * Kp; e += 256) {
+    const int i = e / Kp, c = e % Kp;
+    const float v = (i / 32 <= c / 32) ? gl[e] : 0.f;
+    gp[e] = accumulate ? gp[e] + v : v;
+  }
+}
+
 // Block id -> (tile, split).  Block b runs on XCD b mod 8; XCD x takes the
 // contiguous run of (split, tile) pairs [x*per, (x+1)*per) in split-major
 // order, so the tiles of one row split (which all read the same rows of Y)
@@ -1451,6 +1682,11 @@ int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   return (int)cdiv(nk, kper);
 }
 
+int xvg_grid(int64_t rows_cap) {
+  const int64_t tiles = cdiv(rows_cap, 128);
+  return (int)(tiles < kNumCU ? tiles : kNumCU);
+}
+
 int xv_grid(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   // split short passes: one G partial per k_ysum workgroup (16 rows)
   if (xv_ksplit(dtype, Kp, d, rows_cap) > 1) return (int)cdiv(rows_cap, kYsumRows);
@@ -1489,6 +1725,16 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
                          yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
                          accumulate ? 1 : 0);
     };
+    // projection of bf16 data with the two-term operand
+    if constexpr (NB % 2 == 0) {
+      if (b.split && p.dtype == PPCA_BF16 && want_g && !want_y) {
+        hipLaunchKernelGGL(k_xvg<NB>, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
+                           p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, b.gpart,
+                           accumulate ? 1 : 0);
+        return hipGetLastError();
+      }
+    }
+    if (b.split) return hipErrorInvalidValue;
     // bf16 / f32 data: LDS-DMA kernel; fp8 data: register-staged kernel
     auto by_mw = [&](auto dtc, auto yc, auto gc) {
       constexpr int DT = decltype(dtc)::value;

@@ -108,6 +108,7 @@ struct Plan {
   int64_t rows_cap = 0;   // rows of the Y staging buffer
   int ntiles = 0, nsplit = 0, ngpart = 0, ksplit = 1;
   bool fused = false;     // power passes (Z only) run the single-read kernel
+  bool split = false;     // projection and Rayleigh-Ritz: two-term bf16 operand hi + lo
   int fnsplit = 0;
   size_t fex = 0, fyb = 0, fflags = 0, fdummy = 0, fpart = 0;
   // offsets
@@ -144,6 +145,10 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
                      fused_eligible(dtype, d, (int)round_up(K, 32)) &&
                      !(chunk_knob > 0 && chunk_knob < zrows);
   if (fused) p.Kp = (int)round_up(K, 32);
+  // the projection of bf16 data and the Rayleigh-Ritz step that follows it
+  // use the two-term operand (its products run on 32-column blocks)
+  p.split = (op == PPCA_OP_PROJECT || op == PPCA_OP_RR) && dtype == PPCA_BF16;
+  if (p.split) p.Kp = (int)round_up(K, 32);
   Carve c;
   p.status = c.take(256);
   if (op == PPCA_OP_CENTER) {
@@ -155,7 +160,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     return p;
   }
   const int es_op = dtype == PPCA_F32 ? 4 : 2;
-  p.vop = c.take((size_t)p.Kp * p.dp * es_op);
+  p.vop = c.take((size_t)p.Kp * p.dp * es_op * (p.split ? 2 : 1));
   p.veff = c.take((size_t)d * p.Kp * sizeof(double));
   const size_t kk = (size_t)K * K * sizeof(double);
   if (op == PPCA_OP_RR) {
@@ -183,9 +188,9 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.part = c.take(op == PPCA_OP_PROJECT
                       ? 16
                       : (size_t)p.ntiles * p.nsplit * p.Kp * xty_cols(p.Kp) * sizeof(float));
-  p.ngpart = xv_grid(dtype, p.Kp, d, p.rows_cap);
+  p.ngpart = p.split ? xvg_grid(p.rows_cap) : xv_grid(dtype, p.Kp, d, p.rows_cap);
   p.gpart = c.take((size_t)p.ngpart * p.Kp * p.Kp * sizeof(float));
-  p.ksplit = xv_ksplit(dtype, p.Kp, d, p.rows_cap);
+  p.ksplit = p.split ? 1 : xv_ksplit(dtype, p.Kp, d, p.rows_cap);
   p.ypart = c.take(p.ksplit > 1 ? (size_t)p.ksplit * round_up(p.rows_cap, 64) * p.Kp * sizeof(float)
                                 : 16);
   p.z = c.take((size_t)d * K * sizeof(float));
@@ -272,6 +277,7 @@ StreamBufs bufs_of(const Plan& p, void* ws) {
   b.Kp = p.Kp;
   b.ksplit = p.ksplit;
   b.ypart = at<float>(ws, p.ypart);
+  b.split = p.split;
   return b;
 }
 
@@ -338,7 +344,7 @@ int cholqr2(const float* A, float* V, int64_t d, int K, const Plan& p, void* ws,
 
 int make_operand(const ppca_matrix* X, const float* V, const Plan& p, void* ws, hipStream_t s) {
   HIP_TRY(launch_make_operand(V, X->d, p.K, p.Kp, p.dp, X->dtype, X->col_scale,
-                              at<void>(ws, p.vop), at<double>(ws, p.veff), s));
+                              at<void>(ws, p.vop), at<double>(ws, p.veff), p.split, s));
   return PPCA_OK;
 }
 

@@ -73,6 +73,7 @@ struct StreamBufs {
   int Kp;               // K padded to 16
   int ksplit;           // column splits of a short pass (1 = none)
   float* ypart;         // float32 Y partials [ksplit][rows_cap rounded to 64][Kp]
+  bool split = false;   // two-term operand: vop holds hi [Kp][dp] then lo [Kp][dp]
 };
 
 // stream kernels (k_stream.hip)
@@ -82,6 +83,7 @@ int xty_blocks_per_cu(int Kp);     // resident workgroups per CU of the X^T Y ke
 constexpr int kNumCU = 256;        // compute units of an MI355X
 int xty_tiles(int64_t d, int Kp);  // column tiles of X in the X^T Y kernel
 int xv_grid(int32_t dtype, int Kp, int64_t d, int64_t rows_cap);   // workgroups of k_xv
+int xvg_grid(int64_t rows_cap);    // workgroups of the two-term projection pass
 hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
                      bool want_y, bool want_g, bool accumulate, hipStream_t s);
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
@@ -111,9 +113,11 @@ hipError_t launch_fused_pass(const PassDesc& p, const void* vop, int64_t dp, int
                              const FusedBufs& fb, int* status, int spin_limit, hipStream_t s);
 
 // dense float64 kernels (k_dense.hip)
+// split: bf16 operand as hi = bf16(V) at vop and lo = bf16(V - hi) at
+// vop + Kp dp, V_eff = hi + lo (bf16 data only)
 hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp,
                                int32_t dtype, const float* col_scale, void* vop,
-                               double* veff, hipStream_t s);
+                               double* veff, bool split, hipStream_t s);
 // partial Grams of a (rows x K) matrix A (row stride lda); in_f64 selects the type
 int gram_parts(int64_t rows, int K);
 hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,

@@ -34,6 +34,18 @@ def operand_basis(v32: np.ndarray, dtype: int, scale: np.ndarray | None) -> np.n
     return O.bf16_value(O.bf16_round(sv)) / scale.astype(np.float64)[:, None]
 
 
+def projection_basis(v32: np.ndarray, dtype: int, scale: np.ndarray | None) -> np.ndarray:
+    """V_eff of the projection pass and of Rayleigh-Ritz: for bf16 data the
+    two-term operand hi + lo, hi = bf16(V), lo = bf16(V - hi) (V - hi is exact
+    in float32); for f32 and fp8 data the single operand of operand_basis."""
+    if dtype != BF16:
+        return operand_basis(v32, dtype, scale)
+    v32 = np.asarray(v32, np.float32)
+    hi = O.bf16_value(O.bf16_round(v32))
+    rest = (v32.astype(np.float64) - hi).astype(np.float32)
+    return hi + O.bf16_value(O.bf16_round(rest))
+
+
 def host(t: torch.Tensor) -> np.ndarray:
     if t.dtype == torch.bfloat16:
         return t.view(torch.int16).cpu().numpy().view(np.uint16)

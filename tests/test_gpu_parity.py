@@ -19,7 +19,8 @@ from oracle import ppca_oracle as O
 from synthdata import gaussian_block, make_problem
 
 from ._gpu_util import (BF16, F32, FP8, TRAJ_REL, col_cos, device_data, gram_err, host,
-                        operand_basis, oracle_replay, sin_theta, trajectory_error)
+                        operand_basis, oracle_replay, projection_basis, sin_theta,
+                        trajectory_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +76,7 @@ def test_project_gram(dtype, n, d, K, pad):
     v = gaussian_block(d, K, 7, np.float32)
     G, B = P().project_gram(data, K, torch.from_numpy(v).cuda())
     torch.cuda.synchronize()
-    veff = operand_basis(v, dtype, scale)
+    veff = projection_basis(v, dtype, scale)
     g_ref, b_ref = O.project_gram(xs, veff)
     tol = 2e-5 if dtype == F32 else 4e-3
     assert gram_err(G.cpu().numpy(), g_ref) < tol
@@ -295,10 +296,13 @@ def test_low_precision_ppca_scaled(dtype, spec, k, iters):
     count.  Parity: after Rayleigh-Ritz the GPU result matches the oracle's
     own run on the same stored data within 2e-3 (eigenvalue relative error
     and largest principal-angle sine).  Against the exact spectrum of the
-    float32 data the eigenvalues stay within 2e-3; the subspace of the stored
-    data itself differs from the exact one by quantisation noise whose effect
-    shrinks like 1/sqrt(n) (about 2e-3 for bf16 and 4e-3 for fp8 at this n,
-    ten to twenty times less at the full row counts), hence the 1e-2 bound."""
+    float32 data the eigenvalues stay within 2e-3.  The bf16 subspace is held
+    to 2e-3 as well: the projection multiplies by the two-term operand
+    hi + lo, whose span is that of V to about 2^-16 (a single bf16 operand
+    alone puts a floor of about 2e-3 under the largest principal-angle sine,
+    whatever n).  fp8 storage (3 mantissa bits, per-column scales) moves the
+    stored data's own eigenvectors by about 4e-3 at this n, and its projection
+    uses the single operand: 1e-2 there."""
     n, d, l = 20011, 2048, k
     p = make_problem(n, d, spec, seed=1003, mode="exact")
     data, xs, scale = device_data(p.x, dtype)
@@ -309,7 +313,9 @@ def test_low_precision_ppca_scaled(dtype, spec, k, iters):
     assert np.max(O.rel_eig_error(ev, th)) < 2e-3
     assert sin_theta(E, e_or) < 2e-3
     assert np.max(O.rel_eig_error(ev, p.lam[:k])) < 2e-3
-    assert sin_theta(E, p.q[:, :k]) < 1e-2
+    s_exact = sin_theta(E, p.q[:, :k])
+    print(f"sin theta vs exact subspace: {s_exact:.3e}")
+    assert s_exact < (2e-3 if dtype == BF16 else 1e-2)
 
 
 # ----------------------------------------------------- minibatch primings

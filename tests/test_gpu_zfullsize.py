@@ -8,11 +8,10 @@ brought to the host in row chunks:
 * four whole columns of Z = X^T (X V') from the power step's kernels, against
   the same elementwise bound as the smaller stream-pass cases;
 * the 4 x 4 block of G = (X V')^T (X V') of those columns from the projection
-  pass, and the operand Gram B = V'^T V' in full;
+  pass (two-term operand V' = hi + lo), and B = V'^T V' in full;
 * the end-to-end result (priming, projection, Rayleigh-Ritz) against the
-  exact spectrum of the data: eigenvalue relative error 2e-3, orthonormal
-  Ritz vectors, and the subspace within the 1e-2 quantisation bound of the
-  scaled bf16 case.
+  exact spectrum of the data: eigenvalue relative error and largest
+  principal-angle sine within 2e-3, orthonormal Ritz vectors.
 The minibatch workloads (Oja on f32 data, EigenGame on fp8 data) are checked
 at their full sizes on the steps whose rows wrap past the end of the data, and
 the 512-problem grouped workload on one step of sampled problems and on every
@@ -26,7 +25,7 @@ from oracle import ppca_oracle as O
 from synthdata import gaussian_block, make_problem_device
 
 from ._gpu_util import (BF16, F32, FP8, TRAJ_REL, gram_err, operand_basis, oracle_replay,
-                        sin_theta, stored_values, trajectory_error)
+                        projection_basis, sin_theta, stored_values, trajectory_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +66,10 @@ def test_full_size_stream_and_projection_sampled(workload):
     gs = G.cpu().numpy()[np.ix_(COLS, COLS)]
     bh = B.cpu().numpy()
 
-    veff = operand_basis(v, BF16, None)              # bf16(V), float64
+    veff = operand_basis(v, BF16, None)              # bf16(V), float64: power step
+    vpro = projection_basis(v, BF16, None)           # hi + lo: projection
     vc = torch.from_numpy(np.ascontiguousarray(veff[:, COLS]))
+    vp = torch.from_numpy(np.ascontiguousarray(vpro[:, COLS]))
     z_ref = torch.zeros((D, len(COLS)), dtype=torch.float64)
     z_bnd = torch.zeros((D, len(COLS)), dtype=torch.float64)
     g_ref = torch.zeros((len(COLS), len(COLS)), dtype=torch.float64)
@@ -78,13 +79,14 @@ def test_full_size_stream_and_projection_sampled(workload):
         y = xc @ vc
         z_ref += xc.T @ y
         z_bnd += xc.abs().T @ y.abs()
-        g_ref += y.T @ y
+        yp = xc @ vp
+        g_ref += yp.T @ yp
     z_ref, z_bnd, g_ref = z_ref.numpy(), z_bnd.numpy(), g_ref.numpy()
 
     # Y' = bf16(Y) feeds Z: each term is off by at most 2^-8 of |x||y|
     assert np.all(np.abs(zs - z_ref) <= 2.0 ** -8 * z_bnd + 1e-30)
     assert gram_err(gs, g_ref) < 4e-3
-    assert gram_err(bh, veff.T @ veff) < 1e-12
+    assert gram_err(bh, vpro.T @ vpro) < 1e-12
 
 
 @pytest.mark.timeout(600)
@@ -102,7 +104,9 @@ def test_full_size_ppca_against_exact_spectrum(workload):
     assert np.all(np.diff(evh) <= 0)
     assert np.max(O.rel_eig_error(evh, lam[:KK])) < 2e-3
     assert np.max(np.abs(Eh.T @ Eh - np.eye(KK))) < 1e-5
-    assert sin_theta(Eh, q[:, :KK]) < 1e-2
+    s_exact = sin_theta(Eh, q[:, :KK])
+    print(f"[fullsize] sin theta vs exact subspace: {s_exact:.3e}", flush=True)
+    assert s_exact < 2e-3
 
 
 # ------------------------------------------------ minibatch primings, full size
