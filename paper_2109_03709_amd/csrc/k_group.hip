@@ -132,6 +132,17 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
     for (int nb = 0; nb < NB2; ++nb)
       vf[s][nb] = *reinterpret_cast<const uint4*>(P.vop + (int64_t)(32 * nb + l32) * C::DC + c0 +
                                                   16 * s + 8 * hl);
+  // projection pass: the second term lo of the two-term operand, same layout
+  constexpr int NLO = WZ ? 1 : C::DW / 16;
+  uint4 vl[NLO][NB2];
+  if constexpr (!WZ) {
+#pragma unroll
+    for (int s = 0; s < C::DW / 16; ++s)
+#pragma unroll
+      for (int nb = 0; nb < NB2; ++nb)
+        vl[s][nb] = *reinterpret_cast<const uint4*>(P.vlo + (int64_t)(32 * nb + l32) * C::DC +
+                                                    c0 + 16 * s + 8 * hl);
+  }
 
   // DMA lanes: slot q = 64 j + lane of a stage is (row q / CPR, slot q % CPR)
   // and holds the slice's 16-byte column chunk slot ^ (row & 7); chunks past d
@@ -215,6 +226,12 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
         for (int nb = 0; nb < NB2; ++nb)
           ya[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
                                                            ya[nb], 0, 0, 0);
+        if constexpr (!WZ) {
+#pragma unroll
+          for (int nb = 0; nb < NB2; ++nb)
+            ya[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(vl[s][nb]),
+                                                             ya[nb], 0, 0, 0);
+        }
       }
     }
     // Y' = bf16(Y), rows past the item zeroed: yb[nb][m] holds this lane's
@@ -598,15 +615,28 @@ __device__ inline void trmm_wg(Load load, int64_t rows, int K, const double* Rin
   __syncthreads();
 }
 
-// operand vop[c][j] = bf16(V[j][c]) of one problem (zero for j >= d or
-// c >= K, up to Kp x dc), by one workgroup of 256 threads
+// two-term operand of one problem: vop[c][j] = hi = bf16(V[j][c]) and
+// vlo[c][j] = lo = bf16(V[j][c] - hi) (V - hi is exact in float32; zero for
+// j >= d or c >= K, up to Kp x dc), by one workgroup of 256 threads.  The
+// power passes multiply by hi, the projection pass by hi + lo.
 __device__ inline void write_operand(const GProb& P, const float* V) {
   const int64_t d = P.d;
   const int K = P.K, Kp = P.Kp, dc = P.dc;
   for (int e = threadIdx.x; e < Kp * dc; e += 256) {
     const int c = e / dc, j = e - c * dc;
-    P.vop[e] = (j < d && c < K) ? (uint16_t)f32_to_bf16_bits(V[(int64_t)j * K + c]) : 0;
+    const bool in = j < d && c < K;
+    const float v = in ? V[(int64_t)j * K + c] : 0.f;
+    const uint32_t hi = f32_to_bf16_bits(v);
+    P.vop[e] = (uint16_t)hi;
+    P.vlo[e] = (uint16_t)f32_to_bf16_bits(v - bf16_bits_to_f32(hi));
   }
+}
+
+// V_eff entry of the projection pass: hi + lo of V[j][c], exact in float64
+__device__ inline double veff_two_term(float v) {
+  const uint32_t hi = f32_to_bf16_bits(v);
+  const float h = bf16_bits_to_f32(hi);
+  return (double)h + (double)bf16_bits_to_f32(f32_to_bf16_bits(v - h));
 }
 
 // the operand of problem blockIdx.x from its V as it stands
@@ -616,8 +646,8 @@ __global__ __launch_bounds__(256) void k_goperand(const GProb* __restrict__ prob
 }
 
 // CholeskyQR2 of Z (or of V when from_v) for problem blockIdx.x: V = Q, the
-// operand vop[c][j] = bf16(V[j][c]) (zero for j >= d or c >= K, up to Kp x dc)
-// and, with want_b, B = V'^T V' of the bf16 values.
+// two-term operand of V (write_operand) and, with want_b (before the
+// projection pass), B = V_eff^T V_eff with V_eff = hi + lo.
 //
 // The staging area and the R^-1 copy of the block products share one LDS
 // array with the Cholesky (the phases are separated by barriers): 66 KB per
@@ -651,9 +681,7 @@ __global__ __launch_bounds__(256) void k_gcholqr2(const GProb* __restrict__ prob
   // operand (V was written by this workgroup before the barrier above)
   write_operand(P, V);
   if (want_b)
-    gram_wg([&](int64_t r, int c) {
-      return (double)bf16_bits_to_f32(f32_to_bf16_bits(V[r * K + c]));
-    }, d, K, P.B, stg);
+    gram_wg([&](int64_t r, int c) { return veff_two_term(V[r * K + c]); }, d, K, P.B, stg);
 }
 
 // Rayleigh-Ritz, part 1: R = chol(B), T = G R^-1, H = (R^-T T) / n.
@@ -698,7 +726,7 @@ __global__ __launch_bounds__(1024) void k_grr_jacobi(const GProb* __restrict__ p
   dev::jacobi_dev<kGroupMaxK, kGroupMaxK>(P.H, P.K, P.W, P.ev, max_sweeps, status, 0);
 }
 
-// Rayleigh-Ritz, part 3: M = R^-1 W[:, :k], E = V_eff M (V_eff = bf16(V)),
+// Rayleigh-Ritz, part 3: M = R^-1 W[:, :k], E = V_eff M (V_eff = hi + lo of V),
 // column signs (largest |.| positive, lowest row on ties), evals = theta[:k].
 __global__ __launch_bounds__(256) void k_grr_e(const GProb* __restrict__ probs,
                                                const int* __restrict__ order, int* status) {
@@ -724,8 +752,7 @@ __global__ __launch_bounds__(256) void k_grr_e(const GProb* __restrict__ probs,
     const int64_t j = e / k;
     const int c = (int)(e - j * k);
     double s = 0.0;
-    for (int p = 0; p < K; ++p)
-      s = fma((double)bf16_bits_to_f32(f32_to_bf16_bits(V[j * K + p])), Ml[p * k + c], s);
+    for (int p = 0; p < K; ++p) s = fma(veff_two_term(V[j * K + p]), Ml[p * k + c], s);
     E[e] = (float)s;
   }
   __syncthreads();

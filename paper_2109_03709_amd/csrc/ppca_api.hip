@@ -507,7 +507,7 @@ int make_group_plan(const ppca_problem* pr, int nprob, GroupPlan& gp,
     gp.bz[p + 1] = gp.bz[p] + (int)cdiv(d * K, 256);
     gp.bg[p + 1] = gp.bg[p] + (int)cdiv((int64_t)K * K, 256);
     const size_t kk = (size_t)K * K * sizeof(double);
-    gp.pv[p] = c.take((size_t)Kp * dc * sizeof(uint16_t));
+    gp.pv[p] = c.take((size_t)2 * Kp * dc * sizeof(uint16_t));   // hi, then lo
     gp.pz[p] = c.take((size_t)d * K * sizeof(float));
     gp.pq[p] = c.take((size_t)d * K * sizeof(double));
     gp.pk[p] = c.take(5 * kk + (size_t)K * sizeof(double));
@@ -560,6 +560,7 @@ void bind_group_plan(GroupPlan& gp, const ppca_problem* pr, void* ws) {
     P.E = q.E;
     P.evals = q.evals;
     P.vop = at<uint16_t>(ws, gp.pv[p]);
+    P.vlo = P.vop + (size_t)P.Kp * P.dc;
     P.Z = at<float>(ws, gp.pz[p]);
     P.q1 = at<double>(ws, gp.pq[p]);
     double* kb = at<double>(ws, gp.pk[p]);

@@ -184,7 +184,8 @@ struct GProb {
   double* B;                // [K][K] (caller)
   float* E;                 // [d][k] (caller, may be null)
   double* evals;            // [k] (caller)
-  uint16_t* vop;            // [Kp][dc] bf16 operand (workspace)
+  uint16_t* vop;            // [Kp][dc] bf16 operand hi = bf16(V) (workspace)
+  uint16_t* vlo;            // [Kp][dc] bf16 second term lo = bf16(V - hi) (workspace)
   float* Z;                 // [d][K] (workspace)
   double* q1;               // [d][K] (workspace)
   double *A, *R, *Rinv, *H, *W, *ev;   // [K][K], ev [K] (workspace)

@@ -238,10 +238,14 @@ def test_full_size_grouped_against_exact_spectra(grouped_workload):
     P.prime_power_grouped(probs, c["iters"])
     P.rayleigh_ritz_grouped(probs)
     torch.cuda.synchronize()
+    worst = 0.0
     for i, (p, (lam_k, q_k)) in enumerate(zip(probs, refs)):
         ev = p.evals.cpu().numpy()
         E = p.E.cpu().numpy().astype(np.float64)
         k = lam_k.size
         assert np.max(O.rel_eig_error(ev, lam_k)) < 2e-3, f"problem {i}"
         assert np.max(np.abs(E.T @ E - np.eye(k))) < 1e-5, f"problem {i}"
-        assert sin_theta(E, q_k) < 1e-2, f"problem {i}"
+        s_i = sin_theta(E, q_k)
+        worst = max(worst, s_i)
+        assert s_i < 1e-2, f"problem {i}"
+    print(f"[grouped] largest sin theta vs exact subspace over 512 problems: {worst:.2e}", flush=True)
