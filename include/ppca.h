@@ -83,6 +83,7 @@ extern "C" {
 #define PPCA_OP_PROJECT     4
 #define PPCA_OP_RR          5
 #define PPCA_OP_STREAM      6
+#define PPCA_OP_POWER_SEQ   7   /* ppca_prime_power_seq */
 
 /* Largest K = k + l supported by the kernels. */
 #define PPCA_MAX_K 128
@@ -146,6 +147,33 @@ int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters,
                      float* V, double* gram_hist, double* b_hist,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* Block power priming with the termination rule of Sec. 2.1 (the power
+ * method stops when |x_i - x_{i+1}| < eps), read for a block as: stop after
+ * the first iteration t at which every column moved by less than eps,
+ * max_j |v_j^t - v_j^{t-1}|_2 < eps (CholeskyQR2 keeps each column's sign, so
+ * the change is meaningful column by column).  Otherwise as
+ * ppca_prime_power with at most max_iters iterations.  iters_done: host int
+ * (the number of iterations run); changes: host double [max_iters] or NULL
+ * (the change of each iteration run).  The host reads the change after every
+ * iteration (one synchronisation per pass).  Workspace: PPCA_OP_POWER. */
+int ppca_prime_power_eps(const ppca_matrix* X, int32_t k, int32_t l, int32_t max_iters,
+                         double eps, float* V, int32_t* iters_done, double* changes,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* The power method of Sec. 2.1 for K = k + l directions found one after the
+ * other: direction i starts from column i of V, orthogonalised against the
+ * directions before it and normalised, and iterates
+ * u <- P X^T X u / |P X^T X u| with P = I - V_<i V_<i^T (the orthogonalisation
+ * after every step that keeps it in the complement of the directions found),
+ * until |u_t - u_{t+1}| < eps or max_steps steps.  Each step is one streaming
+ * pass with K = 1 plus a one-workgroup update in float64; the host reads the
+ * state every 8 steps (steps past convergence change nothing).
+ * V: device d x K float32 in/out (orthonormal columns out); steps: host int
+ * [K], the steps each direction took.  Workspace: PPCA_OP_POWER_SEQ. */
+int ppca_prime_power_seq(const ppca_matrix* X, int32_t k, int32_t l, double eps,
+                         int32_t max_steps, float* V, int32_t* steps,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* Minibatch Sanger / generalised Oja priming (Sec. 2.2): for each step the
  * minibatch mean of dw_m = y_m (x - sum_{l<=m} y_l w_l), in matrix form
  * g = (Z_b - V triu(G_b)) / b with Z_b = X_b^T X_b V', G_b = V'^T X_b^T X_b V';
@@ -186,6 +214,16 @@ int ppca_stream_pass(const ppca_matrix* X, int32_t K, const float* V, int64_t r0
  * G, B: device K x K float64.  V: device d x K float32. */
 int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V,
                       double* G, double* B, void* ws, size_t ws_bytes, void* stream);
+
+/* The projection of ppca_project_gram over the rows r0, r0+1, ...,
+ * r0+nrows-1 (mod n) only: the cheaper final pass of the large-scale runs of
+ * Sec. 5.2, which project a tenth of the rows.  G is the unnormalised Gram of
+ * those rows; pass a matrix descriptor with n = nrows to ppca_rayleigh_ritz so
+ * that H = R^-T G R^-1 / nrows.  0 <= r0 < n, 1 <= nrows <= n.  Workspace:
+ * PPCA_OP_PROJECT with batch = nrows. */
+int ppca_project_gram_rows(const ppca_matrix* X, int32_t K, const float* V, int64_t r0,
+                           int64_t nrows, double* G, double* B,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* Rayleigh-Ritz: exact PCA of the projected data (Alg. 1 step 4).
  * R = chol(B); H = R^-T G R^-1 / n; H = W Theta W^T (parallel Jacobi,
@@ -292,7 +330,8 @@ int ppca_tune_group_items(const ppca_problem* probs, int32_t nprob, const int64_
 
 /* Bytes of workspace needed by operation `op` (PPCA_OP_*) for data X with
  * K directions and minibatch `batch` (rows of the pass for PPCA_OP_STREAM;
- * ignored by the other non-minibatch operations).
+ * for PPCA_OP_PROJECT 0 = all n rows, else the rows of the window of
+ * ppca_project_gram_rows; ignored by the other non-minibatch operations).
  * Returns 0 for invalid arguments. */
 size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch);
 

@@ -28,7 +28,8 @@ __all__ = [
     "e4m3_encode", "e4m3_value", "fp8_column_scales",
     "covariance", "jacobi_eigh", "exact_pca", "sign_normalise",
     "cholesky_upper", "solve_right_upper", "cholqr2",
-    "stream_pass", "prime_power", "minibatch_rows", "learning_rate",
+    "stream_pass", "prime_power", "prime_power_eps", "prime_power_sequential",
+    "minibatch_rows", "learning_rate",
     "sanger_direction", "sanger_per_sample", "prime_oja",
     "eigengame_utility", "eigengame_grad", "prime_eigengame",
     "project_gram", "rayleigh_ritz", "ppca",
@@ -316,6 +317,63 @@ def prime_power(x: np.ndarray, v0: np.ndarray, iters: int, operand=None):
         grams.append(g)
         v, _ = cholqr2(z)
     return v, grams
+
+
+def column_change(v_new: np.ndarray, v_old: np.ndarray) -> float:
+    """max_j |v_new[:, j] - v_old[:, j]|_2: the termination quantity of the
+    power method (Sec. 2.1, |x_i - x_{i+1}| < eps) taken over the columns of
+    a block (reading: the block stops when every column has stopped moving)."""
+    d = np.asarray(v_new, np.float64) - np.asarray(v_old, np.float64)
+    return float(np.max(np.linalg.norm(d, axis=0)))
+
+
+def prime_power_eps(x: np.ndarray, v0: np.ndarray, max_iters: int, eps: float, operand=None):
+    """Block power iteration with the termination rule of Sec. 2.1: as
+    prime_power, stopping after the first iteration t whose column change
+    max_j |v_j^t - v_j^{t-1}| is below eps (or after max_iters).  CholeskyQR
+    keeps every column's sign (positive diagonal of R), so the change is
+    meaningful column by column.  Returns (V_t, t, [changes])."""
+    v, _ = cholqr2(v0)
+    changes = []
+    for t in range(1, max_iters + 1):
+        z, _ = stream_pass(x, v if operand is None else operand(v))
+        vn, _ = cholqr2(z)
+        changes.append(column_change(vn, v))
+        v = vn
+        if changes[-1] < eps:
+            return v, t, changes
+    return v, max_iters, changes
+
+
+def prime_power_sequential(x: np.ndarray, v0: np.ndarray, eps: float, max_iters: int):
+    """The power method of Sec. 2.1 for several directions, one after the
+    other: direction i starts from column i of V0 and iterates
+    u <- P M u / |P M u| with M = X^T X and P = I - V_<i V_<i^T (the
+    orthogonalisation after every step that keeps it in the complement of the
+    directions already found), until |u_t - u_{t+1}| < eps or max_iters
+    steps.  Returns (V d x K with orthonormal columns, [steps per direction])."""
+    x = np.asarray(x, np.float64)
+    v0 = np.asarray(v0, np.float64)
+    d, kk = v0.shape
+    v = np.zeros((d, kk))
+    steps = []
+    for i in range(kk):
+        prev = v[:, :i]
+        u = v0[:, i] - prev @ (prev.T @ v0[:, i])
+        u = u / np.linalg.norm(u)
+        t = 0
+        while t < max_iters:
+            w = x.T @ (x @ u)
+            w = w - prev @ (prev.T @ w)
+            w = w / np.linalg.norm(w)
+            t += 1
+            delta = np.linalg.norm(w - u)
+            u = w
+            if delta < eps:
+                break
+        v[:, i] = u
+        steps.append(t)
+    return v, steps
 
 
 # --------------------------------------------------------------------------

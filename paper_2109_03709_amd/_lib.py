@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppca.so")
 
 F32, BF16, FP8_E4M3 = 0, 1, 2
-OP_CENTER, OP_POWER, OP_OJA, OP_EIGENGAME, OP_PROJECT, OP_RR, OP_STREAM = range(7)
+OP_CENTER, OP_POWER, OP_OJA, OP_EIGENGAME, OP_PROJECT, OP_RR, OP_STREAM, OP_POWER_SEQ = range(8)
 MAX_K = 128
 
 EXPORTS = [
@@ -27,7 +27,8 @@ EXPORTS = [
     "ppca_set_kernel_timing", "ppca_kernel_stats", "ppca_set_chunk_rows",
     "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
     "ppca_grouped_workspace_bytes_for", "ppca_set_group_item_bytes", "ppca_tune_group_items",
-    "ppca_rayleigh_ritz_noalloc", "ppca_set_fused_pass",
+    "ppca_rayleigh_ritz_noalloc", "ppca_set_fused_pass", "ppca_prime_power_eps",
+    "ppca_prime_power_seq", "ppca_project_gram_rows",
 ]
 NOALLOC_SCRATCH_BYTES = 16 << 20
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
@@ -77,6 +78,11 @@ def lib():
         L.ppca_center_quantize.argtypes = [vp, i64, i64, i64, i32, vp, i64, vp, vp, vp, sz, vp]
         L.ppca_prime_power.argtypes = [mp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
         L.ppca_prime_oja.argtypes = [mp, i32, i32, sp, vp, vp, sz, vp]
+        L.ppca_prime_power_eps.argtypes = [mp, i32, i32, i32, dbl, vp, ctypes.POINTER(i32),
+                                           ctypes.POINTER(dbl), vp, sz, vp]
+        L.ppca_prime_power_seq.argtypes = [mp, i32, i32, dbl, i32, vp, ctypes.POINTER(i32), vp,
+                                           sz, vp]
+        L.ppca_project_gram_rows.argtypes = [mp, i32, vp, i64, i64, vp, vp, vp, sz, vp]
         L.ppca_prime_eigengame.argtypes = [mp, i32, i32, sp, vp, vp, sz, vp]
         L.ppca_stream_pass.argtypes = [mp, i32, vp, i64, i64, vp, vp, vp, sz, vp]
         L.ppca_project_gram.argtypes = [mp, i32, vp, vp, vp, vp, sz, vp]
@@ -195,6 +201,39 @@ def prime_power(X: Data, k: int, l: int, iters: int, V: torch.Tensor,
     return V
 
 
+def prime_power_eps(X: Data, k: int, l: int, max_iters: int, eps: float, V: torch.Tensor,
+                    ws: torch.Tensor | None = None):
+    """Block power priming stopped by the Sec. 2.1 rule (every column moved by
+    less than eps); V updated in place.  Returns (V, iterations run, [changes])."""
+    K = k + l
+    _check_v(V, X.d, K)
+    m = X.as_c()
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_POWER, X, K), V.device)
+    it = ctypes.c_int32(0)
+    ch = (ctypes.c_double * max_iters)()
+    code = lib().ppca_prime_power_eps(ctypes.byref(m), k, l, max_iters, float(eps), _ptr(V),
+                                      ctypes.byref(it), ch, _ptr(ws), ws.numel(), _stream())
+    _check(code, "ppca_prime_power_eps")
+    return V, it.value, list(ch[:it.value])
+
+
+def prime_power_seq(X: Data, k: int, l: int, eps: float, max_steps: int, V: torch.Tensor,
+                    ws: torch.Tensor | None = None):
+    """Sequential power method (one direction after the other, Sec. 2.1); V
+    updated in place.  Returns (V, [steps per direction])."""
+    K = k + l
+    _check_v(V, X.d, K)
+    m = X.as_c()
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_POWER_SEQ, X, K), V.device)
+    steps = (ctypes.c_int32 * K)()
+    code = lib().ppca_prime_power_seq(ctypes.byref(m), k, l, float(eps), max_steps, _ptr(V),
+                                      steps, _ptr(ws), ws.numel(), _stream())
+    _check(code, "ppca_prime_power_seq")
+    return V, list(steps)
+
+
 def _sgd(X: Data, K: int, V: torch.Tensor, batch: int, steps: int | None, epochs: float | None,
          eta0: float, t0: float, momentum: float, nesterov: bool, start_step: int,
          mom_buf, snapshot_every: int, snapshots, orthonormalise_start: bool) -> _Sgd:
@@ -304,11 +343,31 @@ def rayleigh_ritz_noalloc(X: Data, K: int, k: int, G: torch.Tensor, B: torch.Ten
     return ev, E
 
 
-def ppca(X: Data, V: torch.Tensor, k: int):
-    """Alg. 1 steps 2-4 on primed directions V: (evals[k], E d x k)."""
+def project_gram_rows(X: Data, K: int, V: torch.Tensor, r0: int, nrows: int, ws=None):
+    """(G, B) of the projection over rows r0 .. r0 + nrows - 1 (mod n)."""
+    _check_v(V, X.d, K)
+    G = torch.empty((K, K), dtype=torch.float64, device=V.device)
+    B = torch.empty((K, K), dtype=torch.float64, device=V.device)
+    m = X.as_c()
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_PROJECT, X, K, nrows), V.device)
+    code = lib().ppca_project_gram_rows(ctypes.byref(m), K, _ptr(V), r0, nrows, _ptr(G), _ptr(B),
+                                        _ptr(ws), ws.numel(), _stream())
+    _check(code, "ppca_project_gram_rows")
+    return G, B
+
+
+def ppca(X: Data, V: torch.Tensor, k: int, rows: tuple[int, int] | None = None):
+    """Alg. 1 steps 2-4 on primed directions V: (evals[k], E d x k).  rows =
+    (r0, nrows) projects only that row window (Sec. 5.2 projects a tenth)."""
     K = V.shape[1]
-    G, B = project_gram(X, K, V)
-    return rayleigh_ritz(X, K, k, G, B, V)
+    if rows is None:
+        G, B = project_gram(X, K, V)
+        return rayleigh_ritz(X, K, k, G, B, V)
+    r0, nrows = rows
+    G, B = project_gram_rows(X, K, V, r0, nrows)
+    Xs = Data(X.x[:nrows], X.dtype, X.col_scale)     # descriptor with n = nrows (data not read)
+    return rayleigh_ritz(Xs, K, k, G, B, V)
 
 
 def _check_v(V: torch.Tensor, d: int, K: int):

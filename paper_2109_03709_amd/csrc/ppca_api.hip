@@ -115,7 +115,7 @@ struct Plan {
   size_t ypart = 0;
   size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
          a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
-         sums = 0, cmax = 0, mean = 0;
+         sums = 0, cmax = 0, mean = 0, vprev = 0, chg = 0, su = 0, sw = 0, stmp = 0, sst = 0;
   size_t total = 0;
 };
 
@@ -176,6 +176,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   }
   int64_t pass_rows = n;
   if (op == PPCA_OP_OJA || op == PPCA_OP_EIGENGAME || op == PPCA_OP_STREAM) pass_rows = batch;
+  if (op == PPCA_OP_PROJECT && batch > 0) pass_rows = batch;   // projection of a row window
   const int64_t chunk = g_chunk_rows.load();
   if (chunk > 0 && chunk < pass_rows) pass_rows = round_up(chunk, 256);
   p.rows_cap = round_up(pass_rows, 256);
@@ -211,10 +212,28 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     p.fdummy = c.take(fz.dummy_bytes);
     p.fpart = c.take(fz.part_bytes);
   }
+  if (op == PPCA_OP_POWER) {
+    p.vprev = c.take((size_t)d * K * sizeof(float));   // termination rule: previous iterate
+    p.chg = c.take(256);
+  }
   if (op == PPCA_OP_EIGENGAME) {
     const int64_t nblk = eigengame_blocks(d, K);
     p.egs = c.take((size_t)(2 * d * K + 2 * nblk * K) * sizeof(double));
   }
+  p.total = c.off;
+  return p;
+}
+
+// Sequential power method: the plan of a K = 1 power pass, then three
+// d-vectors and the step state of the direction being computed.
+Plan make_seq_plan(int64_t n, int64_t d, int32_t dtype) {
+  Plan p = make_plan(PPCA_OP_POWER, n, d, dtype, 1, 0);
+  Carve c;
+  c.off = p.total;
+  p.su = c.take((size_t)d * sizeof(float));
+  p.sw = c.take((size_t)d * sizeof(float));
+  p.stmp = c.take((size_t)d * sizeof(float));
+  p.sst = c.take(256);
   p.total = c.off;
   return p;
 }
@@ -720,6 +739,86 @@ int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters, 
   return finish(p, ws, s);
 }
 
+int ppca_prime_power_eps(const ppca_matrix* X, int32_t k, int32_t l, int32_t max_iters, double eps,
+                         float* V, int32_t* iters_done, double* changes, void* ws,
+                         size_t ws_bytes, void* stream) {
+  RET_IF(check_matrix(X));
+  if (k < 1 || l < 0 || max_iters < 1 || !V || !iters_done) return PPCA_ERR_ARG;
+  if (!(eps >= 0.0) || !isfinite(eps)) return PPCA_ERR_ARG;
+  const int K = k + l;
+  RET_IF(check_k(X, K));
+  const Plan p = make_plan(PPCA_OP_POWER, X->n, X->d, X->dtype, K, 0);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  RET_IF(cholqr2(V, V, X->d, K, p, ws, s));
+  float* Z = at<float>(ws, p.z);
+  float* Vp = at<float>(ws, p.vprev);
+  double* ch = at<double>(ws, p.chg);
+  *iters_done = max_iters;
+  for (int t = 1; t <= max_iters; ++t) {
+    HIP_TRY(launch_copy_f32(V, Vp, X->d * K, s));
+    RET_IF(make_operand(X, V, p, ws, s));
+    RET_IF(run_pass(X, p, ws, 0, X->n, Z, nullptr, nullptr, false, s));
+    RET_IF(cholqr2(Z, V, X->d, K, p, ws, s));
+    HIP_TRY(launch_col_change(V, Vp, X->d, K, ch, s));
+    double h = 0.0;
+    int hst = 0;
+    HIP_TRY(hipMemcpyAsync(&h, ch, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hst != PPCA_OK) return hst;
+    if (changes) changes[t - 1] = h;
+    if (h < eps) {
+      *iters_done = t;
+      break;
+    }
+  }
+  return finish(p, ws, s);
+}
+
+int ppca_prime_power_seq(const ppca_matrix* X, int32_t k, int32_t l, double eps,
+                         int32_t max_steps, float* V, int32_t* steps, void* ws, size_t ws_bytes,
+                         void* stream) {
+  RET_IF(check_matrix(X));
+  if (k < 1 || l < 0 || max_steps < 1 || !V || !steps) return PPCA_ERR_ARG;
+  if (!(eps >= 0.0) || !isfinite(eps)) return PPCA_ERR_ARG;
+  const int K = k + l;
+  RET_IF(check_k(X, K));
+  const Plan p = make_seq_plan(X->n, X->d, X->dtype);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  int* st = at<int>(ws, p.status);
+  HIP_TRY(launch_zero(st, 256, s));
+  float* u = at<float>(ws, p.su);
+  float* w = at<float>(ws, p.sw);
+  float* tmp = at<float>(ws, p.stmp);
+  SeqState* ss = at<SeqState>(ws, p.sst);
+  float* Z = at<float>(ws, p.z);
+  constexpr int kBatch = 8;   // steps between two reads of the state
+  for (int i = 0; i < K; ++i) {
+    HIP_TRY(launch_seq_start(V, X->d, K, i, u, ss, tmp, st, s));
+    SeqState h{0, 0, 0.0};
+    while (!h.done) {
+      for (int b = 0; b < kBatch; ++b) {
+        // Z = X^T X u: the power step's pass with K = 1 (u is a d x 1 block)
+        RET_IF(make_operand(X, u, p, ws, s));
+        RET_IF(run_pass(X, p, ws, 0, X->n, Z, nullptr, nullptr, false, s));
+        HIP_TRY(launch_seq_step(V, X->d, K, i, Z, u, w, ss, eps, max_steps, st, s));
+      }
+      int hst = 0;
+      HIP_TRY(hipMemcpyAsync(&h, ss, sizeof(SeqState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (hst != PPCA_OK) return hst;
+    }
+    HIP_TRY(launch_seq_store(V, X->d, K, i, u, s));
+    steps[i] = h.steps;
+  }
+  return finish(p, ws, s);
+}
+
 int ppca_prime_oja(const ppca_matrix* X, int32_t k, int32_t l, const ppca_sgd_params* p, float* V,
                    void* ws, size_t ws_bytes, void* stream) {
   return prime_sgd(false, X, k, l, p, V, ws, ws_bytes, stream);
@@ -756,6 +855,22 @@ int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V, double* G
   RET_IF(make_operand(X, V, p, ws, s));
   RET_IF(operand_gram(X, p, ws, B, s));
   RET_IF(run_pass(X, p, ws, 0, X->n, nullptr, G, nullptr, true, s));
+  return finish(p, ws, s);
+}
+
+int ppca_project_gram_rows(const ppca_matrix* X, int32_t K, const float* V, int64_t r0,
+                           int64_t nrows, double* G, double* B, void* ws, size_t ws_bytes,
+                           void* stream) {
+  RET_IF(check_matrix(X));
+  if (!V || !G || !B || r0 < 0 || r0 >= X->n || nrows < 1) return PPCA_ERR_ARG;
+  RET_IF(check_k(X, K));
+  const Plan p = make_plan(PPCA_OP_PROJECT, X->n, X->d, X->dtype, K, nrows);
+  RET_IF(check_ws(ws, ws_bytes, p));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
+  RET_IF(make_operand(X, V, p, ws, s));
+  RET_IF(operand_gram(X, p, ws, B, s));
+  RET_IF(run_pass(X, p, ws, r0, nrows, nullptr, G, nullptr, true, s));
   return finish(p, ws, s);
 }
 
@@ -936,10 +1051,12 @@ int ppca_tune_group_items(const ppca_problem* probs, int32_t nprob, const int64_
 
 size_t ppca_workspace_bytes(int32_t op, const ppca_matrix* X, int32_t K, int32_t batch) {
   if (!X || X->n < 1 || X->d < 1) return 0;
-  if (op < PPCA_OP_CENTER || op > PPCA_OP_STREAM) return 0;
+  if (op < PPCA_OP_CENTER || op > PPCA_OP_POWER_SEQ) return 0;
   if (op != PPCA_OP_CENTER && (K < 1 || K > PPCA_MAX_K)) return 0;
   if ((op == PPCA_OP_OJA || op == PPCA_OP_EIGENGAME) && (batch < 1 || batch > X->n)) return 0;
   if (op == PPCA_OP_STREAM && batch < 1) return 0;
+  if (op == PPCA_OP_PROJECT && (batch < 0 || batch > X->n)) return 0;
+  if (op == PPCA_OP_POWER_SEQ) return make_seq_plan(X->n, X->d, X->dtype).total;
   const Plan p = make_plan(op, X->n, X->d, X->dtype, op == PPCA_OP_CENTER ? 1 : K, batch);
   return p.total;
 }

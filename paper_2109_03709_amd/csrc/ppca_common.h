@@ -139,6 +139,20 @@ hipError_t launch_sign_fix(float* E, int64_t d, int k, int* status, hipStream_t 
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
+// power method's termination rule and sequential power method (k_seq.hip)
+struct SeqState {
+  int steps, done;
+  double delta;
+};
+hipError_t launch_col_change(const float* Vn, const float* Vo, int64_t d, int K, double* out,
+                             hipStream_t s);
+hipError_t launch_seq_start(const float* V, int64_t d, int K, int i, float* u, SeqState* st,
+                            float* tmp, int* status, hipStream_t s);
+hipError_t launch_seq_step(const float* V, int64_t d, int K, int i, const float* Z, float* u,
+                           float* w, SeqState* st, double eps, int max_steps, int* status,
+                           hipStream_t s);
+hipError_t launch_seq_store(float* V, int64_t d, int K, int i, const float* u, hipStream_t s);
+
 // minibatch updates (k_update.hip)
 hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                 int b, double eta, double mu, int nesterov, float* mom,

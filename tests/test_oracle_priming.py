@@ -244,3 +244,75 @@ def test_oja_converges_on_easy_problem():
     v, _ = O.prime_oja(x, gaussian_block(10, 3, 1, np.float64), batch=100, steps=1500, eta0=0.2, t0=0)
     ang = O.angles(v, p.q[:, :3])
     assert np.all(ang < 0.05)
+
+
+# ------------------------------------------------ termination rule (Sec. 2.1)
+def _data(n, d, seed):
+    """Centred Gaussian rows with a decaying column scale (distinct eigenvalues)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d)) * (0.8 ** np.arange(d))[None, :]
+    return x - x.mean(axis=0, keepdims=True)
+
+def test_power_eps_stops_where_the_iterates_stop_moving():
+    """The eps-terminated block power iteration is the plain iteration cut at
+    the first t where every column moved by less than eps: its changes equal
+    the column changes of the plain iterates (brute force), and it stops at
+    the first one below eps."""
+    x = _data(300, 12, seed=41)
+    v0 = np.random.default_rng(42).standard_normal((12, 4))
+    eps = 1e-6
+    v, t, changes = O.prime_power_eps(x, v0, 200, eps)
+    prev = O.cholqr2(v0)[0]
+    for s in range(1, t + 1):
+        cur, _ = O.prime_power(x, v0, s)
+        ch = np.max(np.linalg.norm(cur - prev, axis=0))
+        assert abs(ch - changes[s - 1]) < 1e-12
+        assert (ch < eps) == (s == t)
+        prev = cur
+    assert np.allclose(v, prev, atol=1e-14)
+
+
+def test_power_eps_fixed_point():
+    """Started on the top-K eigenvectors the iterates do not move: one step."""
+    p = make_problem(400, 10, "exp0.9", seed=43, mode="exact")
+    x = O.center_fp32(p.x, O.column_means(p.x)).astype(np.float64)
+    u = O.exact_pca(x, 3)[1]
+    v, t, ch = O.prime_power_eps(x, u, 50, 1e-9)
+    assert t == 1 and ch[0] < 1e-9
+
+
+def test_sequential_power_first_direction_is_the_printed_recurrence():
+    """Direction 0 of the sequential method is x_{t+1} = M x_t / |M x_t|
+    (Sec. 2.1) run until |x_t - x_{t+1}| < eps: the same vector as
+    M^T x_0 / |M^T x_0| for the step count it reports (matrix powers)."""
+    x = _data(200, 8, seed=44)
+    m = x.T @ x
+    v0 = np.random.default_rng(45).standard_normal((8, 3))
+    v, steps = O.prime_power_sequential(x, v0, 1e-8, 5000)
+    t = steps[0]
+    u0 = v0[:, 0] / np.linalg.norm(v0[:, 0])
+    mp = np.linalg.matrix_power(m / np.linalg.norm(m, 2), t)
+    ref = mp @ u0
+    ref /= np.linalg.norm(ref)
+    assert np.allclose(v[:, 0], ref, atol=1e-10)
+    # the rule: the last step moved less than eps, the one before did not
+    mp1 = np.linalg.matrix_power(m / np.linalg.norm(m, 2), t - 1) @ u0
+    mp1 /= np.linalg.norm(mp1)
+    assert np.linalg.norm(ref - mp1) < 1e-8
+    if t >= 2:
+        mp2 = np.linalg.matrix_power(m / np.linalg.norm(m, 2), t - 2) @ u0
+        mp2 /= np.linalg.norm(mp2)
+        assert np.linalg.norm(mp1 - mp2) >= 1e-8
+
+
+def test_sequential_power_finds_the_eigenvectors_in_order():
+    """On exact-spectrum data with separated eigenvalues every direction
+    converges to +-q_i in order, orthonormal (closed form of the generator)."""
+    p = make_problem(2000, 12, "exp0.9", seed=46, mode="exact")
+    x = O.center_fp32(p.x, O.column_means(p.x)).astype(np.float64)
+    v0 = np.random.default_rng(47).standard_normal((12, 5))
+    v, steps = O.prime_power_sequential(x, v0, 1e-11, 20000)
+    cos = np.abs(np.sum(v * p.q[:, :5], axis=0))
+    assert np.min(cos) > 1 - 1e-8
+    assert np.linalg.norm(v.T @ v - np.eye(5)) < 1e-10
+    assert all(s < 20000 for s in steps)
