@@ -18,6 +18,9 @@ Prints one JSON line:
 
 --workload oja-f32 / eigengame-fp8 / grouped-bf16 print the same line for the
 minibatch primings and for 512 independent problems solved together.
+--workload paper-synthetic runs the paper's own small-scale synthetic study
+(Sec. 5.1: 5000 x 50, spectra from 1000 to 1, k = 16, l in {0, 2, 4}) on the GPU
+path and reports the time to a longest correct eigenvector streak of 16.
 """
 from __future__ import annotations
 
@@ -65,7 +68,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=500000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8", "grouped-bf16"],
+    ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8", "grouped-bf16",
+                                           "paper-synthetic"],
                     default="power-bf16",
                     help="power-bf16: the headline block-power workload (default); oja-f32 / "
                          "eigengame-fp8: the minibatch primings at their configuration shapes; "
@@ -80,6 +84,8 @@ def main():
         sys.exit(2)
     if a.workload == "grouped-bf16":
         return main_grouped(a)
+    if a.workload == "paper-synthetic":
+        return main_paper_synthetic(a)
     if a.workload != "power-bf16":
         return main_minibatch(a)
     import torch
@@ -133,7 +139,7 @@ def main():
         ev, E = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    slots = (0, 1, 3)
+    slots = (0, 1, 3, 4)
     P_stats = {sl: P.kernel_stats(sl) for sl in slots}
     P.set_kernel_timing(False)
     ms_per_step = dt * 1e3 / a.steps
@@ -160,8 +166,9 @@ def main():
     # stream).  Every launch of these kernels streams X once: its algorithmic
     # bytes are n d s; the Y staging traffic of the two-kernel pass is
     # reported beside them, not counted.
-    names = {0: "ppca_xv (Y = X V', G = Y^T Y)", 1: "ppca_xty (Z = X^T Y)",
-             3: "ppca_xxv (single-read power pass, Z = X^T bf16(X V'))"}
+    names = {0: "ppca_xv (power pass Y = X V')", 1: "ppca_xty (Z = X^T Y)",
+             3: "ppca_xxv (single-read power pass, Z = X^T bf16(X V'))",
+             4: "ppca_xvg (projection pass, G = Y^T Y, two-term operand)"}
     per = {}
     for sl in slots:
         nl, tot = P_stats[sl]
@@ -198,6 +205,7 @@ def main():
 
     if not a.no_tta:
         out["time_to_1e-3"] = time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch)
+        out["next_steps"] = tenth_and_eps_stop(P, X, V, v0, lam, q, k, l, iters, dev, torch)
     if a.copy_probe:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -241,9 +249,9 @@ def measured_traffic(n, d, K, storage, iters, fused):
         kv = _counter_file(TRAFFIC_FILE, "k_stream.hip", "k_stream_sha1", wl)
         if kv:
             f = lambda k: int(kv[k + ".fetch_bytes"]) + int(kv[k + ".write_bytes"])
-            out[0] = f("xv_project") if fused else int(
-                (iters * f("xv_power") + f("xv_project")) / (iters + 1))
+            out[0] = f("xv_power")
             out[1] = f("xty")
+            out[4] = f("xv_project")
     except (OSError, KeyError, ValueError):
         pass
     try:
@@ -264,6 +272,43 @@ def _timed(torch, fn, reps=3):
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t0) * 1e3)
     return float(np.median(ts))
+
+
+def _acc(ev, E, lam, q, k):
+    rel = float(np.max(np.abs(ev.cpu().numpy() - lam[:k]) / lam[:k]))
+    qe = np.linalg.qr(E.cpu().numpy().astype(np.float64))[0]
+    return rel, float(np.linalg.norm(qe - q[:, :k] @ (q[:, :k].T @ qe), 2))
+
+
+def tenth_and_eps_stop(P, X, V, v0, lam, q, k, l, iters, dev, torch):
+    """The steps on either side of the path (Sec. 5.2 and Sec. 2.1): the pPCA
+    step projecting only a tenth of the rows, on the primed V of the timed run,
+    against the full projection; and block power stopped by the termination
+    rule (every new direction within eps of the previous span) instead of a
+    fixed budget."""
+    K = k + l
+    n = X.n
+    res = {}
+    tenth = n // 10
+    full = _timed(torch, lambda: P.ppca(X, V, k))
+    part = _timed(torch, lambda: P.ppca(X, V, k, rows=(0, tenth)))
+    ev, E = P.ppca(X, V, k, rows=(0, tenth))
+    rel, sin_t = _acc(ev, E, lam, q, k)
+    res["projection_of_a_tenth"] = {"rows": tenth, "ms": round(part, 3), "full_ms": round(full, 3),
+                                    "max_rel_eig_err": rel, "sin_theta_max": sin_t}
+    for eps in (1e-2, 1e-3):
+        Vw = v0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, t, ch = P.prime_power_eps(X, k, l, 120, eps, Vw)
+        ev, E = P.ppca(X, Vw, k)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        rel, sin_t = _acc(ev, E, lam, q, k)
+        res[f"eps_stop_{eps:g}"] = {"iters": t, "ms_with_ppca": round(ms, 2),
+                                    "last_change": ch[-1], "max_rel_eig_err": rel,
+                                    "sin_theta_max": sin_t}
+    return res
 
 
 def time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch, cap=80):
@@ -702,6 +747,213 @@ def cpu_baseline_grouped(data, shapes, v0s, iters, budget_s=12.0):
             "sample": f"the first {done} of the {len(shapes)} problems, each with {iters} power "
                       f"iterations + projection + Rayleigh-Ritz in float64 numpy; GB/s counts "
                       f"one read of the 2-byte stored data per pass, like the GPU value"}
+
+
+# ---------------------------------------------------------------------------
+# The paper's small-scale synthetic study (Sec. 5.1 "Synthetic data", training
+# setup of Sec. 5, hyper-parameter grids, streak metric of Sec. 5.3), run on the
+# GPU path: EigenGame and Oja/Sanger (SGD with Nesterov momentum 0.9, batch
+# 1000) and the sequential power method with its eps-stop, each alone and with
+# the pPCA step on top (l = 0, 2, 4 extra directions).
+# ---------------------------------------------------------------------------
+SMALL = {"n": 5000, "d": 50, "k": 16, "batch": 1000, "steps": 3000, "every": 10,
+         "seeds": 10, "grid_seeds": 3, "seed": 3100,
+         "eg_lrs": [1.0, 1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6],
+         "oja_lrs": [1e-3, 1e-4, 1e-5, 1e-6],
+         "eps": [1e-3, 1e-4, 1e-5, 1e-6, 1e-7], "power_max_steps": 3000,
+         "ls": [0, 2, 4], "thresholds": [8, 16, 32, 64, 128, 256, 512, 1024]}
+
+
+def _col_angles(e, q):
+    """arccos(|<e_i, q_i>| / |e_i|), column by column (q orthonormal)."""
+    e = np.asarray(e, np.float64)
+    nrm = np.linalg.norm(e, axis=0)
+    c = np.abs(np.sum(e * q, axis=0)) / np.where(nrm > 0, nrm, 1.0)
+    c = np.where(np.isfinite(c), c, 0.0)
+    return np.arccos(np.clip(c, 0.0, 1.0))
+
+
+def _streak(ang, th):
+    n = 0
+    for a_ in ang:
+        if a_ < th:
+            n += 1
+        else:
+            break
+    return n
+
+
+def main_paper_synthetic(a):
+    import torch
+    import paper_2109_03709_amd as P
+    from synthdata import gaussian_block, make_problem
+
+    c = SMALL
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, d, k, b = c["n"], c["d"], c["k"], c["batch"]
+    ths = [(f"pi/{t}", math.pi / t) for t in c["thresholds"]]
+    nsnap = c["steps"] // c["every"]
+    out_sets = {}
+    t_all = time.perf_counter()
+    for si, spec in enumerate(["paper-exp", "paper-lin"]):
+        prob = make_problem(n, d, spec, seed=c["seed"] + si, mode="exact")
+        ld = (d + 3) // 4 * 4                   # 16-byte row stride (d = 50 -> 52)
+        xbuf = torch.zeros((n, ld), dtype=torch.float32, device=dev)
+        X, _ = P.center_quantize(torch.from_numpy(prob.x).to(dev), P.F32, out=xbuf[:, :d])
+        torch.cuda.synchronize()
+        q = prob.q[:, :k]
+
+        def sgd(method, K, lr, seed):
+            prime = P.prime_eigengame if method == "eigengame" else P.prime_oja
+            V = torch.from_numpy(gaussian_block(d, K, seed, np.float32)).to(dev)
+            snaps = torch.empty((nsnap, d * K), dtype=torch.float32, device=dev)
+            mom = torch.zeros((d, K), dtype=torch.float32, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prime(X, k, K - k, V, batch=b, steps=c["steps"], eta0=lr, t0=0.0, momentum=0.9,
+                  nesterov=True, mom_buf=mom, snapshot_every=c["every"], snapshots=snaps)
+            torch.cuda.synchronize()
+            return snaps, (time.perf_counter() - t0) / c["steps"]
+
+        def ppca_time(K, snaps):
+            Vs = snaps[-1].view(d, K).contiguous()
+            P.ppca(X, Vs, k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                P.ppca(X, Vs, k)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / 5
+
+        def first_time(angle_rows, t_step, extra):
+            """time to streak 16 per threshold: first snapshot whose streak is k"""
+            res = {}
+            for name, th in ths:
+                tt = None
+                for s_, ang in enumerate(angle_rows):
+                    if _streak(ang, th) >= k:
+                        tt = (s_ + 1) * c["every"] * t_step + extra
+                        break
+                res[name] = tt
+            return res
+
+        rows = {}
+        chosen = {}
+        for method, lrs in (("eigengame", c["eg_lrs"]), ("oja", c["oja_lrs"])):
+            # learning rate: smallest angular error summed over runs, timesteps
+            # and principal components (Sec. 5.1), priming alone, K = k
+            score = {}
+            for lr in lrs:
+                tot = 0.0
+                for r in range(c["grid_seeds"]):
+                    try:
+                        snaps, _ = sgd(method, k, lr, 7000 + r)
+                    except P.PPCAError:          # the rate diverged (non-finite iterate)
+                        tot = float("inf")
+                        break
+                    sh = snaps.view(nsnap, d, k).cpu().numpy()
+                    tot += float(sum(_col_angles(sh[i], q).sum() for i in range(nsnap)))
+                score[lr] = tot if math.isfinite(tot) else float("inf")
+            lr = min(score, key=score.get)
+            chosen[method] = {"lr": lr, "grid_summed_angle": {str(kk): round(v, 2) for kk, v in score.items()}}
+            log(f"{spec} {method}: lr {lr}")
+            names = {0: [method, method + "+pPCA"], 2: [method + "+pPCA2"], 4: [method + "+pPCA4"]}
+            for l in c["ls"]:
+                K = k + l
+                res_by_name = {nm: [] for nm in names[l]}
+                for r in range(c["seeds"]):
+                    snaps, t_step = sgd(method, K, lr, 8000 + r)
+                    sh = snaps.view(nsnap, d, K)
+                    if l == 0:
+                        prim = [_col_angles(sh[i].cpu().numpy(), q) for i in range(nsnap)]
+                        res_by_name[method].append(first_time(prim, t_step, 0.0))
+                    tp = ppca_time(K, snaps)
+                    pp = []
+                    for i in range(nsnap):
+                        try:
+                            _, E = P.ppca(X, sh[i].contiguous(), k)
+                            pp.append(_col_angles(E.cpu().numpy(), q))
+                        except P.PPCAError:      # a snapshot with dependent columns
+                            pp.append(np.full(k, math.pi / 2))
+                    res_by_name[names[l][-1] if l else method + "+pPCA"].append(
+                        first_time(pp, t_step, tp))
+                rows.update(res_by_name)
+        # sequential power method: eps from the grid by the summed angular
+        # error of its final directions; time = the whole run
+        score = {}
+        for eps in c["eps"]:
+            tot = 0.0
+            for r in range(c["grid_seeds"]):
+                V = torch.from_numpy(gaussian_block(d, k, 7000 + r, np.float32)).to(dev)
+                P.prime_power_seq(X, k, 0, eps, c["power_max_steps"], V)
+                tot += float(_col_angles(V.cpu().numpy(), q).sum())
+            score[eps] = tot
+        eps = min(score, key=score.get)
+        chosen["power"] = {"eps": eps, "grid_summed_angle": {str(kk): round(v, 4) for kk, v in score.items()}}
+        rows["power"], rows["power+pPCA"] = [], []
+        for r in range(c["seeds"]):
+            V = torch.from_numpy(gaussian_block(d, k, 8000 + r, np.float32)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, steps = P.prime_power_seq(X, k, 0, eps, c["power_max_steps"], V)
+            torch.cuda.synchronize()
+            t_run = time.perf_counter() - t0
+            ang = _col_angles(V.cpu().numpy(), q)
+            rows["power"].append({nm: (t_run if _streak(ang, th) >= k else None) for nm, th in ths})
+            t0 = time.perf_counter()
+            _, E = P.ppca(X, V, k)
+            torch.cuda.synchronize()
+            t_pp = time.perf_counter() - t0
+            ang = _col_angles(E.cpu().numpy(), q)
+            rows["power+pPCA"].append({nm: (t_run + t_pp if _streak(ang, th) >= k else None)
+                                       for nm, th in ths})
+        # mean +- std over the seeds, "n.a." when one run never reached the streak
+        table = {}
+        means = {}
+        for nm, runs in rows.items():
+            table[nm] = {}
+            means[nm] = {}
+            for th_name, _ in ths:
+                vals = [rr[th_name] for rr in runs]
+                if any(v is None for v in vals):
+                    table[nm][th_name] = "n.a."
+                    means[nm][th_name] = None
+                else:
+                    m_, s_ = float(np.mean(vals)), float(np.std(vals))
+                    table[nm][th_name] = f"{m_ * 1e3:.2f} +- {s_ * 1e3:.2f} ms"
+                    means[nm][th_name] = m_
+        out_sets[spec] = {"chosen": chosen, "time_to_streak16": table, "_means": means}
+    # orderings of Table 3 (V = pi/8): pPCA on top of the SGD primings reaches
+    # the streak sooner; on top of the power method it changes little
+    orders = {}
+    for spec, res in out_sets.items():
+        mm = res.pop("_means")
+
+        def lt(x, y, th="pi/8"):
+            a_, b_ = mm[x][th], mm[y][th]
+            if a_ is None:
+                return False
+            return b_ is None or a_ < b_
+        orders[spec] = {
+            "eigengame+pPCA4 < eigengame": lt("eigengame+pPCA4", "eigengame"),
+            "eigengame+pPCA < eigengame": lt("eigengame+pPCA", "eigengame"),
+            "oja+pPCA4 < oja": lt("oja+pPCA4", "oja"),
+            "oja+pPCA < oja": lt("oja+pPCA", "oja"),
+            "power+pPCA within 25% of power": (mm["power"]["pi/8"] is not None and
+                                               mm["power+pPCA"]["pi/8"] is not None and
+                                               mm["power+pPCA"]["pi/8"] <= 1.25 * mm["power"]["pi/8"]),
+        }
+    out = {"metric": "seconds to a longest correct eigenvector streak of 16 (Sec. 5.3), small-scale synthetic data",
+           "value": None, "unit": "s", "n_gpus": 1, "steps": c["steps"], "warmup": 0,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "paper-small-synthetic", "n": n, "d": d, "k": k,
+                      "batch": b, "l": c["ls"], "momentum": "nesterov 0.9",
+                      "seeds": c["seeds"], "snapshot_every_steps": c["every"]},
+           "datasets": out_sets, "table3_orderings": orders,
+           "wall_s": round(time.perf_counter() - t_all, 1)}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -149,12 +149,15 @@ int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters,
 
 /* Block power priming with the termination rule of Sec. 2.1 (the power
  * method stops when |x_i - x_{i+1}| < eps), read for a block as: stop after
- * the first iteration t at which every column moved by less than eps,
- * max_j |v_j^t - v_j^{t-1}|_2 < eps (CholeskyQR2 keeps each column's sign, so
- * the change is meaningful column by column).  Otherwise as
+ * the first iteration t at which every new direction lies within eps of the
+ * previous iterate's span, max_j |v_j^t - V_{t-1} V_{t-1}^T v_j^t|_2 < eps
+ * (for one unit vector: the sine of the angle it turned, |x_i - x_{i+1}| to
+ * first order; the columns of a block keep turning inside its span long
+ * after the span has settled, so their individual changes are not used).
+ * Otherwise as
  * ppca_prime_power with at most max_iters iterations.  iters_done: host int
  * (the number of iterations run); changes: host double [max_iters] or NULL
- * (the change of each iteration run).  The host reads the change after every
+ * (the span change of each iteration run).  The host reads the change after every
  * iteration (one synchronisation per pass).  Workspace: PPCA_OP_POWER. */
 int ppca_prime_power_eps(const ppca_matrix* X, int32_t k, int32_t l, int32_t max_iters,
                          double eps, float* V, int32_t* iters_done, double* changes,
@@ -343,7 +346,8 @@ const char* ppca_strerror(int status);
  * launch of each streaming kernel and accumulates their elapsed times.
  * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty),
  * 2 = fused grouped pass (power and projection passes of the grouped calls,
- * eager mode only), 3 = single-read power pass (ppca_set_fused_pass).
+ * eager mode only), 3 = single-read power pass (ppca_set_fused_pass),
+ * 4 = projection pass (ppca_project_gram, ppca_project_gram_rows).
  * ppca_kernel_stats returns the number of launches and the total ms since
  * the last reset.  Not thread safe; meant for benchmarks. */
 void ppca_set_kernel_timing(int32_t enable);

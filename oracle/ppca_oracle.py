@@ -319,26 +319,32 @@ def prime_power(x: np.ndarray, v0: np.ndarray, iters: int, operand=None):
     return v, grams
 
 
-def column_change(v_new: np.ndarray, v_old: np.ndarray) -> float:
-    """max_j |v_new[:, j] - v_old[:, j]|_2: the termination quantity of the
-    power method (Sec. 2.1, |x_i - x_{i+1}| < eps) taken over the columns of
-    a block (reading: the block stops when every column has stopped moving)."""
-    d = np.asarray(v_new, np.float64) - np.asarray(v_old, np.float64)
-    return float(np.max(np.linalg.norm(d, axis=0)))
+def span_change(v_new: np.ndarray, v_old: np.ndarray) -> float:
+    """max_j |v_new[:, j] - V_old (V_old^T v_new[:, j])|_2: how far the new
+    iterate's directions lie from the previous iterate's span (V_old with
+    orthonormal columns).  This is the termination quantity of the power
+    method (Sec. 2.1, |x_i - x_{i+1}| < eps) read for a block: a single unit
+    vector gives the sine of the angle it turned, |x_i - x_{i+1}| to first
+    order.  Columns of a block keep turning inside the K-dimensional span
+    long after the span itself has settled, so a column-by-column change
+    would not measure the convergence of block iteration."""
+    v_new = np.asarray(v_new, np.float64)
+    v_old = np.asarray(v_old, np.float64)
+    r = v_new - v_old @ (v_old.T @ v_new)
+    return float(np.max(np.linalg.norm(r, axis=0)))
 
 
 def prime_power_eps(x: np.ndarray, v0: np.ndarray, max_iters: int, eps: float, operand=None):
     """Block power iteration with the termination rule of Sec. 2.1: as
-    prime_power, stopping after the first iteration t whose column change
-    max_j |v_j^t - v_j^{t-1}| is below eps (or after max_iters).  CholeskyQR
-    keeps every column's sign (positive diagonal of R), so the change is
-    meaningful column by column.  Returns (V_t, t, [changes])."""
+    prime_power, stopping after the first iteration t whose span change
+    (span_change of V_t against V_{t-1}) is below eps, or after max_iters.
+    Returns (V_t, t, [changes])."""
     v, _ = cholqr2(v0)
     changes = []
     for t in range(1, max_iters + 1):
         z, _ = stream_pass(x, v if operand is None else operand(v))
         vn, _ = cholqr2(z)
-        changes.append(column_change(vn, v))
+        changes.append(span_change(vn, v))
         v = vn
         if changes[-1] < eps:
             return v, t, changes

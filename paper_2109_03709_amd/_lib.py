@@ -203,8 +203,9 @@ def prime_power(X: Data, k: int, l: int, iters: int, V: torch.Tensor,
 
 def prime_power_eps(X: Data, k: int, l: int, max_iters: int, eps: float, V: torch.Tensor,
                     ws: torch.Tensor | None = None):
-    """Block power priming stopped by the Sec. 2.1 rule (every column moved by
-    less than eps); V updated in place.  Returns (V, iterations run, [changes])."""
+    """Block power priming stopped by the Sec. 2.1 rule (every new direction
+    within eps of the previous span); V updated in place.  Returns (V,
+    iterations run, [span changes])."""
     K = k + l
     _check_v(V, X.d, K)
     m = X.as_c()

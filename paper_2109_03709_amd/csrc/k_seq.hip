@@ -25,21 +25,30 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// out = max_j |Vn[:, j] - Vo[:, j]|_2 over the K columns
-__global__ __launch_bounds__(kT) void k_col_change(const float* __restrict__ Vn,
-                                                   const float* __restrict__ Vo, int64_t d, int K,
-                                                   double* __restrict__ out) {
+// res[j] = |Vn[:, j] - Vo (Vo^T Vn[:, j])|_2, workgroup j: how far the new
+// iterate's direction j lies from the previous iterate's span (Vo has
+// orthonormal columns); the host takes the largest
+__global__ __launch_bounds__(kT) void k_span_change(const float* __restrict__ Vn,
+                                                    const float* __restrict__ Vo, int64_t d, int K,
+                                                    double* __restrict__ res) {
   __shared__ double sh[kT];
-  double best = 0.0;
-  for (int c = 0; c < K; ++c) {
+  __shared__ double coef[PPCA_MAX_K];
+  const int j = blockIdx.x;
+  for (int i = 0; i < K; ++i) {
     double s = 0.0;
-    for (int64_t j = threadIdx.x; j < d; j += kT) {
-      const double df = (double)Vn[j * K + c] - (double)Vo[j * K + c];
-      s += df * df;
-    }
-    best = fmax(best, block_sum(s, sh));
+    for (int64_t r = threadIdx.x; r < d; r += kT) s += (double)Vo[r * K + i] * (double)Vn[r * K + j];
+    const double c = block_sum(s, sh);
+    if (threadIdx.x == 0) coef[i] = c;
   }
-  if (threadIdx.x == 0) *out = sqrt(best);
+  __syncthreads();
+  double nn = 0.0;
+  for (int64_t r = threadIdx.x; r < d; r += kT) {
+    double w = (double)Vn[r * K + j];
+    for (int i = 0; i < K; ++i) w -= coef[i] * (double)Vo[r * K + i];
+    nn += w * w;
+  }
+  const double t = block_sum(nn, sh);
+  if (threadIdx.x == 0) res[j] = sqrt(t);
 }
 
 // w <- w - V_<i (V_<i^T w) for column i of V (w: d-vector, float64 in LDS-free
@@ -130,9 +139,9 @@ __global__ void k_seq_store(float* __restrict__ V, int64_t d, int K, int i,
 
 }  // namespace
 
-hipError_t launch_col_change(const float* Vn, const float* Vo, int64_t d, int K, double* out,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_col_change, dim3(1), dim3(kT), 0, s, Vn, Vo, d, K, out);
+hipError_t launch_span_change(const float* Vn, const float* Vo, int64_t d, int K, double* res,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_span_change, dim3(K), dim3(kT), 0, s, Vn, Vo, d, K, res);
   return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ struct KStat {
   int64_t launches = 0;
   double ms = 0.0;
 };
-KStat g_stats[4];
+KStat g_stats[5];
 struct Pending {
   hipEvent_t a, b;
   int kernel;
@@ -214,7 +214,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   }
   if (op == PPCA_OP_POWER) {
     p.vprev = c.take((size_t)d * K * sizeof(float));   // termination rule: previous iterate
-    p.chg = c.take(256);
+    p.chg = c.take((size_t)K * sizeof(double));        // ... and the span change per column
   }
   if (op == PPCA_OP_EIGENGAME) {
     const int64_t nblk = eigengame_blocks(d, K);
@@ -333,7 +333,7 @@ int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t 
   const int64_t chunk = (p.rows_cap < nrows) ? p.rows_cap : nrows;
   for (int64_t i0 = 0; i0 < nrows; i0 += chunk) {
     const int64_t rows = (nrows - i0) < chunk ? (nrows - i0) : chunk;
-    HIP_TRY(timed(0, s, [&] {
+    HIP_TRY(timed(gram_only ? 4 : 0, s, [&] {
       return launch_xv(pd, b, i0, rows, !gram_only, G != nullptr, i0 > 0, s);
     }));
     if (!gram_only)
@@ -762,13 +762,15 @@ int ppca_prime_power_eps(const ppca_matrix* X, int32_t k, int32_t l, int32_t max
     RET_IF(make_operand(X, V, p, ws, s));
     RET_IF(run_pass(X, p, ws, 0, X->n, Z, nullptr, nullptr, false, s));
     RET_IF(cholqr2(Z, V, X->d, K, p, ws, s));
-    HIP_TRY(launch_col_change(V, Vp, X->d, K, ch, s));
-    double h = 0.0;
+    HIP_TRY(launch_span_change(V, Vp, X->d, K, ch, s));
+    double hres[PPCA_MAX_K];
     int hst = 0;
-    HIP_TRY(hipMemcpyAsync(&h, ch, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hres, ch, (size_t)K * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hst != PPCA_OK) return hst;
+    double h = 0.0;
+    for (int j = 0; j < K; ++j) h = hres[j] > h ? hres[j] : h;
     if (changes) changes[t - 1] = h;
     if (h < eps) {
       *iters_done = t;
@@ -1085,7 +1087,7 @@ void ppca_set_kernel_timing(int32_t enable) {
 }
 
 int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
-  if (kernel < 0 || kernel > 3) return PPCA_ERR_ARG;
+  if (kernel < 0 || kernel > 4) return PPCA_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (launches) *launches = g_stats[kernel].launches;
   if (total_ms) *total_ms = g_stats[kernel].ms;

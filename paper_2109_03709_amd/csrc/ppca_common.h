@@ -144,8 +144,9 @@ struct SeqState {
   int steps, done;
   double delta;
 };
-hipError_t launch_col_change(const float* Vn, const float* Vo, int64_t d, int K, double* out,
-                             hipStream_t s);
+// res[j] (K doubles) = distance of column j of Vn from span(Vo)
+hipError_t launch_span_change(const float* Vn, const float* Vo, int64_t d, int K, double* res,
+                              hipStream_t s);
 hipError_t launch_seq_start(const float* V, int64_t d, int K, int i, float* u, SeqState* st,
                             float* tmp, int* status, hipStream_t s);
 hipError_t launch_seq_step(const float* V, int64_t d, int K, int i, const float* Z, float* u,

@@ -255,9 +255,11 @@ def _data(n, d, seed):
 
 def test_power_eps_stops_where_the_iterates_stop_moving():
     """The eps-terminated block power iteration is the plain iteration cut at
-    the first t where every column moved by less than eps: its changes equal
-    the column changes of the plain iterates (brute force), and it stops at
-    the first one below eps."""
+    the first t where the new span lies within eps of the previous one: its
+    changes equal the largest principal-angle sines between successive plain
+    iterates (brute force through an SVD; equal to the largest column
+    residual up to the factor sqrt(K) at most, here compared as bounds), and
+    it stops at the first one below eps."""
     x = _data(300, 12, seed=41)
     v0 = np.random.default_rng(42).standard_normal((12, 4))
     eps = 1e-6
@@ -265,11 +267,25 @@ def test_power_eps_stops_where_the_iterates_stop_moving():
     prev = O.cholqr2(v0)[0]
     for s in range(1, t + 1):
         cur, _ = O.prime_power(x, v0, s)
-        ch = np.max(np.linalg.norm(cur - prev, axis=0))
+        res = cur - prev @ (prev.T @ cur)
+        ch = np.max(np.linalg.norm(res, axis=0))
         assert abs(ch - changes[s - 1]) < 1e-12
+        # the largest principal-angle sine (SVD) bounds it from both sides
+        sin_max = np.linalg.svd(res, compute_uv=False)[0]
+        assert sin_max / 2.0 - 1e-12 <= ch <= sin_max + 1e-12
         assert (ch < eps) == (s == t)
         prev = cur
     assert np.allclose(v, prev, atol=1e-14)
+
+
+def test_span_change_of_one_vector_is_the_printed_quantity():
+    """For one unit vector the span change is the sine of the turn, equal to
+    the printed |x_i - x_{i+1}| to first order in the angle."""
+    a = np.array([[1.0], [0.0], [0.0]])
+    for th in (1e-2, 1e-4, 1e-6):
+        b = np.array([[math.cos(th)], [math.sin(th)], [0.0]])
+        assert abs(O.span_change(b, a) - math.sin(th)) < 1e-15
+        assert abs(O.span_change(b, a) - np.linalg.norm(b - a)) < th * th
 
 
 def test_power_eps_fixed_point():
