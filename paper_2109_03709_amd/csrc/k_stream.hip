@@ -467,24 +467,28 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x_, int64_t n, int
 // epilogue.  A last step that ends inside a 16-byte chunk has the chunk's
 // columns past d cleared in LDS by the lane that loaded it.
 // ---------------------------------------------------------------------------
-template <int NB, int DT, int MW, bool WANT_Y, bool WANT_G, bool PART = false>
+template <int NB, int DT, int MW, bool WANT_Y, bool WANT_G, bool PART = false, bool SPLIT = false>
 __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, int64_t d_, int64_t ld,
                                                 int64_t rstart, int64_t rows, const uint8_t* vop_,
                                                 int64_t dp, uint8_t* yb, float* gpart,
                                                 int accumulate, float* ypart, int64_t yrows) {
   static_assert(DT == DT_F32 || DT == DT_BF16, "bf16 or f32 data");
   static_assert(!PART || (!WANT_Y && !WANT_G), "partial mode writes only float32 Y partials");
+  // SPLIT: the two-term operand of the projection (hi at vop, lo Kp dp later),
+  // two products per output into one float32 accumulator (partial mode only)
+  static_assert(!SPLIT || (PART && DT == DT_BF16), "two-term operand: bf16 partial mode");
+  constexpr int NV = SPLIT ? 2 : 1;                    // operand terms
   constexpr int Kp = NB * 16;
   constexpr int NBG = (NB + 3) / 4;                    // G column blocks per wave
   constexpr int EB = DT == DT_F32 ? 4 : 2;             // bytes per X / V' / Y element
   constexpr int KS = 128 / EB;                         // columns per k-step
   constexpr int WGR = 64 * MW;                         // rows per tile
   constexpr int XSB = WGR * 128, VSB = Kp * 128;       // stage bytes of X and V'
-  constexpr int STB = XSB + VSB;
+  constexpr int STB = XSB + NV * VSB;
   constexpr int XI = WGR / 32;                         // X DMAs per wave per step
   constexpr int VBLK = Kp / 8;                         // 1 KB blocks of a V' stage
   constexpr int VI = (VBLK + 3) / 4;                   // V' DMAs per wave per step
-  constexpr int DPS = XI + VI;                         // DMAs per wave per step
+  constexpr int DPS = XI + NV * VI;                    // DMAs per wave per step
   constexpr int YR = 16 / EB;                          // rows per Y chunk (8 / 4)
   constexpr int YTB = WGR * Kp * EB;                   // Y tile bytes
   constexpr int YHB = YTB / 2;                         // half tile (rows [0, WGR/2) in st0)
@@ -579,6 +583,12 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
       }
 #pragma unroll
       for (int j = 0; j < VI; ++j) dma16(vsrc[j] + k0 * EB, sb + XSB + vblk[j] * 1024);
+      if constexpr (SPLIT) {
+        const int64_t lo_off = (int64_t)Kp * dp * EB;
+#pragma unroll
+        for (int j = 0; j < VI; ++j)
+          dma16(vsrc[j] + lo_off + k0 * EB, sb + XSB + VSB + vblk[j] * 1024);
+      }
     };
     // clear the columns past d of the chunks this lane loaded in the last step
     auto fix_tail = [&](int b) __attribute__((always_inline)) {
@@ -638,6 +648,20 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
             for (int nb = 0; nb < NB; ++nb)
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af[mb]), as_bf16x8(bf[nb]),
                                                                     acc[mb][nb], 0, 0, 0);
+          if constexpr (SPLIT) {
+            // second term: the same X fragments against lo
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              const int r = nb * 16 + a;
+              bf[nb] = *reinterpret_cast<const uint4*>(vs + VSB + r * 128 + ((c ^ (r & 7)) * 16));
+            }
+#pragma unroll
+            for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    as_bf16x8(af[mb]), as_bf16x8(bf[nb]), acc[mb][nb], 0, 0, 0);
+          }
         }
       }
     };
@@ -1725,16 +1749,31 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
                          yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
                          accumulate ? 1 : 0);
     };
-    // projection of bf16 data with the two-term operand
-    if constexpr (NB % 2 == 0) {
-      if (b.split && p.dtype == PPCA_BF16 && want_g && !want_y) {
+    // projection of bf16 data with the two-term operand: short passes split
+    // their columns (partial products of both terms, then k_ysum), longer
+    // ones run k_xvg
+    if (b.split) {
+      if (p.dtype != PPCA_BF16 || !want_g || want_y) return hipErrorInvalidValue;
+      if (b.ksplit > 1) {
+        const int64_t ntile = cdiv(rows, 64);
+        const int64_t yrows = round_up(b.rows_cap, 64);
+        hipLaunchKernelGGL((k_xvd<NB, DT_BF16, 1, false, false, true, true>), dim3(ntile, b.ksplit),
+                           dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d, p.ld, rstart, rows,
+                           (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr, (float*)nullptr, 0,
+                           b.ypart, yrows);
+        hipLaunchKernelGGL((k_ysum<NB, DT_BF16>), dim3(b.ngpart), dim3(256), 0, s, b.ypart,
+                           b.ksplit, yrows, rows, (uint8_t*)b.yb, b.gpart, 0, 1,
+                           accumulate ? 1 : 0);
+        return hipGetLastError();
+      }
+      if constexpr (NB % 2 == 0) {
         hipLaunchKernelGGL(k_xvg<NB>, dim3(b.ngpart), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
                            p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, b.gpart,
                            accumulate ? 1 : 0);
         return hipGetLastError();
       }
+      return hipErrorInvalidValue;
     }
-    if (b.split) return hipErrorInvalidValue;
     // bf16 / f32 data: LDS-DMA kernel; fp8 data: register-staged kernel
     auto by_mw = [&](auto dtc, auto yc, auto gc) {
       constexpr int DT = decltype(dtc)::value;

@@ -82,6 +82,39 @@ __device__ inline void sum_partials(const double* __restrict__ part, int nblk, i
   __syncthreads();
 }
 
+// Many blocks (large d): the column sums of the per-block partials are formed
+// once, by K workgroups (workgroup c: thread t adds blocks t, t + 256, ... in
+// order, then a fixed tree), instead of by every block of the next kernel.
+constexpr int kDirectPartials = 64;   // up to this many blocks each block sums them itself
+
+__global__ __launch_bounds__(kThreads) void k_sum_cols(const double* __restrict__ part, int nblk,
+                                                       int K, double* __restrict__ out) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (int w = t; w < nblk; w += kThreads) s += part[(int64_t)w * K + c];
+  sh[t] = s;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (t < h) sh[t] += sh[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[c] = sh[0];
+}
+
+// the column sums of part: from the precomputed sums when there are many
+// blocks, else summed here (LDS result)
+__device__ inline void column_sums(const double* __restrict__ part,
+                                   const double* __restrict__ pre, int nblk, int K,
+                                   const Lane& L, double* scr, double* out) {
+  if (pre) {
+    if ((int)threadIdx.x < K) out[threadIdx.x] = pre[threadIdx.x];
+    __syncthreads();
+  } else {
+    sum_partials(part, nblk, K, L, scr, out);
+  }
+}
+
 // Per-block column sums of the thread values (fixed order) -> part[blk * K + c].
 __device__ inline void block_column_sum(double val, int K, const Lane& L, double* scr,
                                         double* __restrict__ part) {
@@ -220,7 +253,8 @@ __global__ __launch_bounds__(kThreads) void k_eg_grad(const float* __restrict__ 
 // EigenGame, phase 2: Riemannian projection, momentum, ascent step; partial norms.
 __global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ V,
                                                       const double* __restrict__ grad,
-                                                      const double* __restrict__ pdot, int nblk,
+                                                      const double* __restrict__ pdot,
+                                                      const double* __restrict__ pdot_sum, int nblk,
                                                       int64_t d, int K, double eta, double mu,
                                                       int nesterov, float* __restrict__ mom,
                                                       double* __restrict__ vnew,
@@ -237,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ 
     v[q] = V[jc * K + c];
     gr[q] = grad[jc * K + c];
   }
-  sum_partials(pdot, nblk, K, L, scr, dots);
+  column_sums(pdot, pdot_sum, nblk, K, L, scr, dots);
   if (status_set(status)) return;
   double sq = 0.0;
 #pragma unroll
@@ -259,6 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ 
 __global__ __launch_bounds__(kThreads) void k_eg_normalise(float* __restrict__ V,
                                                            const double* __restrict__ vnew,
                                                            const double* __restrict__ pnorm,
+                                                           const double* __restrict__ pnorm_sum,
                                                            int nblk, int64_t d, int K,
                                                            int* status) {
   __shared__ double nrm[kMaxK];
@@ -268,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_eg_normalise(float* __restrict__ V
   double vn[kRowsPerThread];
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) vn[q] = vnew[clamp_row(L.row(q), d) * K + c];
-  sum_partials(pnorm, nblk, K, L, scr, nrm);
+  column_sums(pnorm, pnorm_sum, nblk, K, L, scr, nrm);
   if (status_set(status)) return;
   if (threadIdx.x < K) {
     const double s = nrm[threadIdx.x];
@@ -302,7 +337,12 @@ hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64
   return hipGetLastError();
 }
 
-// scratch layout: grad [d*K] | vnew [d*K] | pdot [nblk*K] | pnorm [nblk*K]   (float64)
+size_t eigengame_scratch_doubles(int64_t d, int K) {
+  return (size_t)(2 * d * K + 2 * (int64_t)eigengame_blocks(d, K) * K + 2 * K);
+}
+
+// scratch layout: grad [d*K] | vnew [d*K] | pdot [nblk*K] | pnorm [nblk*K] |
+// pdot sums [K] | pnorm sums [K]   (float64)
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
                                    double* scratch, int* status, hipStream_t s) {
@@ -311,14 +351,20 @@ hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, in
   double* vnew = grad + d * K;
   double* pdot = vnew + d * K;
   double* pnorm = pdot + (int64_t)nblk * K;
+  double* sums = pnorm + (int64_t)nblk * K;
+  const bool two_level = nblk > kDirectPartials;
   const size_t lds = ((size_t)K * K + kThreads) * sizeof(double) +
                      (size_t)block_rows(K) * K * sizeof(float);
   hipLaunchKernelGGL(k_eg_grad, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, grad, pdot,
                      status);
-  hipLaunchKernelGGL(k_eg_step, dim3(nblk), dim3(kThreads), 0, s, V, grad, pdot, nblk, d, K, eta,
-                     mu, nesterov, mom, vnew, pnorm, status);
-  hipLaunchKernelGGL(k_eg_normalise, dim3(nblk), dim3(kThreads), 0, s, V, vnew, pnorm, nblk, d, K,
-                     status);
+  if (two_level) hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pdot, nblk, K, sums);
+  hipLaunchKernelGGL(k_eg_step, dim3(nblk), dim3(kThreads), 0, s, V, grad, pdot,
+                     two_level ? (const double*)sums : nullptr, nblk, d, K, eta, mu, nesterov, mom,
+                     vnew, pnorm, status);
+  if (two_level)
+    hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pnorm, nblk, K, sums + K);
+  hipLaunchKernelGGL(k_eg_normalise, dim3(nblk), dim3(kThreads), 0, s, V, vnew, pnorm,
+                     two_level ? (const double*)(sums + K) : nullptr, nblk, d, K, status);
   return hipGetLastError();
 }
 

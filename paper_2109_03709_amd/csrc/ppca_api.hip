@@ -189,9 +189,11 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.part = c.take(op == PPCA_OP_PROJECT
                       ? 16
                       : (size_t)p.ntiles * p.nsplit * p.Kp * xty_cols(p.Kp) * sizeof(float));
-  p.ngpart = p.split ? xvg_grid(p.rows_cap) : xv_grid(dtype, p.Kp, d, p.rows_cap);
+  // the two-term projection: column split on short passes (as every short
+  // pass), else k_xvg (one partial per workgroup)
+  p.ksplit = xv_ksplit(dtype, p.Kp, d, p.rows_cap);
+  p.ngpart = (p.split && p.ksplit == 1) ? xvg_grid(p.rows_cap) : xv_grid(dtype, p.Kp, d, p.rows_cap);
   p.gpart = c.take((size_t)p.ngpart * p.Kp * p.Kp * sizeof(float));
-  p.ksplit = p.split ? 1 : xv_ksplit(dtype, p.Kp, d, p.rows_cap);
   p.ypart = c.take(p.ksplit > 1 ? (size_t)p.ksplit * round_up(p.rows_cap, 64) * p.Kp * sizeof(float)
                                 : 16);
   p.z = c.take((size_t)d * K * sizeof(float));
@@ -217,8 +219,7 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     p.chg = c.take((size_t)K * sizeof(double));        // ... and the span change per column
   }
   if (op == PPCA_OP_EIGENGAME) {
-    const int64_t nblk = eigengame_blocks(d, K);
-    p.egs = c.take((size_t)(2 * d * K + 2 * nblk * K) * sizeof(double));
+    p.egs = c.take(eigengame_scratch_doubles(d, K) * sizeof(double));
   }
   p.total = c.off;
   return p;

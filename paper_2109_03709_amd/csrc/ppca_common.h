@@ -159,6 +159,7 @@ hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64
                                 int b, double eta, double mu, int nesterov, float* mom,
                                 int* status, hipStream_t s);
 int eigengame_blocks(int64_t d, int K);   // blocks of the EigenGame update kernels
+size_t eigengame_scratch_doubles(int64_t d, int K);
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
                                    double* scratch, int* status, hipStream_t s);

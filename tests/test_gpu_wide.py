@@ -1,0 +1,96 @@
+"""The d >> n regime (the large-scale runs of Sec. 5.2: ~15M dimensions, a few
+thousand rows, minibatch EigenGame then pPCA, a tenth of the rows projected),
+at a shape the float64 oracle can follow: n = 1024, d = 262,144, bf16 data
+with an exact low-rank covariance (make_lowrank_device).  At this shape the
+EigenGame update sums its column partials in two levels (1024 blocks) and the
+two-term projection splits its columns over workgroups (16 row tiles)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ppca_oracle as O
+from synthdata import gaussian_block, make_lowrank_device
+
+from ._gpu_util import (BF16, TRAJ_REL, gram_err, host, operand_basis, oracle_replay,
+                        projection_basis, sin_theta, stored_values, trajectory_error)
+
+pytestmark = pytest.mark.gpu
+
+N, D, R, K, B = 1024, 262_144, 32, 8, 256
+
+
+@pytest.fixture(scope="module")
+def wide():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03709_amd as P
+    P.lib()
+    P.set_chunk_rows(0)
+    print(f"[wide] generating {N} x {D} bf16, rank {R}", flush=True)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    x, lam, b = make_lowrank_device(N, D, R, "exp0.9", seed=91)
+    data = P.Data(x, P.BF16)
+    xs = stored_values(host(x), BF16, None)          # float64 copy of the stored data
+    yield P, data, xs, lam, b.cpu().numpy().astype(np.float64)
+
+
+def test_wide_generator_covariance(wide):
+    """The stored data's covariance is B diag(lam) B^T up to the bf16 rounding
+    of X (relative 2^-9 per element)."""
+    P, data, xs, lam, b = wide
+    # C b_i = lam_i b_i for the leading directions, through two thin products
+    cb = xs.T @ (xs @ b[:, :8]) / N
+    assert np.max(np.abs(cb - b[:, :8] * lam[:8][None, :])) < 1e-2 * lam[0]
+    assert np.max(np.abs(xs.mean(axis=0))) < 1e-3 * np.sqrt(lam[0])
+
+
+def test_wide_eigengame_steps_match_oracle(wide):
+    """One epoch of minibatch EigenGame (4 steps of 256 rows) from the same
+    start, against the oracle's loop replayed on the same rows with the same
+    bf16 operand: the motion-relative bound of the minibatch tests."""
+    P, data, xs, lam, b = wide
+    v0 = gaussian_block(D, K, 92, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    steps, eta0 = 4, 0.2
+    P.prime_eigengame(data, 4, 4, V, batch=B, steps=steps, eta0=eta0)
+    torch.cuda.synchronize()
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    v = oracle_replay("eigengame", lambda t: xs[O.minibatch_rows(N, B, t)], v_start,
+                      range(steps), B, eta0, 0.0,
+                      lambda u: operand_basis(u.astype(np.float32), BF16, None))
+    err = trajectory_error(V.cpu().numpy(), v, v_start)
+    print(f"[wide] EigenGame trajectory error {err:.2e} of the motion", flush=True)
+    assert err < TRAJ_REL
+
+
+def test_wide_projection_and_rayleigh_ritz(wide):
+    """Projection of all rows and of a tenth (two-term operand, column-split
+    pass) against the oracle's Gram; Rayleigh-Ritz against the oracle's on the
+    same G and B; a basis holding the top eigenvectors returns them."""
+    P, data, xs, lam, b = wide
+    # unit-norm eigenvectors plus a perturbation of norm about 1e-3 per column:
+    # the span then lies within ~1e-3 of the top eigenvectors and the Ritz
+    # values within ~1e-6 of lam plus the bf16 rounding of the stored X
+    v = (b[:, :K] + 1e-3 / np.sqrt(D) * gaussian_block(D, K, 93, np.float64)).astype(np.float32)
+    vd = torch.from_numpy(v).cuda()
+    veff = projection_basis(v, BF16, None)
+    for r0, nrows in ((0, N), (300, N // 10)):
+        if nrows == N:
+            G, Bm = P.project_gram(data, K, vd)
+        else:
+            G, Bm = P.project_gram_rows(data, K, vd, r0, nrows)
+        torch.cuda.synchronize()
+        rows = (r0 + np.arange(nrows)) % N
+        g_ref, b_ref = O.project_gram(xs[rows], veff)
+        assert gram_err(G.cpu().numpy(), g_ref) < 4e-3
+        assert np.allclose(Bm.cpu().numpy(), b_ref, rtol=1e-12, atol=1e-12 * np.abs(b_ref).max())
+    ev, E = P.ppca(data, vd, 4)
+    torch.cuda.synchronize()
+    G, Bm = P.project_gram(data, K, vd)
+    th, e_ref, _ = O.rayleigh_ritz(G.cpu().numpy(), Bm.cpu().numpy(), veff, N, 4)
+    assert np.max(O.rel_eig_error(ev.cpu().numpy(), th)) < 1e-8
+    e_lam = np.max(O.rel_eig_error(ev.cpu().numpy(), lam[:4]))
+    s_b = sin_theta(E.cpu().numpy(), b[:, :4])
+    print(f"[wide] Ritz values vs lam {e_lam:.2e}, Ritz vectors vs B {s_b:.2e}", flush=True)
+    assert e_lam < 1e-3
+    assert s_b < 5e-3
