@@ -18,6 +18,10 @@ Prints one JSON line:
 
 --workload oja-f32 / eigengame-fp8 / grouped-bf16 print the same line for the
 minibatch primings and for 512 independent problems solved together.
+--workload eigengame-wide-bf16 runs the d >> n regime of the large-scale runs
+(Sec. 5.2, the image-dataset shape: n = 6654, d = 15,116,544, bf16, 201 GB):
+minibatch EigenGame (b = 1024, k = 8, lr 1e-4, 300 steps) with snapshots every
+30 steps, each followed by the pPCA step on all rows and on a tenth of them.
 --workload paper-synthetic runs the paper's own small-scale synthetic study
 (Sec. 5.1: 5000 x 50, spectra from 1000 to 1, k = 16, l in {0, 2, 4}) on the GPU
 path and reports the time to a longest correct eigenvector streak of 16.
@@ -68,8 +72,10 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=500000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--sgd-steps", type=int, default=0,
+                    help="eigengame-wide-bf16: minibatch steps (0 = the configuration's 300)")
     ap.add_argument("--workload", choices=["power-bf16", "oja-f32", "eigengame-fp8", "grouped-bf16",
-                                           "paper-synthetic"],
+                                           "paper-synthetic", "eigengame-wide-bf16"],
                     default="power-bf16",
                     help="power-bf16: the headline block-power workload (default); oja-f32 / "
                          "eigengame-fp8: the minibatch primings at their configuration shapes; "
@@ -86,6 +92,8 @@ def main():
         return main_grouped(a)
     if a.workload == "paper-synthetic":
         return main_paper_synthetic(a)
+    if a.workload == "eigengame-wide-bf16":
+        return main_wide(a)
     if a.workload != "power-bf16":
         return main_minibatch(a)
     import torch
@@ -954,6 +962,164 @@ def main_paper_synthetic(a):
            "datasets": out_sets, "table3_orderings": orders,
            "wall_s": round(time.perf_counter() - t_all, 1)}
     print(json.dumps(out), flush=True)
+
+
+
+# The d >> n regime (Sec. 5.2, the image dataset: 6654 rows of 1944 x 2592 x 3
+# values, minibatch EigenGame with b = 1024, lr 1e-4, 300 steps, k = 8, then
+# pPCA projecting a tenth of the rows).  The dataset is a stand-in: an exact
+# rank-64 covariance with the paper's own small-scale spectrum (1000 to 1,
+# exponential), at which the paper's grid selects lr 1e-4 for EigenGame.
+WIDE = dict(n=6654, d=1944 * 2592 * 3, rank=64, spectrum="paper-exp", k=8, batch=1024,
+            steps=300, eta0=1e-4, every=30, seed=4100,
+            thresholds=[8, 16, 32, 64, 128, 256, 512, 1024])
+
+
+def main_wide(a):
+    import torch
+    import paper_2109_03709_amd as P
+    from synthdata import make_lowrank_device
+
+    c = WIDE
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    n, d, k, b = c["n"], c["d"], c["k"], c["batch"]
+    steps = a.sgd_steps if a.sgd_steps > 0 else c["steps"]
+    tenth = n // 10
+    log(f"generating X: n={n} d={d} rank={c['rank']} spectrum={c['spectrum']} (bf16)")
+    t0 = time.perf_counter()
+    x, lam, bdir = make_lowrank_device(n, d, c["rank"], c["spectrum"], c["seed"], device=dev)
+    b_top = bdir[:, :k].double().contiguous()
+    del bdir
+    X = P.Data(x, P.BF16)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f}s")
+    g = torch.Generator(device=dev)
+    g.manual_seed(c["seed"] + 1)
+    v0 = torch.randn((d, k), generator=g, device=dev, dtype=torch.float32)
+    V = torch.empty_like(v0)
+    nsnap = steps // c["every"]
+    snaps = torch.empty((max(nsnap, 1), d, k), dtype=torch.float32, device=dev)
+    ws_eg = torch.empty(P.workspace_bytes(P.OP_EIGENGAME, X, k, b), dtype=torch.uint8, device=dev)
+    ws_prj = torch.empty(P.workspace_bytes(P.OP_PROJECT, X, k), dtype=torch.uint8, device=dev)
+    ws_rr = torch.empty(P.workspace_bytes(P.OP_RR, X, k), dtype=torch.uint8, device=dev)
+    Xt = P.Data(x[:tenth], P.BF16)                       # descriptor of the first tenth of rows
+
+    def eigengame(nsteps, snap):
+        V.copy_(v0)
+        P.prime_eigengame(X, k, 0, V, batch=b, steps=nsteps, eta0=c["eta0"],
+                          snapshot_every=c["every"] if snap else 0,
+                          snapshots=snaps if snap else None, ws=ws_eg)
+
+    def ppca_on(Vs, rows):
+        if rows == n:
+            G, B = P.project_gram(X, k, Vs, ws=ws_prj)
+            return P.rayleigh_ritz(X, k, k, G, B, Vs, ws=ws_rr)
+        G, B = P.project_gram(Xt, k, Vs, ws=ws_prj)
+        return P.rayleigh_ritz(Xt, k, k, G, B, Vs, ws=ws_rr)
+
+    # warm-up: a few steps and both projections
+    eigengame(4, False)
+    ppca_on(V, n)
+    ppca_on(V, tenth)
+    torch.cuda.synchronize()
+    P.set_kernel_timing(True)
+    t0 = time.perf_counter()
+    eigengame(steps, True)
+    torch.cuda.synchronize()
+    t_eg = time.perf_counter() - t0
+    P_stats = {sl: P.kernel_stats(sl) for sl in (0, 1)}
+    P.set_kernel_timing(False)
+    t_full = _timed(torch, lambda: ppca_on(V, n)) * 1e-3
+    t_tenth = _timed(torch, lambda: ppca_on(V, tenth)) * 1e-3
+    log(f"EigenGame {steps} steps {t_eg * 1e3:.1f} ms; pPCA all rows {t_full * 1e3:.1f} ms, "
+        f"tenth {t_tenth * 1e3:.1f} ms")
+
+    def angles(E):
+        e = E.double()
+        cth = (e * b_top).sum(0).abs() / e.norm(dim=0).clamp_min(1e-300)
+        return torch.arccos(cth.clamp(0.0, 1.0)).cpu().numpy()
+
+    def subspace_sin(E):
+        qe = torch.linalg.qr(E.double())[0]
+        r = qe - b_top @ (b_top.T @ qe)
+        return float(torch.linalg.matrix_norm(r, 2))
+
+    ths = [(f"pi/{t}", math.pi / t) for t in c["thresholds"]]
+    curve = []
+    for si in range(nsnap):
+        Vs = snaps[si].contiguous()
+        row = {"step": (si + 1) * c["every"]}
+        row["eigengame"] = {"streak": {nm: _streak(angles(Vs), th) for nm, th in ths},
+                            "max_angle": float(np.max(angles(Vs))),
+                            "sin_theta": subspace_sin(Vs)}
+        for key, rows in (("ppca_all_rows", n), ("ppca_tenth", tenth)):
+            ev, E = ppca_on(Vs, rows)
+            ang = angles(E)
+            row[key] = {"streak": {nm: _streak(ang, th) for nm, th in ths},
+                        "max_angle": float(np.max(ang)), "sin_theta": subspace_sin(E),
+                        "max_rel_eig_err": float(np.max(np.abs(ev.cpu().numpy() - lam[:k])
+                                                        / lam[:k]))}
+        curve.append(row)
+    es = 2
+    xbytes = (steps * b + tenth) * d * es
+    dt = t_eg + t_tenth
+    names = {0: "ppca_xv (Y = X_b V', column-split partials + their sum)",
+             1: "ppca_xty (Z = X_b^T Y)"}
+    per = {}
+    for sl, (nl, tot) in P_stats.items():
+        if nl:
+            per[sl] = {"kernel": names[sl], "launches": nl, "avg_ms": round(tot / nl, 4),
+                       "achieved_GBs": round(nl * b * d * es / (tot * 1e-3) / 1e9, 1)}
+    dom = max(per, key=lambda sl: P_stats[sl][1])
+    roofline = {"bound": "hbm", "achieved": per[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(per[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "traffic": None, "kernel": names[dom], "avg_ms": per[dom]["avg_ms"],
+                "alg_bytes_per_launch": b * d * es, "launches": per[dom]["launches"],
+                "other_kernels": [per[sl] for sl in per if sl != dom]}
+    out = {"metric": METRIC, "value": round(xbytes / dt / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(dt * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": a.workload, "n": n, "d": d, "k": k, "l": 0, "batch": b,
+                      "minibatch_steps": steps, "eta0": c["eta0"], "rank": c["rank"],
+                      "spectrum": c["spectrum"], "projection_rows": tenth},
+           "eigengame_ms": round(t_eg * 1e3, 2),
+           "ms_per_minibatch_step": round(t_eg * 1e3 / steps, 3),
+           "ppca_all_rows_ms": round(t_full * 1e3, 2), "ppca_tenth_ms": round(t_tenth * 1e3, 2),
+           "roofline": roofline, "curve": curve}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_wide(X, k, c, v0)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_wide(X, k, c, v0, rows=32, budget_s=12.0):
+    """The float64 oracle's EigenGame steps on a bounded sample: minibatches of
+    `rows` stored rows at the full width d (a 1024-row minibatch at this width
+    is 124 GB in float64), timed over as many steps as about budget_s seconds
+    allow."""
+    import torch
+    from oracle import ppca_oracle as O
+    xs = O.bf16_value(X.x[:rows].contiguous().view(torch.int16).cpu().numpy().view(np.uint16))
+    vh = v0.cpu().numpy().astype(np.float64)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() \
+            else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    O.prime_eigengame(xs, vh, batch=rows, steps=1, eta0=c["eta0"], t0=0.0)
+    cal = time.perf_counter() - t0
+    tsteps = max(1, int(budget_s / max(cal, 1e-6)))
+    t0 = time.perf_counter()
+    O.prime_eigengame(xs, vh, batch=rows, steps=tsteps, eta0=c["eta0"], t0=0.0)
+    dt = time.perf_counter() - t0
+    return {"value": round(tsteps * rows * X.d * 2 / dt / 1e9, 4), "unit": "GB/s",
+            "cores": cores, "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"{tsteps} EigenGame steps of {rows} stored rows at d = {X.d}, float64 "
+                      f"numpy; GB/s counts each minibatch's bf16 bytes once"}
 
 
 if __name__ == "__main__":

@@ -244,14 +244,17 @@ int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k,
  * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
  * and errors as ppca_rayleigh_ritz without ws / ws_bytes: its scratch is a
  * fixed device array of PPCA_NOALLOC_SCRATCH_BYTES inside the library (one
- * copy per GPU, held until the process ends).  A call whose workspace
- * (ppca_workspace_bytes(PPCA_OP_RR, X, K, 0)) exceeds that size returns
- * PPCA_ERR_WORKSPACE without running; `stream` must belong to the current
+ * copy per GPU, held until the process ends).  The Rayleigh-Ritz workspace
+ * does not grow with n or d (the rotation reads V directly; its sign rule
+ * keeps at most 1024 x K column maxima): at most about 2.8 MiB, at
+ * K = PPCA_MAX_K, so every valid call fits; a call whose workspace
+ * (ppca_workspace_bytes(PPCA_OP_RR, X, K, 0)) exceeded the array would return
+ * PPCA_ERR_WORKSPACE without running.  `stream` must belong to the current
  * device (else PPCA_ERR_ARG).  All calls on one GPU share the array: calls
  * that overlap on one GPU (different streams or threads) race and must be
  * serialised by the caller.  No hipMalloc, hipFree or allocating library
  * routine is called. */
-#define PPCA_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define PPCA_NOALLOC_SCRATCH_BYTES (4u << 20)
 int ppca_rayleigh_ritz_noalloc(const ppca_matrix* X, int32_t K, int32_t k,
                                const double* G, const double* B, const float* V,
                                float* E, double* evals, void* stream);

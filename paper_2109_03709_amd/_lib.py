@@ -30,7 +30,7 @@ EXPORTS = [
     "ppca_rayleigh_ritz_noalloc", "ppca_set_fused_pass", "ppca_prime_power_eps",
     "ppca_prime_power_seq", "ppca_project_gram_rows",
 ]
-NOALLOC_SCRATCH_BYTES = 16 << 20
+NOALLOC_SCRATCH_BYTES = 4 << 20
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
 
 

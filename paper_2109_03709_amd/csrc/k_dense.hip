@@ -1,5 +1,6 @@
 // Small dense float64 kernels around the streaming passes:
-//   * the MFMA operand V' and its float64 image V_eff (operand-exact basis),
+//   * the MFMA operand V' (its float64 values V_eff are recomputed from V
+//     where needed: the operand Gram B and the Ritz rotation),
 //   * Gram matrices A^T A of tall d x K blocks (CholeskyQR2, B = V'^T V'),
 //   * Cholesky with an explicit inverse of the triangular factor,
 //   * Q = A R^-1 (CholeskyQR2), small K x K products (Rayleigh-Ritz),
@@ -17,40 +18,71 @@ using dev::status_set;
 constexpr int kJacRows = dev::kJacRows;
 
 // --------------------------------------------------------------------------
-// Operand: vop[c][j] (c < Kp, j < dp; zero outside d x K) and veff[j][c]
-// (j < d, c < Kp; zero for c >= K).
+// Operand: vop[c][j] (c < Kp, j < dp; zero outside d x K), and for the
+// two-term operand the low terms at vop[Kp dp + c dp + j].  One workgroup
+// transposes a 256-row x 16-column tile of V through LDS, so that both the
+// reads of V (row-major) and the writes of vop (column-major) are coalesced.
+// The float64 value an operand entry stands for is recomputed where it is
+// needed (operand_value), never stored: at d in the millions it would be the
+// largest buffer after X.
 // --------------------------------------------------------------------------
+constexpr int kOpRows = 256;   // rows of V per tile
+constexpr int kOpCols = 16;    // columns per tile (Kp is a multiple of 16)
+
 __global__ __launch_bounds__(256) void k_make_operand(const float* __restrict__ V, int64_t d, int K,
-                                                      int Kp, int64_t dp, int dtype,
+                                                      int64_t dp, int dtype,
                                                       const float* __restrict__ scale,
-                                                      void* __restrict__ vop,
-                                                      double* __restrict__ veff, int split) {
-  const int64_t total = (int64_t)Kp * dp;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / dp);
-    const int64_t j = e % dp;
-    const bool in = (j < d) && (c < K);
-    const float v = in ? V[j * K + c] : 0.f;
-    double ve = 0.0;
+                                                      void* __restrict__ vop, int64_t total,
+                                                      int split) {
+  __shared__ float tile[kOpCols][kOpRows + 1];
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kOpRows;
+  const int c0 = (int)blockIdx.y * kOpCols;
+#pragma unroll
+  for (int q = 0; q < kOpRows * kOpCols / 256; ++q) {
+    const int i = t + 256 * q;
+    const int r = i / kOpCols, cc = i % kOpCols;
+    const int64_t j = j0 + r;
+    const int c = c0 + cc;
+    tile[cc][r] = (j < d && c < K) ? V[j * K + c] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kOpRows * kOpCols / 256; ++q) {
+    const int i = t + 256 * q;
+    const int cc = i / kOpRows, r = i % kOpRows;
+    const int64_t j = j0 + r;
+    if (j >= dp) continue;
+    const int64_t e = (int64_t)(c0 + cc) * dp + j;
+    const float v = tile[cc][r];
     if (dtype == PPCA_F32) {
       reinterpret_cast<float*>(vop)[e] = v;
-      ve = (double)v;
     } else {
-      const float sv = (dtype == PPCA_FP8_E4M3 && in) ? scale[j] * v : v;
+      const float sv = (dtype == PPCA_FP8_E4M3 && j < d) ? scale[j] * v : v;
       const uint32_t h = f32_to_bf16_bits(sv);
       reinterpret_cast<uint16_t*>(vop)[e] = (uint16_t)h;
-      ve = (double)bf16_bits_to_f32(h);
       if (split) {
         // sv - hi has at most 16 significant bits: exact in float32
         const uint32_t lo = f32_to_bf16_bits(sv - bf16_bits_to_f32(h));
         reinterpret_cast<uint16_t*>(vop)[total + e] = (uint16_t)lo;
-        ve += (double)bf16_bits_to_f32(lo);
       }
-      if (dtype == PPCA_FP8_E4M3 && in) ve = ve / (double)scale[j];
     }
-    if (j < d) veff[j * Kp + c] = ve;
   }
+}
+
+// The float64 value the operand holds for entry v of row j (j < d): v itself
+// for float32 data; else the bf16 rounding of v (of scale_j v for fp8 data,
+// divided back by scale_j), plus the bf16 rounding of the remainder for the
+// two-term operand.  Same arithmetic as k_make_operand, entry by entry.
+__device__ inline double operand_value(float v, int64_t j, int dtype, int split,
+                                       const float* __restrict__ scale) {
+  if (dtype == PPCA_F32) return (double)v;
+  const float sv = dtype == PPCA_FP8_E4M3 ? scale[j] * v : v;
+  const uint32_t h = f32_to_bf16_bits(sv);
+  double ve = (double)bf16_bits_to_f32(h);
+  if (split) ve += (double)bf16_bits_to_f32(f32_to_bf16_bits(sv - bf16_bits_to_f32(h)));
+  if (dtype == PPCA_FP8_E4M3) ve = ve / (double)scale[j];
+  return ve;
 }
 
 // --------------------------------------------------------------------------
@@ -62,10 +94,14 @@ __global__ __launch_bounds__(256) void k_make_operand(const float* __restrict__ 
 constexpr int kGT = 32;            // Gram output tile
 constexpr int kGR = 64;            // rows staged per step
 
-template <typename T>
+// OPV: A is V (float32, lda = K) and the Gram is taken of the operand values
+// operand_value(V[row][c], row, dtype, split, scale).
+template <typename T, bool OPV = false>
 __global__ __launch_bounds__(256) void k_gram_tile(const T* __restrict__ A, int64_t rows, int K,
                                                    int64_t lda, int nchunk,
-                                                   double* __restrict__ parts) {
+                                                   double* __restrict__ parts, int dtype = 0,
+                                                   int split = 0,
+                                                   const float* __restrict__ scale = nullptr) {
   __shared__ double Ai[kGR][kGT + 1], Aj[kGR][kGT + 1];
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const int nt = (K + kGT - 1) / kGT;
@@ -85,8 +121,15 @@ __global__ __launch_bounds__(256) void k_gram_tile(const T* __restrict__ A, int6
       const int r = e / kGT, c = e % kGT;
       const int64_t row = r0 + r;
       const int ci = ti * kGT + c, cj = tj * kGT + c;
-      Ai[r][c] = (row < re && ci < K) ? (double)A[row * lda + ci] : 0.0;
-      Aj[r][c] = (row < re && cj < K) ? (double)A[row * lda + cj] : 0.0;
+      if constexpr (OPV) {
+        Ai[r][c] = (row < re && ci < K) ? operand_value(A[row * lda + ci], row, dtype, split, scale)
+                                        : 0.0;
+        Aj[r][c] = (row < re && cj < K) ? operand_value(A[row * lda + cj], row, dtype, split, scale)
+                                        : 0.0;
+      } else {
+        Ai[r][c] = (row < re && ci < K) ? (double)A[row * lda + ci] : 0.0;
+        Aj[r][c] = (row < re && cj < K) ? (double)A[row * lda + cj] : 0.0;
+      }
     }
     __syncthreads();
     const int nr = (int)(re - r0 < kGR ? re - r0 : kGR);
@@ -229,60 +272,115 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ H, i
 }
 
 // --------------------------------------------------------------------------
-// E[j][c] = sum_p veff[j][p] M[p][c]  (float64 accumulate, float32 out)
+// Ritz vectors E[j][c] = sum_p veff[j][p] M[p][c] (float64 accumulate, float32
+// out), veff the operand values of V, then the sign rule: column c is negated
+// when its largest-|.| entry (lowest row on ties) is negative.
+//   k_rotate      E, and per workgroup and column the largest |E| entry
+//                 (value and row) among the rows the workgroup wrote;
+//   k_sign_decide one workgroup: per column the largest entry over the
+//                 workgroups (the same entry whatever the order), its sign;
+//   k_flip        negates the flagged columns.
+// A tile is R = 1024 / k rows of E (R k <= 1024 entries, four per thread);
+// thread t always holds tile entries t + 256 q, so its columns are fixed and
+// it keeps a running maximum for each.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ veff, int64_t d, int Kp,
-                                                int K, const double* __restrict__ M, int k,
-                                                float* __restrict__ E, int* status) {
-  __shared__ double Ms[kMaxK * kMaxK];
+constexpr int kRotTile = 1024;
+constexpr int kRotMaxBlocks = 1024;
+
+__device__ inline bool colmax_better(float a, int64_t j, float ba, int64_t bj) {
+  return a > ba || (a == ba && j < bj);
+}
+
+// MS: LDS entries for M (K k <= MS).
+template <int MS>
+__global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ V, int64_t d, int K,
+                                                int dtype, int split,
+                                                const float* __restrict__ scale,
+                                                const double* __restrict__ M, int k,
+                                                float* __restrict__ E, ColMax* __restrict__ part,
+                                                int* status) {
+  __shared__ double Ms[MS];
+  __shared__ ColMax sm[kRotTile];
   if (status_set(status)) return;
   for (int e = threadIdx.x; e < K * k; e += blockDim.x) Ms[e] = M[e];
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d * k;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / k;
-    const int c = (int)(e % k);
-    double s = 0.0;
-    for (int p = 0; p < K; ++p) s = fma(veff[j * Kp + p], Ms[p * k + c], s);
-    E[e] = (float)s;
+  const int R = kRotTile / k > 0 ? kRotTile / k : 1;
+  const int nel = R * k;
+  const int64_t ntiles = (d + R - 1) / R;
+  float ba[4], bv[4];
+  int64_t bj[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ba[q] = -1.f;
+    bv[q] = 0.f;
+    bj[q] = INT64_MAX;
+  }
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i >= nel) continue;
+      const int64_t j = tl * R + i / k;
+      const int c = i % k;
+      if (j >= d) continue;
+      const float* vr = V + j * K;
+      double s = 0.0;
+      for (int p = 0; p < K; ++p) s = fma(operand_value(vr[p], j, dtype, split, scale), Ms[p * k + c], s);
+      const float ef = (float)s;
+      E[j * k + c] = ef;
+      const float a = fabsf(ef);
+      if (colmax_better(a, j, ba[q], bj[q])) {
+        ba[q] = a;
+        bv[q] = ef;
+        bj[q] = j;
+      }
+    }
+  }
+  // the block's maximum per column over its threads' slots
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    if (i < nel) sm[i] = ColMax{ba[q], bv[q], bj[q]};
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    ColMax b{-1.f, 0.f, INT64_MAX};
+    for (int i = c; i < nel; i += k)
+      if (colmax_better(sm[i].a, sm[i].j, b.a, b.j)) b = sm[i];
+    part[(int64_t)blockIdx.x * k + c] = b;
   }
 }
 
-// Flip column c of E so that its largest-|.| entry (lowest row on ties) is positive.
-__global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ E, int64_t d, int k,
-                                                  int* status) {
-  __shared__ float bv[256];
-  __shared__ int64_t bi[256];
+__global__ __launch_bounds__(256) void k_sign_decide(const ColMax* __restrict__ part, int nblk,
+                                                     int k, int* __restrict__ flip, int* status) {
   if (status_set(status)) return;
-  const int c = blockIdx.x;
-  float best = -1.f;
-  int64_t bidx = 0;
-  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
-    const float v = fabsf(E[j * k + c]);
-    if (v > best) { best = v; bidx = j; }
-  }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = bidx;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const float v2 = bv[threadIdx.x + o];
-      const int64_t i2 = bi[threadIdx.x + o];
-      if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
-        bv[threadIdx.x] = v2;
-        bi[threadIdx.x] = i2;
-      }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    ColMax b{-1.f, 0.f, INT64_MAX};
+    for (int w = 0; w < nblk; ++w) {
+      const ColMax m = part[(int64_t)w * k + c];
+      if (colmax_better(m.a, m.j, b.a, b.j)) b = m;
     }
-    __syncthreads();
+    flip[c] = b.a >= 0.f && b.v < 0.f;
   }
-  // One thread reads the pivot and publishes the decision; every thread
-  // waits for it before any row is negated (the pivot row belongs to one of
-  // the threads, which would otherwise negate it before the others read it).
-  __shared__ int flip;
-  if (threadIdx.x == 0) flip = E[bi[0] * k + c] < 0.f;
-  __syncthreads();
-  if (flip)
-    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) E[j * k + c] = -E[j * k + c];
+}
+
+__global__ __launch_bounds__(256) void k_flip(float* __restrict__ E, int64_t d, int k,
+                                              const int* __restrict__ flip, int* status) {
+  if (status_set(status)) return;
+  const int R = kRotTile / k > 0 ? kRotTile / k : 1;
+  const int nel = R * k;
+  const int64_t ntiles = (d + R - 1) / R;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i >= nel) continue;
+      const int64_t j = tl * R + i / k;
+      const int c = i % k;
+      if (j < d && flip[c]) E[j * k + c] = -E[j * k + c];
+    }
+  }
 }
 
 __global__ void k_copy_f64(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
@@ -306,10 +404,11 @@ inline int64_t grid_for(int64_t n, int64_t cap = 4096) {
 }  // namespace
 
 hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp, int32_t dtype,
-                               const float* col_scale, void* vop, double* veff, bool split,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_make_operand, dim3(grid_for((int64_t)Kp * dp)), dim3(256), 0, s, V, d, K,
-                     Kp, dp, (int)dtype, col_scale, vop, veff, split ? 1 : 0);
+                               const float* col_scale, void* vop, bool split, hipStream_t s) {
+  if (Kp % kOpCols != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)cdiv(dp, kOpRows), (unsigned)(Kp / kOpCols));
+  hipLaunchKernelGGL(k_make_operand, grid, dim3(256), 0, s, V, d, K, dp, (int)dtype, col_scale,
+                     vop, (int64_t)Kp * dp, split ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -337,6 +436,18 @@ hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t 
   else
     hipLaunchKernelGGL(k_gram_tile<float>, grid, dim3(256), 0, s, (const float*)A, rows, K, lda,
                        np, parts);
+  hipLaunchKernelGGL(k_sum_gram, dim3(grid_for((int64_t)K * K)), dim3(256), 0, s, parts, np, K,
+                     out, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_operand_gram(const float* V, int64_t d, int K, int32_t dtype, bool split,
+                               const float* col_scale, double* parts, double* out, int* status,
+                               hipStream_t s) {
+  const int np = gram_parts(d, K);
+  const dim3 grid(gram_tiles(K), np);
+  hipLaunchKernelGGL((k_gram_tile<float, true>), grid, dim3(256), 0, s, V, d, K, (int64_t)K, np,
+                     parts, (int)dtype, split ? 1 : 0, col_scale);
   hipLaunchKernelGGL(k_sum_gram, dim3(grid_for((int64_t)K * K)), dim3(256), 0, s, parts, np, K,
                      out, status);
   return hipGetLastError();
@@ -382,15 +493,25 @@ hipError_t launch_jacobi(const double* H, int K, double* W, double* evals, int m
   return hipGetLastError();
 }
 
-hipError_t launch_rotate(const double* veff, int64_t d, int Kp, int K, const double* M, int k,
-                         float* E, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_rotate, dim3(grid_for(d * k, 1024)), dim3(256), 0, s, veff, d, Kp, K, M, k,
-                     E, status);
-  return hipGetLastError();
+int rotate_blocks(int64_t d, int k) {
+  const int64_t R = kRotTile / k > 0 ? kRotTile / k : 1;
+  const int64_t nb = cdiv(d, R);
+  return (int)(nb < kRotMaxBlocks ? nb : kRotMaxBlocks);
 }
 
-hipError_t launch_sign_fix(float* E, int64_t d, int k, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_fix, dim3(k), dim3(256), 0, s, E, d, k, status);
+hipError_t launch_rotate(const float* V, int64_t d, int K, int32_t dtype, bool split,
+                         const float* col_scale, const double* M, int k, float* E, ColMax* part,
+                         int* flip, int* status, hipStream_t s) {
+  if (k < 1 || k > K || K > kMaxK) return hipErrorInvalidValue;
+  const int nb = rotate_blocks(d, k);
+  if (K * k <= 1024)
+    hipLaunchKernelGGL(k_rotate<1024>, dim3(nb), dim3(256), 0, s, V, d, K, (int)dtype,
+                       split ? 1 : 0, col_scale, M, k, E, part, status);
+  else
+    hipLaunchKernelGGL(k_rotate<kMaxK * kMaxK>, dim3(nb), dim3(256), 0, s, V, d, K, (int)dtype,
+                       split ? 1 : 0, col_scale, M, k, E, part, status);
+  hipLaunchKernelGGL(k_sign_decide, dim3(1), dim3(256), 0, s, part, nb, k, flip, status);
+  hipLaunchKernelGGL(k_flip, dim3(nb), dim3(256), 0, s, E, d, k, flip, status);
   return hipGetLastError();
 }
 

@@ -113,7 +113,7 @@ struct Plan {
   size_t fex = 0, fyb = 0, fflags = 0, fdummy = 0, fpart = 0;
   // offsets
   size_t ypart = 0;
-  size_t status = 0, vop = 0, veff = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
+  size_t status = 0, vop = 0, rotp = 0, flip = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
          a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
          sums = 0, cmax = 0, mean = 0, vprev = 0, chg = 0, su = 0, sw = 0, stmp = 0, sst = 0;
   size_t total = 0;
@@ -159,11 +159,13 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     p.total = c.off;
     return p;
   }
-  const int es_op = dtype == PPCA_F32 ? 4 : 2;
-  p.vop = c.take((size_t)p.Kp * p.dp * es_op * (p.split ? 2 : 1));
-  p.veff = c.take((size_t)d * p.Kp * sizeof(double));
   const size_t kk = (size_t)K * K * sizeof(double);
   if (op == PPCA_OP_RR) {
+    // the rotation reads V itself: no operand; per-workgroup column maxima
+    // of the sign rule (rotate_blocks grows as k shrinks the tile's rows,
+    // so K bounds every k <= K; at most 1024 workgroups, whatever d)
+    p.rotp = c.take((size_t)rotate_blocks(d, K) * K * sizeof(ColMax));
+    p.flip = c.take((size_t)K * sizeof(int));
     p.r = c.take(kk);
     p.rinv = c.take(kk);
     p.t = c.take(kk);
@@ -174,6 +176,8 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     p.total = c.off;
     return p;
   }
+  const int es_op = dtype == PPCA_F32 ? 4 : 2;
+  p.vop = c.take((size_t)p.Kp * p.dp * es_op * (p.split ? 2 : 1));
   int64_t pass_rows = n;
   if (op == PPCA_OP_OJA || op == PPCA_OP_EIGENGAME || op == PPCA_OP_STREAM) pass_rows = batch;
   if (op == PPCA_OP_PROJECT && batch > 0) pass_rows = batch;   // projection of a row window
@@ -364,14 +368,15 @@ int cholqr2(const float* A, float* V, int64_t d, int K, const Plan& p, void* ws,
 
 int make_operand(const ppca_matrix* X, const float* V, const Plan& p, void* ws, hipStream_t s) {
   HIP_TRY(launch_make_operand(V, X->d, p.K, p.Kp, p.dp, X->dtype, X->col_scale,
-                              at<void>(ws, p.vop), at<double>(ws, p.veff), p.split, s));
+                              at<void>(ws, p.vop), p.split, s));
   return PPCA_OK;
 }
 
-// B = V_eff^T V_eff (K x K f64)
-int operand_gram(const ppca_matrix* X, const Plan& p, void* ws, double* B, hipStream_t s) {
-  HIP_TRY(launch_gram(at<double>(ws, p.veff), true, X->d, p.K, p.Kp, at<double>(ws, p.gparts), B,
-                      at<int>(ws, p.status), s));
+// B = V_eff^T V_eff (K x K f64), V_eff the operand's values, recomputed from V
+int operand_gram(const ppca_matrix* X, const float* V, const Plan& p, void* ws, double* B,
+                 hipStream_t s) {
+  HIP_TRY(launch_operand_gram(V, X->d, p.K, X->dtype, p.split, X->col_scale,
+                              at<double>(ws, p.gparts), B, at<int>(ws, p.status), s));
   return PPCA_OK;
 }
 
@@ -412,10 +417,9 @@ int rayleigh_ritz_on(const ppca_matrix* X, int K, int k, const double* G, const 
   HIP_TRY(launch_jacobi(H, K, W, ev, 60, st, s));
   HIP_TRY(launch_copy_f64(ev, evals, k, s));
   if (E) {
-    RET_IF(make_operand(X, V, p, ws, s));
     HIP_TRY(launch_small_gemm(Ri, false, W, M, K, k, K, K, K, k, 1.0, st, s));
-    HIP_TRY(launch_rotate(at<double>(ws, p.veff), X->d, p.Kp, K, M, k, E, st, s));
-    HIP_TRY(launch_sign_fix(E, X->d, k, st, s));
+    HIP_TRY(launch_rotate(V, X->d, K, X->dtype, p.split, X->col_scale, M, k, E,
+                          at<ColMax>(ws, p.rotp), at<int>(ws, p.flip), st, s));
   }
   return finish(p, ws, s);
 }
@@ -731,7 +735,7 @@ int ppca_prime_power(const ppca_matrix* X, int32_t k, int32_t l, int32_t iters, 
   const int64_t kk = (int64_t)K * K;
   for (int t = 0; t < iters; ++t) {
     RET_IF(make_operand(X, V, p, ws, s));
-    if (b_hist) RET_IF(operand_gram(X, p, ws, b_hist + t * kk, s));
+    if (b_hist) RET_IF(operand_gram(X, V, p, ws, b_hist + t * kk, s));
     // G = Y^T Y is only formed when the caller asks for its history
     RET_IF(run_pass(X, p, ws, 0, X->n, Z, gram_hist ? G : nullptr,
                     gram_hist ? gram_hist + t * kk : nullptr, false, s));
@@ -856,7 +860,7 @@ int ppca_project_gram(const ppca_matrix* X, int32_t K, const float* V, double* G
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
   RET_IF(make_operand(X, V, p, ws, s));
-  RET_IF(operand_gram(X, p, ws, B, s));
+  RET_IF(operand_gram(X, V, p, ws, B, s));
   RET_IF(run_pass(X, p, ws, 0, X->n, nullptr, G, nullptr, true, s));
   return finish(p, ws, s);
 }
@@ -872,7 +876,7 @@ int ppca_project_gram_rows(const ppca_matrix* X, int32_t K, const float* V, int6
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_zero(at<int>(ws, p.status), 256, s));
   RET_IF(make_operand(X, V, p, ws, s));
-  RET_IF(operand_gram(X, p, ws, B, s));
+  RET_IF(operand_gram(X, V, p, ws, B, s));
   RET_IF(run_pass(X, p, ws, r0, nrows, nullptr, G, nullptr, true, s));
   return finish(p, ws, s);
 }

@@ -115,9 +115,8 @@ hipError_t launch_fused_pass(const PassDesc& p, const void* vop, int64_t dp, int
 // dense float64 kernels (k_dense.hip)
 // split: bf16 operand as hi = bf16(V) at vop and lo = bf16(V - hi) at
 // vop + Kp dp, V_eff = hi + lo (bf16 data only)
-hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp,
-                               int32_t dtype, const float* col_scale, void* vop,
-                               double* veff, bool split, hipStream_t s);
+hipError_t launch_make_operand(const float* V, int64_t d, int K, int Kp, int64_t dp, int32_t dtype,
+                               const float* col_scale, void* vop, bool split, hipStream_t s);
 // partial Grams of a (rows x K) matrix A (row stride lda); in_f64 selects the type
 int gram_parts(int64_t rows, int K);
 hipError_t launch_gram(const void* A, bool in_f64, int64_t rows, int K, int64_t lda,
@@ -133,9 +132,18 @@ hipError_t launch_small_gemm(const double* A, bool transA, const double* B, doub
                              int* status, hipStream_t s);
 hipError_t launch_jacobi(const double* H, int K, double* W, double* evals, int max_sweeps,
                          int* status, hipStream_t s);
-hipError_t launch_rotate(const double* veff, int64_t d, int Kp, int K, const double* M, int k,
-                         float* E, int* status, hipStream_t s);
-hipError_t launch_sign_fix(float* E, int64_t d, int k, int* status, hipStream_t s);
+// Per workgroup and column: the largest |E| entry (its value and row).
+struct ColMax {
+  float a, v;
+  int64_t j;
+};
+int rotate_blocks(int64_t d, int k);
+hipError_t launch_rotate(const float* V, int64_t d, int K, int32_t dtype, bool split,
+                         const float* col_scale, const double* M, int k, float* E, ColMax* part,
+                         int* flip, int* status, hipStream_t s);
+hipError_t launch_operand_gram(const float* V, int64_t d, int K, int32_t dtype, bool split,
+                               const float* col_scale, double* parts, double* out, int* status,
+                               hipStream_t s);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 

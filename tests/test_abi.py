@@ -103,16 +103,18 @@ def test_grouped_work_split_host_calls():
 
 def test_noalloc_rayleigh_ritz_host_checks():
     """The allocation-free Rayleigh-Ritz validates on the host before touching
-    the device: bad arguments, and a problem whose workspace exceeds the fixed
-    scratch, are rejected with no GPU call."""
+    the device (bad arguments are rejected with no GPU call), and its
+    workspace is bounded whatever n and d: the widest problems fit the fixed
+    scratch at the largest K."""
     from paper_2109_03709_amd import _lib
     L = _lib.lib()
-    assert _lib.NOALLOC_SCRATCH_BYTES == 16 << 20
+    assert _lib.NOALLOC_SCRATCH_BYTES == 4 << 20
     p = ctypes.c_void_p(256)
-    big = _lib._Matrix(16, 1000, 100_000, 100_000, _lib.F32, 0)
-    need = L.ppca_workspace_bytes(_lib.OP_RR, ctypes.byref(big), 128, 0)
-    assert need > _lib.NOALLOC_SCRATCH_BYTES
-    assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(big), 128, 8, p, p, p, p, p, None) == -6
+    for n, d in ((16, 64), (6654, 15_116_544), (1 << 40, 1 << 34)):
+        for dt in (_lib.F32, _lib.BF16):
+            m = _lib._Matrix(16, n, d, d, dt, 0)
+            need = L.ppca_workspace_bytes(_lib.OP_RR, ctypes.byref(m), 128, 0)
+            assert 0 < need <= 3 << 20, (n, d, dt, need)
     ok = _lib._Matrix(16, 1000, 64, 64, _lib.F32, 0)
     assert L.ppca_workspace_bytes(_lib.OP_RR, ctypes.byref(ok), 16, 0) < _lib.NOALLOC_SCRATCH_BYTES
     assert L.ppca_rayleigh_ritz_noalloc(ctypes.byref(ok), 0, 1, p, p, p, p, p, None) == -1
