@@ -1356,7 +1356,10 @@ __device__ inline bool xty_tile_split(int ntiles, int nsplit, int& tile, int& sp
 // Z partials, Z = X^T Y.  Workgroup (tile t, split s): the 256 columns
 // [256t, 256t+256) of X (64 per wave) against all Kp columns of Y over the
 // rows of split s, i.e. rows [s*rps, min(rows, (s+1)*rps)); k-step = 32 rows
-// (16 for f32).  Output: part[t][s][Kp][256] float32.
+// (16 for f32).  Output: part[t][s][Kp][256] float32; or, when the pass has
+// a single row split and a single chunk (zd not null), Z itself:
+// zd[j][c] = float(double(sum) * s_j) for j < d, c < K (s_j = 1 unless fp8),
+// the value the fixed-order reduction of one partial would give.
 // Each k-step's X rows (whole 512-byte row segments for bf16) and Y chunks go
 // straight to LDS with global_load_lds into four LDS stages, three of them in
 // flight while the MFMAs consume the fourth:
@@ -1370,7 +1373,8 @@ template <int NB, int DT>
 __global__ __launch_bounds__(256, 1) void k_xtyd(const uint8_t* x, int64_t n, int64_t d, int64_t ld,
                                                  int64_t rstart, int64_t rows, int64_t rps,
                                                  const uint8_t* yb, float* part, int ntiles,
-                                                 int nsplit, int accumulate) {
+                                                 int nsplit, int accumulate, float* zd, int K,
+                                                 const float* zscale, int* status) {
   constexpr int Kp = NB * 16;
   constexpr int TC = 256;
   constexpr int EB = DT == DT_F32 ? 4 : DT == DT_BF16 ? 2 : 1;   // bytes per X element
@@ -1543,6 +1547,30 @@ __global__ __launch_bounds__(256, 1) void k_xtyd(const uint8_t* x, int64_t n, in
   }
   wait_vmcnt<0>();
 
+  if (zd) {
+    // lane (a, g): acc[v][nb][u] is column c0 + wave*64 + 16g + 4u + v of X,
+    // column nb*16 + a of Y
+    bool bad = false;
+    const int64_t cb = c0 + wave * 64 + 16 * g;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int yc = nb * 16 + a;
+      if (yc >= K) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = cb + 4 * u + v;
+          if (j >= d) continue;
+          const float zf = zscale ? (float)((double)acc[v][nb][u] * (double)zscale[j])
+                                  : acc[v][nb][u];
+          if (!isfinite(zf)) bad = true;
+          zd[j * K + yc] = zf;
+        }
+    }
+    if (bad) set_status(status, PPCA_ERR_NONFINITE);
+    return;
+  }
   if (c0 + wave * 64 < d) {
     // lane (j = a, g): acc[v][nb][u] is tile column wave*64 + 16g + 4u + v,
     // Y column nb*16 + a
@@ -1700,7 +1728,13 @@ int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   if (ntile > 128) return 1;
   // columns per k-step: k_xvd 128 bytes of a row (f32 32, bf16 64), k_xv (fp8) 32
   const int64_t nk = cdiv(d, dtype == PPCA_BF16 ? 64 : 32);
-  int64_t target = std::min<int64_t>(16, std::min<int64_t>(kNumCU / ntile, nk));
+  // long rows (d in the millions for bf16): two workgroups per CU, up to 32
+  // splits of at least 64 k-steps each (measured at 1024 x 15.1M bf16: 256
+  // workgroups 4.6 TB/s, 512 5.8 TB/s, 1024 5.5 TB/s); shorter rows keep one
+  // per CU and at most 16 splits, so the partial sums stay small beside X
+  const bool long_rows = nk >= 2048;
+  const int64_t cap = long_rows ? 32 : 16, per_cu = long_rows ? 2 : 1;
+  int64_t target = std::min<int64_t>(cap, std::min<int64_t>(per_cu * kNumCU / ntile, nk));
   if (target < 2) return 1;
   const int64_t kper = cdiv(nk, target);
   return (int)cdiv(nk, kper);
@@ -1808,7 +1842,9 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
 }
 
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                      bool accumulate, hipStream_t s) {
+                      bool accumulate, float* Z, int K, int* status, hipStream_t s) {
+  if (Z && (b.nsplit != 1 || accumulate)) return hipErrorInvalidValue;
+  const float* zscale = p.dtype == PPCA_FP8_E4M3 ? p.col_scale : nullptr;
   if (rows <= 0) return hipSuccess;
   const int64_t rstart = (p.r0 + i0) % p.n;
   const int ntiles = xty_tiles(p.d, b.Kp);
@@ -1820,7 +1856,7 @@ hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d, p.ld,
                          rstart, rows, rps, (const uint8_t*)b.yb, b.part, ntiles, b.nsplit,
-                         accumulate ? 1 : 0);
+                         accumulate ? 1 : 0, Z, K, zscale, status);
     };
     if (p.dtype == PPCA_F32) go(k_xtyd<NB, DT_F32>);
     else if (p.dtype == PPCA_BF16) go(k_xtyd<NB, DT_BF16>);
@@ -1835,6 +1871,7 @@ hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* 
   int64_t zb = gram_only ? 0 : cdiv(d * K, 256);
   if (zb > 2048) zb = 2048;
   const int64_t gb = G ? cdiv((int64_t)K * K, 64) : 0;
+  if (zb + gb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_zg, dim3(zb + gb), dim3(256), 0, s, b.part, b.gpart, b.nsplit,
                      b.ngpart, b.Kp, d, K, col_scale, Z, G, G_copy, (int)zb, status);
   return hipGetLastError();

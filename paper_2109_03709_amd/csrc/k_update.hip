@@ -184,20 +184,26 @@ __global__ __launch_bounds__(kThreads) void k_sanger(float* __restrict__ V,
   }
 }
 
-// EigenGame, phase 1: grad = (2/b) Z R and per-block partial dots v_c . grad_c.
-// LDS: Rs [K][K] f64 | scr [kThreads] f64 | Zs [rb][K] f32.
-__global__ __launch_bounds__(kThreads) void k_eg_grad(const float* __restrict__ V,
-                                                      const float* __restrict__ Z,
-                                                      const double* __restrict__ G, int64_t d,
-                                                      int K, int b, double* __restrict__ grad,
-                                                      double* __restrict__ pdot, int* status) {
-  extern __shared__ double lds[];
-  const Lane L(K);
-  double* Rs = lds;
-  double* scr = lds + K * K;
-  float* Zs = reinterpret_cast<float*>(scr + kThreads);
+// EigenGame update in three passes over the rows of V and Z, none of which
+// stores the gradient or the unnormalised step (both are recomputed, with the
+// same arithmetic, from V, Z and G in every pass):
+//   k_eg_dots   per-block partial dots v_c . grad_c;
+//   k_eg_norms  vn = v + eta step(grad - (v . grad) v), per-block partial
+//               squared norms (the momentum buffer is read, not written);
+//   k_eg_apply  the same vn, V <- vn / |vn|, the momentum buffer, and (when
+//               vop is given) the next step's MFMA operand of the new V.
+// grad = (2/b) Z R with R_ii = 1, R_ic = -G_ic / G_ii (i < c), else 0.
+// LDS (dynamic): Rs [K][K] f64 | scr [kThreads] f64 | Zs [rb][K] f32.
+
+// Loads this thread's rows of V and the block's rows of Z, builds R, and
+// returns the gradient rows in gr (valid where L.act and the row is < d).
+// Returns false (in every thread) when the status word is set.
+__device__ inline bool eg_grad_rows(const float* __restrict__ V, const float* __restrict__ Z,
+                                    const double* __restrict__ G, int64_t d, int K, int b,
+                                    const Lane& L, double* Rs, float* Zs, const int* status,
+                                    float (&v)[kRowsPerThread], double (&gr)[kRowsPerThread]) {
   const int c = L.c;
-  float v[kRowsPerThread], z[kRowsPerThread];
+  float z[kRowsPerThread];
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t jc = clamp_row(L.row(q), d);
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_eg_grad(const float* __restrict__ 
   }
   const bool stop = status_set(status);
   __syncthreads();
-  if (stop) return;
+  if (stop) return false;
   double s[kRowsPerThread];
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) s[q] = 0.0;
@@ -237,42 +243,58 @@ __global__ __launch_bounds__(kThreads) void k_eg_grad(const float* __restrict__ 
     for (int q = 0; q < kRowsPerThread; ++q) s[q] = fma((double)Zs[L.lrow(q) * K + i], ri, s[q]);
   }
   const double sc = 2.0 / (double)b;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) gr[q] = sc * s[q];
+  return true;
+}
+
+// The step of momentum_step without writing the buffer.
+__device__ inline double momentum_peek(double g, double mu, int nesterov, const float* mom,
+                                       int64_t idx) {
+  if (mu == 0.0) return g;
+  const double buf = mu * (double)mom[idx] + g;
+  return nesterov ? g + mu * buf : buf;
+}
+
+__global__ __launch_bounds__(kThreads) void k_eg_dots(const float* __restrict__ V,
+                                                      const float* __restrict__ Z,
+                                                      const double* __restrict__ G, int64_t d,
+                                                      int K, int b, double* __restrict__ pdot,
+                                                      int* status) {
+  extern __shared__ double lds[];
+  const Lane L(K);
+  double* Rs = lds;
+  double* scr = lds + K * K;
+  float* Zs = reinterpret_cast<float*>(scr + kThreads);
+  float v[kRowsPerThread];
+  double gr[kRowsPerThread];
+  if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
   double dot = 0.0;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int64_t j = L.row(q);
-    if (L.act && j < d) {
-      const double gv = sc * s[q];
-      grad[j * K + c] = gv;
-      dot += (double)v[q] * gv;
-    }
-  }
+  for (int q = 0; q < kRowsPerThread; ++q)
+    if (L.act && L.row(q) < d) dot += (double)v[q] * gr[q];
   block_column_sum(dot, K, L, scr, pdot);
 }
 
-// EigenGame, phase 2: Riemannian projection, momentum, ascent step; partial norms.
-__global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ V,
-                                                      const double* __restrict__ grad,
-                                                      const double* __restrict__ pdot,
-                                                      const double* __restrict__ pdot_sum, int nblk,
-                                                      int64_t d, int K, double eta, double mu,
-                                                      int nesterov, float* __restrict__ mom,
-                                                      double* __restrict__ vnew,
-                                                      double* __restrict__ pnorm, int* status) {
+__global__ __launch_bounds__(kThreads) void k_eg_norms(const float* __restrict__ V,
+                                                       const float* __restrict__ Z,
+                                                       const double* __restrict__ G, int64_t d,
+                                                       int K, int b, const double* __restrict__ pdot,
+                                                       const double* __restrict__ pdot_sum,
+                                                       int nblk, double eta, double mu,
+                                                       int nesterov, const float* __restrict__ mom,
+                                                       double* __restrict__ pnorm, int* status) {
+  extern __shared__ double lds[];
   __shared__ double dots[kMaxK];
-  __shared__ double scr[kThreads];
   const Lane L(K);
-  const int c = L.c;
+  double* Rs = lds;
+  double* scr = lds + K * K;
+  float* Zs = reinterpret_cast<float*>(scr + kThreads);
   float v[kRowsPerThread];
   double gr[kRowsPerThread];
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int64_t jc = clamp_row(L.row(q), d);
-    v[q] = V[jc * K + c];
-    gr[q] = grad[jc * K + c];
-  }
+  if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
   column_sums(pdot, pdot_sum, nblk, K, L, scr, dots);
-  if (status_set(status)) return;
+  const int c = L.c;
   double sq = 0.0;
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
@@ -280,41 +302,62 @@ __global__ __launch_bounds__(kThreads) void k_eg_step(const float* __restrict__ 
     if (L.act && j < d) {
       const double vq = (double)v[q];
       const double gq = gr[q] - dots[c] * vq;
-      const double step = momentum_step(gq, mu, nesterov, mom, j * K + c);
-      const double vn = vq + eta * step;
-      vnew[j * K + c] = vn;
+      const double vn = vq + eta * momentum_peek(gq, mu, nesterov, mom, j * K + c);
       sq += vn * vn;
     }
   }
   block_column_sum(sq, K, L, scr, pnorm);
 }
 
-// EigenGame, phase 3: unit-norm columns.
-__global__ __launch_bounds__(kThreads) void k_eg_normalise(float* __restrict__ V,
-                                                           const double* __restrict__ vnew,
-                                                           const double* __restrict__ pnorm,
-                                                           const double* __restrict__ pnorm_sum,
-                                                           int nblk, int64_t d, int K,
-                                                           int* status) {
-  __shared__ double nrm[kMaxK];
-  __shared__ double scr[kThreads];
+__global__ __launch_bounds__(kThreads) void k_eg_apply(float* __restrict__ V,
+                                                       const float* __restrict__ Z,
+                                                       const double* __restrict__ G, int64_t d,
+                                                       int K, int b, const double* __restrict__ pdot,
+                                                       const double* __restrict__ pnorm,
+                                                       const double* __restrict__ sums, int nblk,
+                                                       double eta, double mu, int nesterov,
+                                                       float* __restrict__ mom, void* __restrict__ vop,
+                                                       int64_t dp, int dtype,
+                                                       const float* __restrict__ scale,
+                                                       int* status) {
+  extern __shared__ double lds[];
+  __shared__ double dots[kMaxK], nrm[kMaxK];
   const Lane L(K);
-  const int c = L.c;
-  double vn[kRowsPerThread];
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) vn[q] = vnew[clamp_row(L.row(q), d) * K + c];
-  column_sums(pnorm, pnorm_sum, nblk, K, L, scr, nrm);
-  if (status_set(status)) return;
+  double* Rs = lds;
+  double* scr = lds + K * K;
+  float* Zs = reinterpret_cast<float*>(scr + kThreads);
+  float v[kRowsPerThread];
+  double gr[kRowsPerThread];
+  if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
+  column_sums(pdot, sums, nblk, K, L, scr, dots);
+  column_sums(pnorm, sums ? sums + K : nullptr, nblk, K, L, scr, nrm);
   if (threadIdx.x < K) {
     const double s = nrm[threadIdx.x];
     if (!(s > 0.0) || !isfinite(s)) set_status(status, PPCA_ERR_NONFINITE);
   }
   if (!L.act) return;
+  const int c = L.c;
   const double ic = 1.0 / sqrt(nrm[c]);
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t j = L.row(q);
-    if (j < d) V[j * K + c] = (float)(vn[q] * ic);
+    if (j < d) {
+      const double vq = (double)v[q];
+      const double gq = gr[q] - dots[c] * vq;
+      const double vn = vq + eta * momentum_step(gq, mu, nesterov, mom, j * K + c);
+      const float vf = (float)(vn * ic);
+      V[j * K + c] = vf;
+      if (vop) {
+        // the operand entry k_make_operand would write for this V
+        const int64_t e = (int64_t)c * dp + j;
+        if (dtype == PPCA_F32) {
+          reinterpret_cast<float*>(vop)[e] = vf;
+        } else {
+          const float sv = dtype == PPCA_FP8_E4M3 ? scale[j] * vf : vf;
+          reinterpret_cast<uint16_t*>(vop)[e] = (uint16_t)f32_to_bf16_bits(sv);
+        }
+      }
+    }
   }
 }
 
@@ -338,33 +381,34 @@ hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64
 }
 
 size_t eigengame_scratch_doubles(int64_t d, int K) {
-  return (size_t)(2 * d * K + 2 * (int64_t)eigengame_blocks(d, K) * K + 2 * K);
+  return (size_t)(2 * (int64_t)eigengame_blocks(d, K) * K + 2 * K);
 }
 
-// scratch layout: grad [d*K] | vnew [d*K] | pdot [nblk*K] | pnorm [nblk*K] |
-// pdot sums [K] | pnorm sums [K]   (float64)
+// scratch layout: pdot [nblk*K] | pnorm [nblk*K] | pdot sums [K] | pnorm sums [K]
+// (float64).  vop (optional): the operand of the new V, [Kp][dp] (its padding
+// is left as it is: zero from the operand built before the first step).
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
-                                   double* scratch, int* status, hipStream_t s) {
+                                   double* scratch, void* vop, int64_t dp, int32_t dtype,
+                                   const float* col_scale, int* status, hipStream_t s) {
   const int nblk = eigengame_blocks(d, K);
-  double* grad = scratch;
-  double* vnew = grad + d * K;
-  double* pdot = vnew + d * K;
+  double* pdot = scratch;
   double* pnorm = pdot + (int64_t)nblk * K;
   double* sums = pnorm + (int64_t)nblk * K;
   const bool two_level = nblk > kDirectPartials;
   const size_t lds = ((size_t)K * K + kThreads) * sizeof(double) +
                      (size_t)block_rows(K) * K * sizeof(float);
-  hipLaunchKernelGGL(k_eg_grad, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, grad, pdot,
+  hipLaunchKernelGGL(k_eg_dots, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot,
                      status);
   if (two_level) hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pdot, nblk, K, sums);
-  hipLaunchKernelGGL(k_eg_step, dim3(nblk), dim3(kThreads), 0, s, V, grad, pdot,
-                     two_level ? (const double*)sums : nullptr, nblk, d, K, eta, mu, nesterov, mom,
-                     vnew, pnorm, status);
+  hipLaunchKernelGGL(k_eg_norms, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot,
+                     two_level ? (const double*)sums : nullptr, nblk, eta, mu, nesterov,
+                     (const float*)mom, pnorm, status);
   if (two_level)
     hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pnorm, nblk, K, sums + K);
-  hipLaunchKernelGGL(k_eg_normalise, dim3(nblk), dim3(kThreads), 0, s, V, vnew, pnorm,
-                     two_level ? (const double*)(sums + K) : nullptr, nblk, d, K, status);
+  hipLaunchKernelGGL(k_eg_apply, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot, pnorm,
+                     two_level ? (const double*)sums : nullptr, nblk, eta, mu, nesterov, mom, vop,
+                     dp, (int)dtype, col_scale, status);
   return hipGetLastError();
 }
 

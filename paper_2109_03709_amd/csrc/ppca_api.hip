@@ -336,16 +336,21 @@ int run_pass(const ppca_matrix* X, const Plan& p, void* ws, int64_t r0, int64_t 
     return PPCA_OK;
   }
   const int64_t chunk = (p.rows_cap < nrows) ? p.rows_cap : nrows;
+  // one row split and one chunk: the X^T Y kernel writes Z itself
+  const bool direct_z = !gram_only && p.nsplit == 1 && nrows <= chunk;
+  int* st = at<int>(ws, p.status);
   for (int64_t i0 = 0; i0 < nrows; i0 += chunk) {
     const int64_t rows = (nrows - i0) < chunk ? (nrows - i0) : chunk;
     HIP_TRY(timed(gram_only ? 4 : 0, s, [&] {
       return launch_xv(pd, b, i0, rows, !gram_only, G != nullptr, i0 > 0, s);
     }));
     if (!gram_only)
-      HIP_TRY(timed(1, s, [&] { return launch_xty(pd, b, i0, rows, i0 > 0, s); }));
+      HIP_TRY(timed(1, s, [&] {
+        return launch_xty(pd, b, i0, rows, i0 > 0, direct_z ? Z : nullptr, p.K, st, s);
+      }));
   }
   HIP_TRY(launch_reduce_zg(b, X->d, p.K, X->dtype == PPCA_FP8_E4M3 ? X->col_scale : nullptr, Z, G,
-                           Gcopy, gram_only, at<int>(ws, p.status), s));
+                           Gcopy, gram_only || direct_z, st, s));
   return PPCA_OK;
 }
 
@@ -677,12 +682,15 @@ int prime_sgd(bool eigengame, const ppca_matrix* X, int32_t k, int32_t l, const 
   for (int64_t t = 0; t < q->steps; ++t) {
     const int64_t gstep = q->start_step + t;
     const int64_t r0 = (int64_t)(((__int128)gstep * b) % X->n);
-    RET_IF(make_operand(X, V, p, ws, s));
+    // the EigenGame update writes the next step's operand itself
+    if (!eigengame || t == 0) RET_IF(make_operand(X, V, p, ws, s));
     RET_IF(run_pass(X, p, ws, r0, b, Z, G, nullptr, false, s));
     const double eta = q->t0 > 0.0 ? q->eta0 / (1.0 + (double)gstep / q->t0) : q->eta0;
     if (eigengame) {
+      void* next_op = t + 1 < q->steps ? at<void>(ws, p.vop) : nullptr;
       HIP_TRY(launch_eigengame_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
-                                      q->mom_buf, at<double>(ws, p.egs), st, s));
+                                      q->mom_buf, at<double>(ws, p.egs), next_op, p.dp, X->dtype,
+                                      X->col_scale, st, s));
     } else {
       HIP_TRY(launch_sanger_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
                                    q->mom_buf, st, s));

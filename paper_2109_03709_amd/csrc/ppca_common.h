@@ -86,8 +86,10 @@ int xv_grid(int32_t dtype, int Kp, int64_t d, int64_t rows_cap);   // workgroups
 int xvg_grid(int64_t rows_cap);    // workgroups of the two-term projection pass
 hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
                      bool want_y, bool want_g, bool accumulate, hipStream_t s);
+// Z (d x K) non-null: written directly by the pass (single row split, single
+// chunk); else partials for launch_reduce_zg.
 hipError_t launch_xty(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t rows,
-                      bool accumulate, hipStream_t s);
+                      bool accumulate, float* Z, int K, int* status, hipStream_t s);
 hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* col_scale,
                             float* Z, double* G, double* G_copy, bool gram_only, int* status,
                             hipStream_t s);
@@ -170,7 +172,8 @@ int eigengame_blocks(int64_t d, int K);   // blocks of the EigenGame update kern
 size_t eigengame_scratch_doubles(int64_t d, int K);
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
-                                   double* scratch, int* status, hipStream_t s);
+                                   double* scratch, void* vop, int64_t dp, int32_t dtype,
+                                   const float* col_scale, int* status, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t count, hipStream_t s);
 
 // data preparation (k_prep.hip)
