@@ -7,6 +7,9 @@
 //                                        Riemannian projection, step, unit-norm columns.
 //  Optional momentum (training setup of Sec. 5): buf <- mu buf + g,
 //  step = g + mu buf (Nesterov) or buf.
+//
+// Both updates also write the MFMA operand of the new V (when asked), so the
+// next minibatch pass needs no operand kernel of its own.
 #include "ppca_common.h"
 
 namespace ppca {
@@ -15,17 +18,19 @@ namespace {
 
 // Thread layout shared by the update kernels: with ng = 256 / K row groups,
 // thread t < ng * K owns column c = t % K and row group g = t / K; a block covers
-// rb = ng * kRowsPerThread rows and the thread handles rows g + ng * q of it.
+// rb = ng * RPT rows and the thread handles rows g + ng * q of it (q < RPT).
+// RPT (rows per thread) is 8 for large d and drops to 4, 2 or 1 when d is
+// small, so that the update still runs on about 256 workgroups.
 // The 256 - ng * K spare threads (K not a power of two) load like group ng - 1
 // but store nothing.  All loads are unconditional (row indices clamped to d - 1)
 // so that they issue back to back.  Reductions over rows run in a fixed order
 // (rows of a thread, then groups, then blocks): results do not depend on timing.
 constexpr int kThreads = 256;
-constexpr int kRowsPerThread = 8;
+constexpr int kMaxRPT = 8;
 
 __host__ __device__ inline int row_groups(int K) { return kThreads / K; }
-__host__ __device__ inline int block_rows(int K) { return row_groups(K) * kRowsPerThread; }
 
+template <int RPT>
 struct Lane {
   int c, g, ng, rb;
   bool act;
@@ -33,7 +38,7 @@ struct Lane {
   __device__ Lane(int K) {
     const int t = threadIdx.x;
     ng = row_groups(K);
-    rb = ng * kRowsPerThread;
+    rb = ng * RPT;
     c = t % K;
     g = min(t / K, ng - 1);
     act = t < ng * K;
@@ -57,21 +62,35 @@ __device__ inline double momentum_step(double g, double mu, int nesterov, float*
   return nesterov ? g + mu * buf : buf;
 }
 
-// out[c] = sum over w < nblk of part[w * K + c], for c < K (LDS result; scr
+// The operand entry (c, j) of the new value vf of V: what k_make_operand
+// writes for it (float32 data: vf; else bf16 of vf, of s_j vf for fp8).
+__device__ inline void write_operand(void* vop, int64_t dp, int dtype, const float* scale, int c,
+                                     int64_t j, float vf) {
+  const int64_t e = (int64_t)c * dp + j;
+  if (dtype == PPCA_F32) {
+    reinterpret_cast<float*>(vop)[e] = vf;
+  } else {
+    const float sv = dtype == PPCA_FP8_E4M3 ? scale[j] * vf : vf;
+    reinterpret_cast<uint16_t*>(vop)[e] = (uint16_t)f32_to_bf16_bits(sv);
+  }
+}
+
+// out[c] = sum over w < nblk of part[w * ld + c], for c < K (LDS result; scr
 // holds kThreads doubles).  Loads go out eight at a time.
-__device__ inline void sum_partials(const double* __restrict__ part, int nblk, int K,
-                                    const Lane& L, double* scr, double* out) {
+template <int RPT>
+__device__ inline void sum_partials(const double* __restrict__ part, int nblk, int K, int64_t ld,
+                                    const Lane<RPT>& L, double* scr, double* out) {
   const int t = threadIdx.x;
   double s = 0.0;
   int w = L.g;
   for (; w + 7 * L.ng < nblk; w += 8 * L.ng) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + u * L.ng) * K + L.c];
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + u * L.ng) * ld + L.c];
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += v[u];
   }
-  for (; w < nblk; w += L.ng) s += part[(int64_t)w * K + L.c];
+  for (; w < nblk; w += L.ng) s += part[(int64_t)w * ld + L.c];
   if (L.act) scr[t] = s;
   __syncthreads();
   if (t < K) {
@@ -83,16 +102,25 @@ __device__ inline void sum_partials(const double* __restrict__ part, int nblk, i
 }
 
 // Many blocks (large d): the column sums of the per-block partials are formed
-// once, by K workgroups (workgroup c: thread t adds blocks t, t + 256, ... in
-// order, then a fixed tree), instead of by every block of the next kernel.
+// once, by one workgroup per column (thread t adds blocks t, t + 256, ... in
+// order, eight loads in flight, then a fixed tree), instead of by every block
+// of the next kernel.
 constexpr int kDirectPartials = 64;   // up to this many blocks each block sums them itself
 
 __global__ __launch_bounds__(kThreads) void k_sum_cols(const double* __restrict__ part, int nblk,
-                                                       int K, double* __restrict__ out) {
+                                                       int ncol, double* __restrict__ out) {
   __shared__ double sh[kThreads];
   const int c = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int w = t; w < nblk; w += kThreads) s += part[(int64_t)w * K + c];
+  int w = t;
+  for (; w + 7 * kThreads < nblk; w += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + u * kThreads) * ncol + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; w < nblk; w += kThreads) s += part[(int64_t)w * ncol + c];
   sh[t] = s;
   __syncthreads();
   for (int h = kThreads / 2; h > 0; h >>= 1) {
@@ -102,49 +130,43 @@ __global__ __launch_bounds__(kThreads) void k_sum_cols(const double* __restrict_
   if (t == 0) out[c] = sh[0];
 }
 
-// the column sums of part: from the precomputed sums when there are many
-// blocks, else summed here (LDS result)
-__device__ inline void column_sums(const double* __restrict__ part,
-                                   const double* __restrict__ pre, int nblk, int K,
-                                   const Lane& L, double* scr, double* out) {
-  if (pre) {
-    if ((int)threadIdx.x < K) out[threadIdx.x] = pre[threadIdx.x];
-    __syncthreads();
-  } else {
-    sum_partials(part, nblk, K, L, scr, out);
-  }
-}
-
-// Per-block column sums of the thread values (fixed order) -> part[blk * K + c].
-__device__ inline void block_column_sum(double val, int K, const Lane& L, double* scr,
+// Per-block column sums of the thread values (fixed order) -> part[c]
+// (part already offset to this block's row of partials).  Starts with a
+// barrier, so that calls may follow one another on the same scr.
+template <int RPT>
+__device__ inline void block_column_sum(double val, int K, const Lane<RPT>& L, double* scr,
                                         double* __restrict__ part) {
   const int t = threadIdx.x;
+  __syncthreads();
   if (L.act) scr[t] = val;
   __syncthreads();
   if (t < K) {
     double s = 0.0;
     for (int g = 0; g < L.ng; ++g) s += scr[g * K + t];
-    part[(int64_t)blockIdx.x * K + t] = s;
+    part[t] = s;
   }
 }
 
 // Sanger / generalised Oja step.  LDS: Gs [K][K] f64 (upper triangle of G, zeros
 // below) | Vs [rb][K] f32 (the block's rows of V).
+template <int RPT>
 __global__ __launch_bounds__(kThreads) void k_sanger(float* __restrict__ V,
                                                      const float* __restrict__ Z,
                                                      const double* __restrict__ G, int64_t d,
                                                      int K, int b, double eta, double mu,
                                                      int nesterov, float* __restrict__ mom,
+                                                     void* __restrict__ vop, int64_t dp, int dtype,
+                                                     const float* __restrict__ scale,
                                                      int* status) {
   extern __shared__ double lds[];
   double* Gs = lds;
-  const Lane L(K);
+  const Lane<RPT> L(K);
   float* Vs = reinterpret_cast<float*>(lds + K * K);
   const int c = L.c;
-  double z[kRowsPerThread];
-  float v[kRowsPerThread];
+  double z[RPT];
+  float v[RPT];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     const int64_t jc = clamp_row(L.row(q), d);
     z[q] = (double)Z[jc * K + c];
     v[q] = V[jc * K + c];
@@ -162,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void k_sanger(float* __restrict__ V,
   }
   if (L.act) {
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) Vs[L.lrow(q) * K + c] = v[q];
+    for (int q = 0; q < RPT; ++q) Vs[L.lrow(q) * K + c] = v[q];
   }
   const bool stop = status_set(status);
   __syncthreads();
@@ -171,41 +193,49 @@ __global__ __launch_bounds__(kThreads) void k_sanger(float* __restrict__ V,
   for (int i = 0; i < K; ++i) {
     const double gi = Gs[i * K + c];
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q)
-      z[q] = fma(-(double)Vs[L.lrow(q) * K + i], gi, z[q]);
+    for (int q = 0; q < RPT; ++q) z[q] = fma(-(double)Vs[L.lrow(q) * K + i], gi, z[q]);
   }
   const double inv_b = 1.0 / (double)b;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     const int64_t j = L.row(q);
     if (j >= d) continue;
     const double step = momentum_step(z[q] * inv_b, mu, nesterov, mom, j * K + c);
-    V[j * K + c] = (float)((double)v[q] + eta * step);
+    const float vf = (float)((double)v[q] + eta * step);
+    V[j * K + c] = vf;
+    if (vop) write_operand(vop, dp, dtype, scale, c, j, vf);
   }
 }
 
-// EigenGame update in three passes over the rows of V and Z, none of which
-// stores the gradient or the unnormalised step (both are recomputed, with the
-// same arithmetic, from V, Z and G in every pass):
-//   k_eg_dots   per-block partial dots v_c . grad_c;
-//   k_eg_norms  vn = v + eta step(grad - (v . grad) v), per-block partial
-//               squared norms (the momentum buffer is read, not written);
-//   k_eg_apply  the same vn, V <- vn / |vn|, the momentum buffer, and (when
-//               vop is given) the next step's MFMA operand of the new V.
+// EigenGame update in two passes over the rows of V and Z; neither stores the
+// gradient (it is recomputed, with the same arithmetic, from V, Z and G):
+//   k_eg_sums   per block and column: S_vv = sum v^2, S_gg = sum g^2,
+//               S_mm = sum m^2, S_vg = sum v g, S_vm = sum v m, S_gm = sum g m
+//               (g the gradient, m the momentum buffer, zero without momentum);
+//   k_eg_apply  dot = S_vg; the step is vn = a v + p g + r m with
+//               a = 1 - eta alpha dot, p = eta alpha, r = eta beta, where
+//               alpha, beta = 1, mu (heavy ball), 1 + mu, mu^2 (Nesterov),
+//               beta = 0 without momentum; so
+//               |vn|^2 = a^2 S_vv + p^2 S_gg + r^2 S_mm + 2ap S_vg + 2ar S_vm
+//                        + 2pr S_gm,
+//               then V <- vn / |vn|, the momentum buffer, and (when vop is
+//               given) the next step's operand.
 // grad = (2/b) Z R with R_ii = 1, R_ic = -G_ic / G_ii (i < c), else 0.
 // LDS (dynamic): Rs [K][K] f64 | scr [kThreads] f64 | Zs [rb][K] f32.
+constexpr int kEgSums = 6;
 
 // Loads this thread's rows of V and the block's rows of Z, builds R, and
 // returns the gradient rows in gr (valid where L.act and the row is < d).
 // Returns false (in every thread) when the status word is set.
+template <int RPT>
 __device__ inline bool eg_grad_rows(const float* __restrict__ V, const float* __restrict__ Z,
                                     const double* __restrict__ G, int64_t d, int K, int b,
-                                    const Lane& L, double* Rs, float* Zs, const int* status,
-                                    float (&v)[kRowsPerThread], double (&gr)[kRowsPerThread]) {
+                                    const Lane<RPT>& L, double* Rs, float* Zs, const int* status,
+                                    float (&v)[RPT], double (&gr)[RPT]) {
   const int c = L.c;
-  float z[kRowsPerThread];
+  float z[RPT];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     const int64_t jc = clamp_row(L.row(q), d);
     z[q] = Z[jc * K + c];
     v[q] = V[jc * K + c];
@@ -229,91 +259,65 @@ __device__ inline bool eg_grad_rows(const float* __restrict__ V, const float* __
   }
   if (L.act) {
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) Zs[L.lrow(q) * K + c] = L.row(q) < d ? z[q] : 0.f;
+    for (int q = 0; q < RPT; ++q) Zs[L.lrow(q) * K + c] = L.row(q) < d ? z[q] : 0.f;
   }
   const bool stop = status_set(status);
   __syncthreads();
   if (stop) return false;
-  double s[kRowsPerThread];
+  double s[RPT];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) s[q] = 0.0;
+  for (int q = 0; q < RPT; ++q) s[q] = 0.0;
   for (int i = 0; i < K; ++i) {
     const double ri = Rs[i * K + c];
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) s[q] = fma((double)Zs[L.lrow(q) * K + i], ri, s[q]);
+    for (int q = 0; q < RPT; ++q) s[q] = fma((double)Zs[L.lrow(q) * K + i], ri, s[q]);
   }
   const double sc = 2.0 / (double)b;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) gr[q] = sc * s[q];
+  for (int q = 0; q < RPT; ++q) gr[q] = sc * s[q];
   return true;
 }
 
-// The step of momentum_step without writing the buffer.
-__device__ inline double momentum_peek(double g, double mu, int nesterov, const float* mom,
-                                       int64_t idx) {
-  if (mu == 0.0) return g;
-  const double buf = mu * (double)mom[idx] + g;
-  return nesterov ? g + mu * buf : buf;
-}
-
-__global__ __launch_bounds__(kThreads) void k_eg_dots(const float* __restrict__ V,
+// part: [nblk][kEgSums][K]; mom null without momentum
+template <int RPT>
+__global__ __launch_bounds__(kThreads) void k_eg_sums(const float* __restrict__ V,
                                                       const float* __restrict__ Z,
                                                       const double* __restrict__ G, int64_t d,
-                                                      int K, int b, double* __restrict__ pdot,
-                                                      int* status) {
+                                                      int K, int b, const float* __restrict__ mom,
+                                                      double* __restrict__ part, int* status) {
   extern __shared__ double lds[];
-  const Lane L(K);
+  const Lane<RPT> L(K);
   double* Rs = lds;
   double* scr = lds + K * K;
   float* Zs = reinterpret_cast<float*>(scr + kThreads);
-  float v[kRowsPerThread];
-  double gr[kRowsPerThread];
+  float v[RPT];
+  double gr[RPT];
   if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
-  double dot = 0.0;
+  double s[kEgSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q)
-    if (L.act && L.row(q) < d) dot += (double)v[q] * gr[q];
-  block_column_sum(dot, K, L, scr, pdot);
-}
-
-__global__ __launch_bounds__(kThreads) void k_eg_norms(const float* __restrict__ V,
-                                                       const float* __restrict__ Z,
-                                                       const double* __restrict__ G, int64_t d,
-                                                       int K, int b, const double* __restrict__ pdot,
-                                                       const double* __restrict__ pdot_sum,
-                                                       int nblk, double eta, double mu,
-                                                       int nesterov, const float* __restrict__ mom,
-                                                       double* __restrict__ pnorm, int* status) {
-  extern __shared__ double lds[];
-  __shared__ double dots[kMaxK];
-  const Lane L(K);
-  double* Rs = lds;
-  double* scr = lds + K * K;
-  float* Zs = reinterpret_cast<float*>(scr + kThreads);
-  float v[kRowsPerThread];
-  double gr[kRowsPerThread];
-  if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
-  column_sums(pdot, pdot_sum, nblk, K, L, scr, dots);
-  const int c = L.c;
-  double sq = 0.0;
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     const int64_t j = L.row(q);
     if (L.act && j < d) {
-      const double vq = (double)v[q];
-      const double gq = gr[q] - dots[c] * vq;
-      const double vn = vq + eta * momentum_peek(gq, mu, nesterov, mom, j * K + c);
-      sq += vn * vn;
+      const double vq = (double)v[q], gq = gr[q];
+      const double mq = mom ? (double)mom[j * K + L.c] : 0.0;
+      s[0] = fma(vq, vq, s[0]);
+      s[1] = fma(gq, gq, s[1]);
+      s[2] = fma(mq, mq, s[2]);
+      s[3] = fma(vq, gq, s[3]);
+      s[4] = fma(vq, mq, s[4]);
+      s[5] = fma(gq, mq, s[5]);
     }
   }
-  block_column_sum(sq, K, L, scr, pnorm);
+  double* pb = part + (int64_t)blockIdx.x * kEgSums * K;
+#pragma unroll
+  for (int u = 0; u < kEgSums; ++u) block_column_sum(s[u], K, L, scr, pb + u * K);
 }
 
+template <int RPT>
 __global__ __launch_bounds__(kThreads) void k_eg_apply(float* __restrict__ V,
                                                        const float* __restrict__ Z,
                                                        const double* __restrict__ G, int64_t d,
-                                                       int K, int b, const double* __restrict__ pdot,
-                                                       const double* __restrict__ pnorm,
+                                                       int K, int b, const double* __restrict__ part,
                                                        const double* __restrict__ sums, int nblk,
                                                        double eta, double mu, int nesterov,
                                                        float* __restrict__ mom, void* __restrict__ vop,
@@ -321,42 +325,49 @@ __global__ __launch_bounds__(kThreads) void k_eg_apply(float* __restrict__ V,
                                                        const float* __restrict__ scale,
                                                        int* status) {
   extern __shared__ double lds[];
-  __shared__ double dots[kMaxK], nrm[kMaxK];
-  const Lane L(K);
+  __shared__ double S[kEgSums][kMaxK];
+  __shared__ double coef[2][kMaxK];   // dot and 1 / |vn| per column
+  const Lane<RPT> L(K);
   double* Rs = lds;
   double* scr = lds + K * K;
   float* Zs = reinterpret_cast<float*>(scr + kThreads);
-  float v[kRowsPerThread];
-  double gr[kRowsPerThread];
+  float v[RPT];
+  double gr[RPT];
   if (!eg_grad_rows(V, Z, G, d, K, b, L, Rs, Zs, status, v, gr)) return;
-  column_sums(pdot, sums, nblk, K, L, scr, dots);
-  column_sums(pnorm, sums ? sums + K : nullptr, nblk, K, L, scr, nrm);
-  if (threadIdx.x < K) {
-    const double s = nrm[threadIdx.x];
-    if (!(s > 0.0) || !isfinite(s)) set_status(status, PPCA_ERR_NONFINITE);
+  if (sums) {
+    for (int e = threadIdx.x; e < kEgSums * K; e += kThreads) S[e / K][e % K] = sums[e];
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int u = 0; u < kEgSums; ++u)
+      sum_partials(part + u * K, nblk, K, (int64_t)kEgSums * K, L, scr, S[u]);
   }
+  const double alpha = nesterov ? 1.0 + mu : 1.0;
+  const double beta = mu != 0.0 ? (nesterov ? mu * mu : mu) : 0.0;
+  if ((int)threadIdx.x < K) {
+    const int cc = threadIdx.x;
+    const double dot = S[3][cc];
+    const double a = 1.0 - eta * alpha * dot, p = eta * alpha, r = eta * beta;
+    const double n2 = a * a * S[0][cc] + p * p * S[1][cc] + r * r * S[2][cc] +
+                      2.0 * a * p * S[3][cc] + 2.0 * a * r * S[4][cc] + 2.0 * p * r * S[5][cc];
+    if (!(n2 > 0.0) || !isfinite(n2)) set_status(status, PPCA_ERR_NONFINITE);
+    coef[0][cc] = dot;
+    coef[1][cc] = 1.0 / sqrt(n2);
+  }
+  __syncthreads();
   if (!L.act) return;
   const int c = L.c;
-  const double ic = 1.0 / sqrt(nrm[c]);
+  const double dot = coef[0][c], ic = coef[1][c];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     const int64_t j = L.row(q);
     if (j < d) {
       const double vq = (double)v[q];
-      const double gq = gr[q] - dots[c] * vq;
+      const double gq = gr[q] - dot * vq;
       const double vn = vq + eta * momentum_step(gq, mu, nesterov, mom, j * K + c);
       const float vf = (float)(vn * ic);
       V[j * K + c] = vf;
-      if (vop) {
-        // the operand entry k_make_operand would write for this V
-        const int64_t e = (int64_t)c * dp + j;
-        if (dtype == PPCA_F32) {
-          reinterpret_cast<float*>(vop)[e] = vf;
-        } else {
-          const float sv = dtype == PPCA_FP8_E4M3 ? scale[j] * vf : vf;
-          reinterpret_cast<uint16_t*>(vop)[e] = (uint16_t)f32_to_bf16_bits(sv);
-        }
-      }
+      if (vop) write_operand(vop, dp, dtype, scale, c, j, vf);
     }
   }
 }
@@ -367,49 +378,77 @@ __global__ void k_copy_f32(const float* __restrict__ s, float* __restrict__ d, i
     d[e] = s[e];
 }
 
+// Rows per thread: 8, or fewer while that leaves fewer than 256 blocks.
+int update_rpt(int64_t d, int K) {
+  const int64_t ng = row_groups(K);
+  int rpt = kMaxRPT;
+  while (rpt > 1 && cdiv(d, ng * rpt) < 256) rpt /= 2;
+  return rpt;
+}
+
+template <typename F>
+hipError_t dispatch_rpt(int rpt, F&& f) {
+  switch (rpt) {
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
-int eigengame_blocks(int64_t d, int K) { return (int)cdiv(d, block_rows(K)); }
+int eigengame_blocks(int64_t d, int K) {
+  return (int)cdiv(d, (int64_t)row_groups(K) * update_rpt(d, K));
+}
 
 hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K, int b,
-                                double eta, double mu, int nesterov, float* mom, int* status,
+                                double eta, double mu, int nesterov, float* mom, void* vop,
+                                int64_t dp, int32_t dtype, const float* col_scale, int* status,
                                 hipStream_t s) {
-  const size_t lds = (size_t)K * K * sizeof(double) + (size_t)block_rows(K) * K * sizeof(float);
-  hipLaunchKernelGGL(k_sanger, dim3((unsigned)cdiv(d, block_rows(K))), dim3(kThreads), lds, s, V,
-                     Z, G, d, K, b, eta, mu, nesterov, mom, status);
-  return hipGetLastError();
+  const int rpt = update_rpt(d, K);
+  const int64_t rb = (int64_t)row_groups(K) * rpt;
+  const size_t lds = (size_t)K * K * sizeof(double) + (size_t)rb * K * sizeof(float);
+  return dispatch_rpt(rpt, [&](auto rc) -> hipError_t {
+    constexpr int RPT = decltype(rc)::value;
+    hipLaunchKernelGGL(k_sanger<RPT>, dim3((unsigned)cdiv(d, rb)), dim3(kThreads), lds, s, V, Z, G,
+                       d, K, b, eta, mu, nesterov, mom, vop, dp, (int)dtype, col_scale, status);
+    return hipGetLastError();
+  });
 }
 
 size_t eigengame_scratch_doubles(int64_t d, int K) {
-  return (size_t)(2 * (int64_t)eigengame_blocks(d, K) * K + 2 * K);
+  return (size_t)((int64_t)kEgSums * eigengame_blocks(d, K) * K + kEgSums * K);
 }
 
-// scratch layout: pdot [nblk*K] | pnorm [nblk*K] | pdot sums [K] | pnorm sums [K]
-// (float64).  vop (optional): the operand of the new V, [Kp][dp] (its padding
-// is left as it is: zero from the operand built before the first step).
+// scratch layout: partials [nblk][6][K] | their column sums [6][K] (float64).
+// vop (optional): the operand of the new V, [Kp][dp] (its padding is left as
+// it is: zero from the operand built before the first step).
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
                                    int b, double eta, double mu, int nesterov, float* mom,
                                    double* scratch, void* vop, int64_t dp, int32_t dtype,
                                    const float* col_scale, int* status, hipStream_t s) {
-  const int nblk = eigengame_blocks(d, K);
-  double* pdot = scratch;
-  double* pnorm = pdot + (int64_t)nblk * K;
-  double* sums = pnorm + (int64_t)nblk * K;
+  const int rpt = update_rpt(d, K);
+  const int64_t rb = (int64_t)row_groups(K) * rpt;
+  const int nblk = (int)cdiv(d, rb);
+  double* part = scratch;
+  double* sums = part + (int64_t)nblk * kEgSums * K;
   const bool two_level = nblk > kDirectPartials;
-  const size_t lds = ((size_t)K * K + kThreads) * sizeof(double) +
-                     (size_t)block_rows(K) * K * sizeof(float);
-  hipLaunchKernelGGL(k_eg_dots, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot,
-                     status);
-  if (two_level) hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pdot, nblk, K, sums);
-  hipLaunchKernelGGL(k_eg_norms, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot,
-                     two_level ? (const double*)sums : nullptr, nblk, eta, mu, nesterov,
-                     (const float*)mom, pnorm, status);
-  if (two_level)
-    hipLaunchKernelGGL(k_sum_cols, dim3(K), dim3(kThreads), 0, s, pnorm, nblk, K, sums + K);
-  hipLaunchKernelGGL(k_eg_apply, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, pdot, pnorm,
-                     two_level ? (const double*)sums : nullptr, nblk, eta, mu, nesterov, mom, vop,
-                     dp, (int)dtype, col_scale, status);
-  return hipGetLastError();
+  const size_t lds = ((size_t)K * K + kThreads) * sizeof(double) + (size_t)rb * K * sizeof(float);
+  const float* mom_in = mu != 0.0 ? mom : nullptr;
+  return dispatch_rpt(rpt, [&](auto rc) -> hipError_t {
+    constexpr int RPT = decltype(rc)::value;
+    hipLaunchKernelGGL(k_eg_sums<RPT>, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b,
+                       mom_in, part, status);
+    if (two_level)
+      hipLaunchKernelGGL(k_sum_cols, dim3(kEgSums * K), dim3(kThreads), 0, s, part, nblk,
+                         kEgSums * K, sums);
+    hipLaunchKernelGGL(k_eg_apply<RPT>, dim3(nblk), dim3(kThreads), lds, s, V, Z, G, d, K, b, part,
+                       two_level ? (const double*)sums : nullptr, nblk, eta, mu, nesterov, mom,
+                       vop, dp, (int)dtype, col_scale, status);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t count, hipStream_t s) {

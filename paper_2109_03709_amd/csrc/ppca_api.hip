@@ -682,18 +682,18 @@ int prime_sgd(bool eigengame, const ppca_matrix* X, int32_t k, int32_t l, const 
   for (int64_t t = 0; t < q->steps; ++t) {
     const int64_t gstep = q->start_step + t;
     const int64_t r0 = (int64_t)(((__int128)gstep * b) % X->n);
-    // the EigenGame update writes the next step's operand itself
-    if (!eigengame || t == 0) RET_IF(make_operand(X, V, p, ws, s));
+    // each update writes the next step's operand itself
+    if (t == 0) RET_IF(make_operand(X, V, p, ws, s));
     RET_IF(run_pass(X, p, ws, r0, b, Z, G, nullptr, false, s));
     const double eta = q->t0 > 0.0 ? q->eta0 / (1.0 + (double)gstep / q->t0) : q->eta0;
+    void* next_op = t + 1 < q->steps ? at<void>(ws, p.vop) : nullptr;
     if (eigengame) {
-      void* next_op = t + 1 < q->steps ? at<void>(ws, p.vop) : nullptr;
       HIP_TRY(launch_eigengame_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
                                       q->mom_buf, at<double>(ws, p.egs), next_op, p.dp, X->dtype,
                                       X->col_scale, st, s));
     } else {
       HIP_TRY(launch_sanger_update(V, Z, G, X->d, K, (int)b, eta, q->momentum, q->nesterov,
-                                   q->mom_buf, st, s));
+                                   q->mom_buf, next_op, p.dp, X->dtype, X->col_scale, st, s));
     }
     if (q->snapshot_every > 0 && (t + 1) % q->snapshot_every == 0) {
       const int64_t slot = (t + 1) / q->snapshot_every - 1;

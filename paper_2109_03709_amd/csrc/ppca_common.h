@@ -165,9 +165,10 @@ hipError_t launch_seq_step(const float* V, int64_t d, int K, int i, const float*
 hipError_t launch_seq_store(float* V, int64_t d, int K, int i, const float* u, hipStream_t s);
 
 // minibatch updates (k_update.hip)
-hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K,
-                                int b, double eta, double mu, int nesterov, float* mom,
-                                int* status, hipStream_t s);
+hipError_t launch_sanger_update(float* V, const float* Z, const double* G, int64_t d, int K, int b,
+                                double eta, double mu, int nesterov, float* mom, void* vop,
+                                int64_t dp, int32_t dtype, const float* col_scale, int* status,
+                                hipStream_t s);
 int eigengame_blocks(int64_t d, int K);   // blocks of the EigenGame update kernels
 size_t eigengame_scratch_doubles(int64_t d, int K);
 hipError_t launch_eigengame_update(float* V, const float* Z, const double* G, int64_t d, int K,
