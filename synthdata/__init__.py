@@ -182,7 +182,7 @@ def make_lowrank_device(n: int, d: int, r: int, spec: str, seed: int, *, device=
                         chunk_rows: int = 32):
     """Centred data with an exact low-rank covariance, for d >> n (where a
     d x d Haar basis cannot be formed): X = A_w diag(sqrt(lam)) B^T with B a
-    d x r block with orthonormal columns (CholeskyQR2 of a Gaussian block, in
+    d x r block with orthonormal columns (Householder QR of a Gaussian block,
     float64) and A_w an n x r Gaussian block, centred and whitened so that
     A_w^T A_w / n = I.  Then X^T X / n = B diag(lam) B^T exactly: the top r
     eigenpairs are (lam_i, b_i) and the rest are zero.  X is written straight
@@ -194,16 +194,9 @@ def make_lowrank_device(n: int, d: int, r: int, spec: str, seed: int, *, device=
     lam = spectrum(spec, r)
     g = torch.Generator(device=device)
     g.manual_seed(seed)
-    b = torch.randn((d, r), generator=g, device=device, dtype=torch.float32)
-    for _ in range(2):                               # CholeskyQR2 in float64
-        gram = torch.zeros((r, r), dtype=torch.float64, device=device)
-        for c0 in range(0, d, 1 << 20):
-            bc = b[c0:c0 + (1 << 20)].double()
-            gram += bc.T @ bc
-        ell = torch.linalg.cholesky(gram)
-        linv_t = torch.linalg.inv(ell).T
-        for c0 in range(0, d, 1 << 20):
-            b[c0:c0 + (1 << 20)] = (b[c0:c0 + (1 << 20)].double() @ linv_t).float()
+    # orthonormal columns: Householder QR of a Gaussian block (library routine, float64)
+    b = torch.linalg.qr(torch.randn((d, r), generator=g, device=device, dtype=torch.float64),
+                        mode="reduced")[0].to(torch.float32)
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     a = _whiten_rows(rng.standard_normal((n, r)))   # centred, A^T A / n = I
     a = a * np.sqrt(lam)[None, :]
