@@ -89,6 +89,15 @@ def test_wide_projection_and_rayleigh_ritz(wide):
     G, Bm = P.project_gram(data, K, vd)
     th, e_ref, _ = O.rayleigh_ritz(G.cpu().numpy(), Bm.cpu().numpy(), veff, N, 4)
     assert np.max(O.rel_eig_error(ev.cpu().numpy(), th)) < 1e-8
+    # Ritz vectors with their signs: the rotation spans 1024 workgroups here,
+    # so the sign rule's column maxima are merged across workgroups; every
+    # column must match the oracle's sign-normalised one in every row
+    e = E.cpu().numpy().astype(np.float64)
+    signed = np.sum(e * e_ref, axis=0) / (np.linalg.norm(e, axis=0) *
+                                          np.linalg.norm(e_ref, axis=0))
+    assert np.min(signed) > 1 - 1e-9
+    piv = np.argmax(np.abs(e), axis=0)
+    assert np.all(e[piv, np.arange(4)] > 0)
     e_lam = np.max(O.rel_eig_error(ev.cpu().numpy(), lam[:4]))
     s_b = sin_theta(E.cpu().numpy(), b[:, :4])
     print(f"[wide] Ritz values vs lam {e_lam:.2e}, Ritz vectors vs B {s_b:.2e}", flush=True)
