@@ -380,6 +380,35 @@ def test_momentum_and_resume():
     assert np.max(np.abs(va.cpu().numpy() - v_or)) < 1e-4 * np.max(np.abs(v_or))
 
 
+@pytest.mark.parametrize("nesterov", [True, False])
+def test_eigengame_momentum_and_resume(nesterov):
+    """EigenGame with momentum 0.9 (Nesterov and heavy ball): six steps match
+    the oracle's, two calls of three equal one of six (V and the buffer
+    bitwise), and the run without momentum lies well outside the tolerance
+    (so a dropped or mis-weighted momentum term would fail)."""
+    n, d, k, l, b = 8000, 128, 4, 4, 1000
+    p = make_problem(n, d, "paper-exp", seed=19, mode="exact")
+    data, xs, _ = device_data((p.x / math.sqrt(1000.0)).astype(np.float32), F32)
+    v0 = torch.from_numpy(gaussian_block(d, k + l, 13, np.float32)).cuda()
+    kw = dict(batch=b, eta0=0.05, t0=0.0, momentum=0.9, nesterov=nesterov)
+    va, ma = v0.clone(), torch.zeros_like(v0)
+    P().prime_eigengame(data, k, l, va, steps=6, mom_buf=ma, **kw)
+    vb, mb = v0.clone(), torch.zeros_like(v0)
+    P().prime_eigengame(data, k, l, vb, steps=3, mom_buf=mb, **kw)
+    P().prime_eigengame(data, k, l, vb, steps=3, mom_buf=mb, start_step=3,
+                        orthonormalise_start=False, **kw)
+    vc = v0.clone()
+    P().prime_eigengame(data, k, l, vc, steps=6, batch=b, eta0=0.05, t0=0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(va, vb) and torch.equal(ma, mb)
+    v_or, m_or = O.prime_eigengame(xs, v0.cpu().numpy().astype(np.float64), batch=b, steps=6,
+                                   eta0=0.05, t0=0.0, momentum=0.9, nesterov=nesterov)
+    err = np.max(np.abs(va.cpu().numpy() - v_or))
+    assert err < 1e-4
+    assert np.max(np.abs(ma.cpu().numpy() - m_or)) < 1e-4 * max(1.0, np.max(np.abs(m_or)))
+    assert np.max(np.abs(vc.cpu().numpy() - v_or)) > 100 * 1e-4
+
+
 def test_snapshots():
     n, d, K, b = 4000, 64, 8, 500
     p = make_problem(n, d, "exp0.9", seed=10, mode="exact")
