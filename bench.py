@@ -237,6 +237,10 @@ def main():
            "prep_ms": round(prep_ms, 2),
            "roofline": roofline}
 
+    # the read ceiling of this GPU in the streaming kernels' access pattern
+    # (no arithmetic): plain vector loads and the power pass's LDS-DMA
+    # pipeline with 128 (as k_xvy), 256 and 512 bytes of a row per step
+    out["read_probe"] = read_probe_rates(P, X, torch)
     if not a.no_tta:
         out["time_to_1e-3"] = time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch)
         out["next_steps"] = tenth_and_eps_stop(P, X, V, v0, lam, q, k, l, iters, dev, torch)
@@ -295,6 +299,24 @@ def measured_traffic(n, d, K, storage, iters, fused):
     except (OSError, KeyError, ValueError):
         pass
     return out or None
+
+
+def read_probe_rates(P, X, torch, reps=3):
+    """GB/s of ppca_read_probe over the stored X (HIP events on the launch
+    stream, average of `reps` launches after one untimed)."""
+    sink = torch.zeros(1024, dtype=torch.int32, device=X.x.device)
+    nbytes = X.n * X.x.stride(0) * X.x.element_size()
+    out = {}
+    for name, mode, seg in (("vector_loads", 0, 128), ("dma_128B_segments", 1, 128),
+                            ("dma_256B_segments", 1, 256), ("dma_512B_segments", 1, 512)):
+        P.read_probe(X, mode, seg, sink)
+        P.set_kernel_timing(True)
+        for _ in range(reps):
+            P.read_probe(X, mode, seg, sink)
+        nl, ms = P.kernel_stats(5)
+        P.set_kernel_timing(False)
+        out[name + "_GBs"] = round(nbytes / (ms / nl * 1e-3) / 1e9, 1)
+    return out
 
 
 def _timed(torch, fn, reps=3):

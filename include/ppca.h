@@ -350,11 +350,29 @@ const char* ppca_strerror(int status);
  * kernel: 0 = X V' pass (ppca_xv), 1 = X^T Y / Gram pass (ppca_xty),
  * 2 = fused grouped pass (power and projection passes of the grouped calls,
  * eager mode only), 3 = single-read power pass (ppca_set_fused_pass),
- * 4 = projection pass (ppca_project_gram, ppca_project_gram_rows).
+ * 4 = projection pass (ppca_project_gram, ppca_project_gram_rows),
+ * 5 = streaming-read probe (ppca_read_probe).
  * ppca_kernel_stats returns the number of launches and the total ms since
  * the last reset.  Not thread safe; meant for benchmarks. */
 void ppca_set_kernel_timing(int32_t enable);
 int  ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Streaming-read probe, a measurement aid (not a step of the method): reads
+ * every byte of the stored X (rows [0, n), ld * element-size bytes each)
+ * exactly once and does no arithmetic on it, so that the streaming kernels'
+ * rates can be set against what this GPU reads in their access pattern.
+ * mode 0: plain 16-byte vector loads striding over the matrix;
+ * mode 1: the LDS-DMA pipeline of the power pass (three 32 KB LDS stages,
+ *         two in flight) walking tiles of 32768 / seg_bytes rows seg_bytes of
+ *         every row per step; seg_bytes = 128, 256 or 512.
+ * sink: device uint32 array of at least sink_len entries, written with the
+ * XOR of the 32-bit words each workgroup read (so the reads are kept; the
+ * XOR over the whole array is the XOR of all words read).  sink_len must be
+ * at least 1024 (mode 0) or 256 (mode 1), else PPCA_ERR_ARG; bad mode or
+ * seg_bytes: PPCA_ERR_ARG; X as in the other calls (PPCA_ERR_ALIGN, _DTYPE).
+ * Synchronises the stream; timed as kernel 5 when kernel timing is on. */
+int ppca_read_probe(const ppca_matrix* X, int32_t mode, int32_t seg_bytes, uint32_t* sink,
+                    int64_t sink_len, void* stream);
 
 /* Tuning knob of the streaming passes: rows per chunk (0 = whole pass in
  * one launch pair).  Chunks bound the size of the Y staging buffer and keep

@@ -28,7 +28,7 @@ EXPORTS = [
     "ppca_prime_power_grouped", "ppca_rayleigh_ritz_grouped", "ppca_grouped_workspace_bytes",
     "ppca_grouped_workspace_bytes_for", "ppca_set_group_item_bytes", "ppca_tune_group_items",
     "ppca_rayleigh_ritz_noalloc", "ppca_set_fused_pass", "ppca_prime_power_eps",
-    "ppca_prime_power_seq", "ppca_project_gram_rows",
+    "ppca_prime_power_seq", "ppca_project_gram_rows", "ppca_read_probe",
 ]
 NOALLOC_SCRATCH_BYTES = 4 << 20
 GROUP_MAX_D, GROUP_MAX_K, GROUP_GRAPH = 768, 64, 1
@@ -83,6 +83,7 @@ def lib():
         L.ppca_prime_power_seq.argtypes = [mp, i32, i32, dbl, i32, vp, ctypes.POINTER(i32), vp,
                                            sz, vp]
         L.ppca_project_gram_rows.argtypes = [mp, i32, vp, i64, i64, vp, vp, vp, sz, vp]
+        L.ppca_read_probe.argtypes = [mp, i32, i32, vp, i64, vp]
         L.ppca_prime_eigengame.argtypes = [mp, i32, i32, sp, vp, vp, sz, vp]
         L.ppca_stream_pass.argtypes = [mp, i32, vp, i64, i64, vp, vp, vp, sz, vp]
         L.ppca_project_gram.argtypes = [mp, i32, vp, vp, vp, vp, sz, vp]
@@ -356,6 +357,19 @@ def project_gram_rows(X: Data, K: int, V: torch.Tensor, r0: int, nrows: int, ws=
                                         _ptr(ws), ws.numel(), _stream())
     _check(code, "ppca_project_gram_rows")
     return G, B
+
+
+def read_probe(X: Data, mode: int, seg_bytes: int = 128, sink=None) -> torch.Tensor:
+    """Streaming-read probe over the stored X (mode 0: vector loads; mode 1:
+    the power pass's LDS-DMA pattern with seg_bytes of a row per step).
+    Returns the per-workgroup XOR sink (uint32 viewed as int32)."""
+    if sink is None:
+        sink = torch.zeros(1024, dtype=torch.int32, device=X.x.device)
+    m = X.as_c()
+    code = lib().ppca_read_probe(ctypes.byref(m), mode, seg_bytes, _ptr(sink), sink.numel(),
+                                 _stream())
+    _check(code, "ppca_read_probe")
+    return sink
 
 
 def ppca(X: Data, V: torch.Tensor, k: int, rows: tuple[int, int] | None = None):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libppca.so")
-SOURCES = ["ppca_api.hip", "k_stream.hip", "k_dense.hip", "k_update.hip", "k_prep.hip", "k_group.hip", "k_fused.hip", "k_seq.hip"]
+SOURCES = ["ppca_api.hip", "k_stream.hip", "k_dense.hip", "k_update.hip", "k_prep.hip", "k_group.hip", "k_fused.hip", "k_seq.hip", "k_probe.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

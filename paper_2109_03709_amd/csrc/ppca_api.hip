@@ -34,7 +34,7 @@ struct KStat {
   int64_t launches = 0;
   double ms = 0.0;
 };
-KStat g_stats[5];
+KStat g_stats[6];
 struct Pending {
   hipEvent_t a, b;
   int kernel;
@@ -1100,10 +1100,26 @@ void ppca_set_kernel_timing(int32_t enable) {
 }
 
 int ppca_kernel_stats(int32_t kernel, int64_t* launches, double* total_ms) {
-  if (kernel < 0 || kernel > 4) return PPCA_ERR_ARG;
+  if (kernel < 0 || kernel > 5) return PPCA_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (launches) *launches = g_stats[kernel].launches;
   if (total_ms) *total_ms = g_stats[kernel].ms;
+  return PPCA_OK;
+}
+
+int ppca_read_probe(const ppca_matrix* X, int32_t mode, int32_t seg_bytes, uint32_t* sink,
+                    int64_t sink_len, void* stream) {
+  RET_IF(check_matrix(X));
+  if (mode != 0 && mode != 1) return PPCA_ERR_ARG;
+  if (mode == 1 && seg_bytes != 128 && seg_bytes != 256 && seg_bytes != 512) return PPCA_ERR_ARG;
+  if (!sink || sink_len < probe_grid(mode)) return PPCA_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t row_bytes = X->ld * elem_size(X->dtype);
+  HIP_TRY(timed(5, s, [&] {
+    return launch_read_probe(X->x, X->n, row_bytes, mode, seg_bytes, sink, s);
+  }));
+  if (hipStreamSynchronize(s) != hipSuccess) return PPCA_ERR_HIP;
+  if (g_timing) resolve_timings();
   return PPCA_OK;
 }
 

@@ -94,6 +94,11 @@ hipError_t launch_reduce_zg(const StreamBufs& b, int64_t d, int K, const float* 
                             float* Z, double* G, double* G_copy, bool gram_only, int* status,
                             hipStream_t s);
 
+// streaming-read probe (k_probe.hip): workgroups of a mode, and its launch
+int probe_grid(int32_t mode);
+hipError_t launch_read_probe(const void* x, int64_t n, int64_t row_bytes, int32_t mode,
+                             int32_t seg, uint32_t* sink, hipStream_t s);
+
 // single-read power pass (k_fused.hip): bf16 data, Kp a multiple of 32 up to
 // 128, d <= 8192; clusters of C = fused_cluster(d) workgroups on one XCD
 // (a cooperative launch of 256 workgroups, one per CU)

@@ -106,13 +106,16 @@ def test_fused_power_iterates_match_two_kernel():
     assert sin_theta(a[:, :k], b[:, :k]) < 2e-2
 
 
+@pytest.mark.parametrize("n", [140_001, 2_000_000])
 @pytest.mark.parametrize("dtype", [BF16, FP8, F32])
-def test_exact_arithmetic_stream_and_projection(dtype):
-    """Exact inputs at 140,001 rows, d = 300 (partial chunk), K = 64: Z of the
-    power step's pass (single-read kernel and two-kernel pass), Z and G of a
-    pass with G, and the projection's G and B all equal the float64 values
-    bit for bit."""
-    n, d, K = 140_001, 300, 64
+def test_exact_arithmetic_stream_and_projection(dtype, n):
+    """Exact inputs at 140,001 and 2,000,000 rows (the row counts where the
+    256-row power-pass tiles and the persistent projection run), d = 300
+    (partial chunk), K = 64: Z of the power step's pass (single-read kernel and
+    two-kernel pass), Z and G of a pass with G, and the projection's G and B
+    all equal the float64 values bit for bit.  At 2M rows |Z| <= 4M in halves
+    (8M units < 2^24), so every float32 partial sum stays exact."""
+    d, K = 300, 64
     print(f"exact arithmetic: dtype {dtype} n {n} d {d} K {K}", flush=True)
     data, scale = exact_codes(n, d, dtype, seed=5 + dtype)
     v = exact_directions(d, K, seed=6)
