@@ -1728,12 +1728,15 @@ int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   if (ntile > 128) return 1;
   // columns per k-step: k_xvd 128 bytes of a row (f32 32, bf16 64), k_xv (fp8) 32
   const int64_t nk = cdiv(d, dtype == PPCA_BF16 ? 64 : 32);
-  // long rows (d in the millions for bf16): two workgroups per CU, up to 32
-  // splits of at least 64 k-steps each (measured at 1024 x 15.1M bf16: 256
-  // workgroups 4.6 TB/s, 512 5.8 TB/s, 1024 5.5 TB/s); shorter rows keep one
-  // per CU and at most 16 splits, so the partial sums stay small beside X
+  // long rows (d in the millions for bf16): up to 32 splits of at least 64
+  // k-steps each, aiming at six workgroups per CU (measured at 1024 x 15.1M
+  // bf16, 16 row tiles: 256 workgroups 4.6 TB/s, 512 5.8 TB/s, 1024 5.5 TB/s;
+  // at 6654 x 1,048,576, 104 tiles, the two-term projection took 5.07 / 4.60
+  // / 4.37 ms with 4 / 7 / 14 splits; at 6654 x 15.1M it reads 4.3 TB/s with
+  // either split count); shorter rows keep one per CU and at most 16
+  // splits, so the partial sums stay small beside X
   const bool long_rows = nk >= 2048;
-  const int64_t cap = long_rows ? 32 : 16, per_cu = long_rows ? 2 : 1;
+  const int64_t cap = long_rows ? 32 : 16, per_cu = long_rows ? 6 : 1;
   int64_t target = std::min<int64_t>(cap, std::min<int64_t>(per_cu * kNumCU / ntile, nk));
   if (target < 2) return 1;
   const int64_t kper = cdiv(nk, target);
