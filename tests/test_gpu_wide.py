@@ -103,3 +103,43 @@ def test_wide_projection_and_rayleigh_ritz(wide):
     print(f"[wide] Ritz values vs lam {e_lam:.2e}, Ritz vectors vs B {s_b:.2e}", flush=True)
     assert e_lam < 1e-3
     assert s_b < 5e-3
+
+
+def test_wide_eigengame_momentum_matches_oracle(wide):
+    """Nesterov momentum at d = 262,144: the update's six column sums (with the
+    momentum buffer) go through the two-level reduction over 1024 blocks; four
+    steps against the oracle's own loop on the same rows and operand."""
+    P, data, xs, lam, b = wide
+    v0 = gaussian_block(D, K, 94, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    mom = torch.zeros_like(V)
+    P.prime_eigengame(data, 4, 4, V, batch=B, steps=4, eta0=0.2, momentum=0.9, nesterov=True,
+                      mom_buf=mom)
+    torch.cuda.synchronize()
+    hook = lambda u: operand_basis(u.astype(np.float32), BF16, None)
+    v, m = O.prime_eigengame(xs, v0.astype(np.float64), batch=B, steps=4, eta0=0.2, t0=0.0,
+                             momentum=0.9, nesterov=True, operand=hook)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    err = trajectory_error(V.cpu().numpy(), v, v_start)
+    merr = float(np.linalg.norm(mom.cpu().numpy() - m) / np.linalg.norm(m))
+    print(f"[wide] EigenGame + Nesterov trajectory error {err:.2e}, buffer {merr:.2e}", flush=True)
+    assert err < TRAJ_REL
+    assert merr < TRAJ_REL
+
+
+def test_wide_oja_matches_oracle(wide):
+    """Minibatch Sanger/Oja at d = 262,144 (eight rows per thread in the
+    update, the operand written by the update): four steps against the
+    oracle's loop on the same rows and operand."""
+    P, data, xs, lam, b = wide
+    v0 = gaussian_block(D, K, 95, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    P.prime_oja(data, 4, 4, V, batch=B, steps=4, eta0=0.5, t0=1000.0)
+    torch.cuda.synchronize()
+    hook = lambda u: operand_basis(u.astype(np.float32), BF16, None)
+    v, _ = O.prime_oja(xs, v0.astype(np.float64), batch=B, steps=4, eta0=0.5, t0=1000.0,
+                       operand=hook)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    err = trajectory_error(V.cpu().numpy(), v, v_start)
+    print(f"[wide] Oja trajectory error {err:.2e}", flush=True)
+    assert err < TRAJ_REL
