@@ -409,6 +409,26 @@ def test_eigengame_momentum_and_resume(nesterov):
     assert np.max(np.abs(vc.cpu().numpy() - v_or)) > 100 * 1e-4
 
 
+@pytest.mark.parametrize("method", ["oja", "eigengame"])
+def test_minibatch_at_the_largest_k(method):
+    """K = PPCA_MAX_K = 128 (k = l = 64): the update kernels then hold the K x K
+    matrix built from G in 128 KB of LDS; two steps against the oracle."""
+    n, d, k, l, b = 4096, 256, 64, 64, 1024
+    p = make_problem(n, d, "exp0.9", seed=31, mode="exact")
+    data, xs, _ = device_data(p.x, F32)
+    v0 = gaussian_block(d, k + l, 32, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    fn, ofn = ((P().prime_oja, O.prime_oja) if method == "oja"
+               else (P().prime_eigengame, O.prime_eigengame))
+    fn(data, k, l, V, batch=b, steps=2, eta0=0.2, t0=0.0)
+    torch.cuda.synchronize()
+    v, _ = ofn(xs, v0.astype(np.float64), batch=b, steps=2, eta0=0.2, t0=0.0)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    err = trajectory_error(V.cpu().numpy(), v, v_start)
+    print(f"{method} K = 128: trajectory error {err:.2e}", flush=True)
+    assert err < 1e-4
+
+
 def test_snapshots():
     n, d, K, b = 4000, 64, 8, 500
     p = make_problem(n, d, "exp0.9", seed=10, mode="exact")
