@@ -143,3 +143,36 @@ def test_wide_oja_matches_oracle(wide):
     err = trajectory_error(V.cpu().numpy(), v, v_start)
     print(f"[wide] Oja trajectory error {err:.2e}", flush=True)
     assert err < TRAJ_REL
+
+
+def test_wide_ragged_width():
+    """Long rows that end inside a 16-byte chunk (d = 262,150 in rows of
+    262,152): the column-split minibatch pass and the two-term projection mask
+    the tail; one EigenGame step and the Gram against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03709_amd as P
+    n, d, ld, k = 512, 262_150, 262_152, 8
+    # structured rows (a low-rank matrix, viewed at the ragged width): on
+    # isotropic rows the bf16 rounding of Y adds up like the signal and alone
+    # reaches the 2^-9 bound
+    buf, _, _ = make_lowrank_device(n, ld, 16, "exp0.9", seed=96)
+    data = P.Data(buf[:, :d], P.BF16)
+    xs = stored_values(host(buf[:, :d].contiguous()), BF16, None)
+    v0 = gaussian_block(d, k, 97, np.float32)
+    V = torch.from_numpy(v0.copy()).cuda()
+    P.prime_eigengame(data, 4, 4, V, batch=256, steps=2, eta0=0.5)
+    G, Bm = P.project_gram(data, k, V)
+    torch.cuda.synchronize()
+    hook = lambda u: operand_basis(u.astype(np.float32), BF16, None)
+    v_start = O.cholqr2(v0.astype(np.float64))[0]
+    v = oracle_replay("eigengame", lambda t: xs[O.minibatch_rows(n, 256, t)], v_start, range(2),
+                      256, 0.5, 0.0, hook)
+    err = trajectory_error(V.cpu().numpy(), v, v_start)
+    vg = V.cpu().numpy()
+    g_ref, b_ref = O.project_gram(xs, projection_basis(vg, BF16, None))
+    print(f"[wide] ragged d: EigenGame {err:.2e} of the motion, Gram {gram_err(G.cpu().numpy(), g_ref):.2e}",
+          flush=True)
+    assert err < TRAJ_REL
+    assert gram_err(G.cpu().numpy(), g_ref) < 4e-3
+    assert np.allclose(Bm.cpu().numpy(), b_ref, rtol=1e-12, atol=1e-12 * np.abs(b_ref).max())
