@@ -99,12 +99,12 @@ def main():
     if a.workload == "eigengame-wide-bf16":
         return main_wide(a)
     if a.workload == "power-f32":
-        # configuration 2's block-power priming: 1M x 1024 float32, lambda_i =
+        # block-power priming of 1M x 1024 float32 data, lambda_i =
         # i^-1.2 + 1e-4, k = l = 32, 20 iterations, then the pPCA step
         a.n, a.d, a.k, a.l, a.iters = 1_000_000, 1024, 32, 32, 20
         a.storage, a.spectrum, a.seed = "f32", "pow1.2+1e-4", 1002
     elif a.workload == "power-f32-small":
-        # configuration 1: 10,000 x 256 float32 (10 MB, resident in the
+        # the small float32 case: 10,000 x 256 (10 MB, resident in the
         # last-level cache), lambda_i = 0.9^i, k = l = 16, 10 iterations
         a.n, a.d, a.k, a.l, a.iters = 10_000, 256, 16, 16, 10
         a.storage, a.spectrum, a.seed = "f32", "exp0.9", 1001
@@ -250,7 +250,7 @@ def main():
     # pipeline with 128 (as k_xvy), 256 and 512 bytes of a row per step
     out["read_probe"] = read_probe_rates(P, X, torch)
     if not a.no_tta:
-        # plain float32 power at configuration 2's spectrum converges at about
+        # plain float32 power at the i^-1.2 spectrum (K = 32) converges at about
         # 0.93 per iteration (about 94 iterations to 1e-3): a longer cap there
         cap = 160 if a.workload == "power-f32" else 80
         out["time_to_1e-3"] = time_to_accuracy(P, X, Xf, v0, lam, k, l, iters, dev, torch,

@@ -26,8 +26,8 @@ from synthdata import gaussian_block, make_problem   # noqa: E402
 SAMPLE_ROWS = 50_000
 GRID = (1.0, 1e-1, 1e-2, 1e-3)
 SNAPSHOTS = 10
-# configuration 2 (Oja, float32 data) and configuration 4 (EigenGame, fp8 data;
-# the sample is used in float64)
+# Oja on 1M x 1024 float32 data and EigenGame on 8M x 2048 fp8 data (its
+# fp8 storage is not emulated: the sample is used in float64)
 CONFIGS = {
     "oja-f32": dict(n=1_000_000, d=1024, spectrum="pow1.2+1e-4", k=32, l=32, batch=1024,
                     epochs=1.0, t0=1000.0, seed=1002, rule="oja"),
