@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
   constexpr int YR = 16 / EB;                          // rows per Y chunk (8 / 4)
   constexpr int YTB = WGR * Kp * EB;                   // Y tile bytes
   constexpr int YHB = YTB / 2;                         // half tile (rows [0, WGR/2) in st0)
-  static_assert(YHB <= STB, "a Y half tile fits a stage");
+  static_assert(PART || YHB <= STB, "a Y half tile fits a stage");   // partials skip LDS
   static_assert(2 * DPS < 64, "vmcnt range");
   __shared__ __attribute__((aligned(16))) uint8_t st0[STB];
   __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
@@ -1722,9 +1722,22 @@ constexpr int xv_stages(int dt, int nb, int mw) { return 6; }
 // kernel runs on a few CUs, so the k-steps are split over up to 16
 // workgroups per tile (at most 256 in all, every split at least one k-step)
 // and a second kernel sums the float32 partials.  1 = no split.
+// Row tiles of the column-split pass: 128 rows (two 16-row blocks per wave)
+// when the rows are long (2048+ k-steps) and the data goes through the
+// LDS-DMA kernel, else 64.  Each tile re-reads its split's slice of V' (for
+// the two-term projection as many bytes as the tile's X), so taller tiles
+// cut that traffic: measured at 6654 x 4M bf16 the two-term projection took
+// 18.5 / 16.4 / 17.0 ms with 64 / 128 / 256-row tiles, the minibatch pass at
+// 1024 x 15.1M 5.31 / 5.18 / 6.41 ms (256-row tiles leave too few
+// workgroups).  Short rows keep 64-row tiles and more workgroups.
+int split_rows(int32_t dtype, int64_t d) {
+  const int64_t nk = cdiv(d, dtype == PPCA_BF16 ? 64 : 32);
+  return (nk >= 2048 && dtype != PPCA_FP8_E4M3) ? 128 : 64;
+}
+
 int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   if (xv_mw(dtype, Kp, rows_cap) != 1) return 1;
-  const int64_t ntile = cdiv(rows_cap, 64);
+  const int64_t ntile = cdiv(rows_cap, split_rows(dtype, d));
   if (ntile > 128) return 1;
   // columns per k-step: k_xvd 128 bytes of a row (f32 32, bf16 64), k_xv (fp8) 32
   const int64_t nk = cdiv(d, dtype == PPCA_BF16 ? 64 : 32);
@@ -1772,7 +1785,8 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
     // fp8 data is rounded to bf16 like that of bf16 data)
     auto go_split = [&](auto dtc) {
       constexpr int DT = decltype(dtc)::value;
-      const int64_t ntile = cdiv(rows, 64);
+      const int srows = split_rows(p.dtype, p.d);
+      const int64_t ntile = cdiv(rows, srows);
       const int64_t yrows = round_up(b.rows_cap, 64);
       auto part = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(ntile, b.ksplit), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
@@ -1780,6 +1794,7 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
                            (float*)nullptr, 0, b.ypart, yrows);
       };
       if constexpr (DT == DT_FP8) part(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), false, false, true>);
+      else if (srows == 128) part(k_xvd<NB, DT, 2, false, false, true>);
       else part(k_xvd<NB, DT, 1, false, false, true>);
       constexpr int DY = DT == DT_F32 ? DT_F32 : DT_BF16;
       hipLaunchKernelGGL((k_ysum<NB, DY>), dim3(b.ngpart), dim3(256), 0, s, b.ypart, b.ksplit,
@@ -1792,12 +1807,16 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
     if (b.split) {
       if (p.dtype != PPCA_BF16 || !want_g || want_y) return hipErrorInvalidValue;
       if (b.ksplit > 1) {
-        const int64_t ntile = cdiv(rows, 64);
+        const int srows = split_rows(p.dtype, p.d);
+        const int64_t ntile = cdiv(rows, srows);
         const int64_t yrows = round_up(b.rows_cap, 64);
-        hipLaunchKernelGGL((k_xvd<NB, DT_BF16, 1, false, false, true, true>), dim3(ntile, b.ksplit),
-                           dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d, p.ld, rstart, rows,
-                           (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr, (float*)nullptr, 0,
-                           b.ypart, yrows);
+        auto sp = [&](auto kern) {
+          hipLaunchKernelGGL(kern, dim3(ntile, b.ksplit), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
+                             p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr,
+                             (float*)nullptr, 0, b.ypart, yrows);
+        };
+        if (srows == 128) sp(k_xvd<NB, DT_BF16, 2, false, false, true, true>);
+        else sp(k_xvd<NB, DT_BF16, 1, false, false, true, true>);
         hipLaunchKernelGGL((k_ysum<NB, DT_BF16>), dim3(b.ngpart), dim3(256), 0, s, b.ypart,
                            b.ksplit, yrows, rows, (uint8_t*)b.yb, b.gpart, 0, 1,
                            accumulate ? 1 : 0);
