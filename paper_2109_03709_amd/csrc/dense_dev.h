@@ -22,15 +22,23 @@ __device__ inline bool status_set(const int* status) {
 // workgroup of 256 threads, in 16 x 16 blocks (the matrix is padded with the
 // identity to a multiple of 16; the padding factors to the identity).
 //
-// Factorisation, for each block row J (three barriers per block row):
-//   (1) wavefront 0 factors the diagonal block: lane c holds column c in
-//       registers; the pivot row is broadcast through LDS (one write, then
-//       every lane reads it).  Pivot test: finite, > K * eps * |a_jj| and > 0,
-//       else NOT_SPD.  The same wavefront then inverts the block (column c of
-//       X_JJ by back substitution, columns of R_JJ read from LDS) into XD[J];
+// Factorisation, for each block row J (two barriers per block row):
+//   (1) wavefront 0 factors the diagonal block by row operations on
+//       [A_JJ | I]: lane c < 16 holds column c of A_JJ, lane 16 + c column c
+//       of the identity, both in registers.  Pivot p scales row p by
+//       a_pp^-1/2 (giving row p of R_JJ), then subtracts r_pi times it from
+//       every row i > p; the pivot and the r_pi come from other lanes by
+//       readlane, so a pivot step has no LDS round trip and no barrier.
+//       The identity columns take the same row operations, E A_JJ = R_JJ, so
+//       they end as E = R_JJ^-T: lane 16 + c holds row c of X_JJ = R_JJ^-1,
+//       written to XD[J].  Pivot test: finite, > K * eps * |a_jj| and > 0,
+//       else NOT_SPD;
 //   (2) row panel R_J,c = X_JJ^T M_J,c (c > J), one 16 x 16 product per
 //       column block on float64 MFMAs;
-//   (3) trailing update M_ib,cb -= R_J,ib^T R_J,cb (J < ib <= cb) on MFMAs.
+//   (3) trailing update M_ib,cb -= R_J,ib^T R_J,cb (J < ib <= cb) on MFMAs,
+//       with a look-ahead: wavefront 0 updates block (J+1, J+1) first and
+//       factors it (step (1) of the next block row) while wavefronts 1-3
+//       update the other blocks.
 // Inverse, for each block row I from the bottom (two barriers per row):
 //   T_I,cb = sum_{I < kb <= cb} R_I,kb X_kb,cb, kept transposed in the unused
 //   strict lower blocks of M, then X_I,cb = -X_II T_I,cb.
@@ -62,7 +70,7 @@ __device__ inline f64x4_t mma16(f64x4_t d, FA a, FB b) {
 // kernel can reuse the area for its other phases)
 template <int KM>
 constexpr int chol_lds_doubles() {
-  return KM * (KM + 1) + (KM / 16) * 16 * 17 + KM + 16;
+  return KM * (KM + 1) + (KM / 16) * 16 * 17 + KM;
 }
 
 template <int KM>
@@ -73,7 +81,6 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
   double* const M = lds;                     // [KM][LDM]; odd row stride: column reads spread banks
   double* const XD = M + KM * LDM;           // [NBK][BS][LDX]: inverses of the diagonal blocks
   double* const dg = XD + NBK * BS * LDX;    // [KM]
-  double* const ub = dg + KM;                // [BS]: pivot row broadcast
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g4 = lane >> 4;
@@ -85,91 +92,93 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
   __syncthreads();
   const int nbk = (K + BS - 1) / BS, Kp = nbk * BS;
   if (tid == 0) fail = 0;
-  // load A in batches of 16 elements per thread, all loads in flight before
-  // any is used (a plain loop waits for every load in turn)
-  for (int e0 = tid; e0 < Kp * Kp; e0 += 16 * 256) {
-    double v[16];
+  // thread -> (column tid % KM, rows tid / KM + RS q): no integer division by
+  // K in the loops; batches of 32 loads in flight before the first is used
+  constexpr int RS = 256 / KM, LB = 32;
+  static_assert(256 % KM == 0, "256 threads");
+  const int cc = tid % KM, r0 = tid / KM;
+  if (cc < Kp) {
+    for (int ib = r0; ib < Kp; ib += LB * RS) {
+      double v[LB];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u;
-      const int i = e / Kp, c = e - i * Kp;
-      v[u] = (e < Kp * Kp && i < K && c < K && c >= i) ? A[i * K + c] : 0.0;
-    }
+      for (int q = 0; q < LB; ++q) {
+        const int i = ib + RS * q;
+        v[q] = (i < K && cc < K && cc >= i) ? A[i * K + cc] : 0.0;
+      }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u;
-      if (e >= Kp * Kp) continue;
-      const int i = e / Kp, c = e - i * Kp;
-      const double w = (i < K && c < K) ? v[u] : (i == c ? 1.0 : 0.0);
-      M[i * LDM + c] = w;
-      if (i == c) dg[i] = w;
+      for (int q = 0; q < LB; ++q) {
+        const int i = ib + RS * q;
+        if (i >= Kp) break;
+        const double w = (i < K && cc < K) ? v[q] : (i == cc ? 1.0 : 0.0);
+        M[i * LDM + cc] = w;
+        if (i == cc) dg[i] = w;
+      }
     }
   }
   __syncthreads();
-  for (int J = 0; J < nbk; ++J) {
+  // (1) diagonal block J and its inverse, wavefront 0 only (lanes >= 32
+  // repeat lanes 0..31 and store nothing)
+  auto factor_diag = [&](int J) {
+    const int j0 = J * BS, c = l16;
+    const bool ip = (lane & 16) != 0;            // identity column
+    double col[BS], tol[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      col[i] = ip ? (i == c ? 1.0 : 0.0) : ((i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0);
+      tol[i] = (double)K * kEps * fabs(dg[j0 + i]);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < BS; ++p) {
+      const double piv = bcast_lane(col[p], p);
+      // uniform: every lane holds the same pivot; after a failure the values
+      // are garbage and are not stored (no short-circuit: no branch in the
+      // pivot chain)
+      ok = ok & (bool)isfinite(piv) & (piv > tol[p]) & (piv > 0.0);
+      const double rinv = rsqrt(fabs(piv));
+      // row p scaled: r_pc in block lane c >= p (r_pp = |a_pp| rinv), zero
+      // left of the diagonal; e_pc in identity lane c
+      const double sp = ip ? col[p] * rinv
+                           : ((c == p) ? fabs(piv) * rinv : ((c > p) ? col[p] * rinv : 0.0));
+#pragma unroll
+      for (int i = p + 1; i < BS; ++i) {
+        const double rpi = bcast_lane(sp, i);    // r_pi, from block lane i
+        if (ip || i <= c) col[i] = fma(-rpi, sp, col[i]);
+      }
+      col[p] = sp;
+    }
+    if (!ok) {
+      if (lane == 0) fail = 1;
+    } else if (lane < BS) {
+#pragma unroll
+      for (int i = 0; i < BS; ++i)
+        if (i <= c) M[(j0 + i) * LDM + j0 + c] = col[i];
+    } else if (lane < 2 * BS) {
+      // row c of X_JJ (zero left of the diagonal)
+#pragma unroll
+      for (int i = 0; i < BS; ++i) XD[J * BS * LDX + c * LDX + i] = (i >= c) ? col[i] : 0.0;
+    }
+  };
+  // (3) M_ib,cb -= R_J,ib^T R_J,cb for one upper block (lower half of a
+  // diagonal block untouched)
+  auto trail_block = [&](int j0, int ib, int cb) {
+    f64x4_t d;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d[r] = M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16];
+    d = mma16(d, [&](int i, int k) { return -M[(j0 + k) * LDM + ib * BS + i]; },
+              [&](int k, int j) { return M[(j0 + k) * LDM + cb * BS + j]; });
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (ib != cb || g4 + 4 * r <= l16) M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
+  };
+  if (wave == 0) factor_diag(0);
+  __syncthreads();
+  if (fail) {
+    if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
+    return;
+  }
+  for (int J = 0; J + 1 < nbk; ++J) {
     const int j0 = J * BS;
-    // (1) diagonal block and its inverse, wavefront 0 (lanes >= 16 repeat
-    // lanes 0..15 and store nothing)
-    if (wave == 0) {
-      const int c = l16;
-      double col[BS], rv[BS];
-#pragma unroll
-      for (int i = 0; i < BS; ++i) col[i] = (i <= c) ? M[(j0 + i) * LDM + j0 + c] : 0.0;
-      bool ok = true;
-#pragma unroll
-      for (int p = 0; p < BS; ++p) {
-        if (lane < BS) ub[lane] = col[p];          // row p of the block (zero left of p)
-        __builtin_amdgcn_wave_barrier();
-        double w[BS];
-#pragma unroll
-        for (int i = p; i < BS; ++i) w[i] = ub[i];
-        __builtin_amdgcn_wave_barrier();
-        const double piv = w[p];
-        // uniform: every lane holds the same pivot; after a failure the
-        // values are garbage and are not stored (no short-circuit: no branch
-        // in the pivot chain)
-        const double tol = (double)K * kEps * fabs(dg[j0 + p]);
-        ok = ok & (bool)isfinite(piv) & (piv > tol) & (piv > 0.0);
-        const double rinv = rsqrt(fabs(piv));
-        rv[p] = rinv;
-        const double rpc = (c == p) ? fabs(piv) * rinv : ((c > p) ? col[p] * rinv : 0.0);
-#pragma unroll
-        for (int i = p + 1; i < BS; ++i)
-          if (i <= c) col[i] = fma(-(w[i] * rinv), rpc, col[i]);
-        col[p] = rpc;
-      }
-      if (!ok) {
-        if (lane == 0) fail = 1;
-      } else {
-        if (lane < BS) {
-#pragma unroll
-          for (int i = 0; i < BS; ++i)
-            if (i <= c) M[(j0 + i) * LDM + j0 + c] = col[i];
-        }
-        __builtin_amdgcn_wave_barrier();
-        // column c of X_JJ: x = e_c, then for p = 15 .. 0: x_p /= r_pp and
-        // x_i -= r_ip x_p (i < p), with column p of R_JJ read from LDS
-        double x[BS];
-#pragma unroll
-        for (int i = 0; i < BS; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int p = BS - 1; p >= 0; --p) {
-          x[p] *= rv[p];
-#pragma unroll
-          for (int i = 0; i < p; ++i) x[i] = fma(-M[(j0 + i) * LDM + j0 + p], x[p], x[i]);
-        }
-        if (lane < BS) {
-#pragma unroll
-          for (int i = 0; i < BS; ++i) XD[J * BS * LDX + i * LDX + c] = (i <= c) ? x[i] : 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    if (fail) {
-      if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
-      return;
-    }
-    if (J == nbk - 1) break;
     // (2) row panel R_J,cb = X_JJ^T M_J,cb
     const double* xj = XD + J * BS * LDX;
     for (int cb = J + 1 + wave; cb < nbk; cb += 4) {
@@ -180,31 +189,34 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
       for (int r = 0; r < 4; ++r) M[(j0 + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
     }
     __syncthreads();
-    // (3) trailing update of the upper blocks (ib, cb), J < ib <= cb
+    // (3) trailing update of the upper blocks (ib, cb), J < ib <= cb, with a
+    // look-ahead: wavefront 0 updates the next diagonal block and factors it
+    // (1) while the other three update the rest
     const int nt = nbk - 1 - J;
-    for (int q = wave; q < nt * (nt + 1) / 2; q += 4) {
-      int ib = 0, rem = q;
-      while (rem >= nt - ib) {
-        rem -= nt - ib;
-        ++ib;
+    if (wave == 0) {
+      trail_block(j0, J + 1, J + 1);
+      __builtin_amdgcn_wave_barrier();   // same wavefront: LDS order is program order
+      factor_diag(J + 1);
+    } else {
+      for (int q = wave; q < nt * (nt + 1) / 2; q += 3) {   // q = 0 is block (J+1, J+1)
+        int ib = 0, rem = q;
+        while (rem >= nt - ib) {
+          rem -= nt - ib;
+          ++ib;
+        }
+        trail_block(j0, J + 1 + ib, J + 1 + ib + rem);
       }
-      const int cb = J + 1 + ib + rem;
-      ib += J + 1;
-      f64x4_t d;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) d[r] = M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16];
-      d = mma16(d, [&](int i, int k) { return -M[(j0 + k) * LDM + ib * BS + i]; },
-                [&](int k, int j) { return M[(j0 + k) * LDM + cb * BS + j]; });
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (ib != cb || g4 + 4 * r <= l16) M[(ib * BS + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
     }
     __syncthreads();
+    if (fail) {
+      if (tid == 0) set_status(status, PPCA_ERR_NOT_SPD);
+      return;
+    }
   }
   // R out (upper triangle)
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e - i * K;
-    R[e] = c >= i ? M[i * LDM + c] : 0.0;
+  if (cc < K) {
+#pragma unroll 4
+    for (int i = r0; i < K; i += RS) R[i * K + cc] = cc >= i ? M[i * LDM + cc] : 0.0;
   }
   __syncthreads();   // R is read out before the diagonal blocks are overwritten
   // diagonal blocks -> their inverses
@@ -236,9 +248,9 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
     }
     __syncthreads();
   }
-  for (int e = tid; e < K * K; e += blockDim.x) {
-    const int i = e / K, c = e - i * K;
-    Rinv[e] = c >= i ? M[i * LDM + c] : 0.0;
+  if (cc < K) {
+#pragma unroll 4
+    for (int i = r0; i < K; i += RS) Rinv[i * K + cc] = cc >= i ? M[i * LDM + cc] : 0.0;
   }
 }
 

@@ -498,16 +498,22 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
   __shared__ __attribute__((aligned(16))) uint8_t st1[STB];
   __shared__ __attribute__((aligned(16))) uint8_t st2[STB];
 
-  // partial mode (split of the columns, blockIdx.y = split): the split's
-  // k-steps [kper y, kper (y + 1)) as a matrix of its own; the host picks the
-  // split count so that every split has at least one k-step
+  // partial mode (split of the columns): the split's k-steps [kper y,
+  // kper (y + 1)) as a matrix of its own; the host picks the split count so
+  // that every split has at least one k-step.  Its grid is (split, tile):
+  // with a split count that is a multiple of 8, the workgroups of one split
+  // (which all stream the same slice of V') share an XCD and its L2
+  const int tb = PART ? (int)blockIdx.y : (int)blockIdx.x;   // tile workgroup
+  const int tg = PART ? (int)gridDim.y : (int)gridDim.x;
+  const int sb = PART ? (int)blockIdx.x : (int)blockIdx.y;   // split
+  const int sg = PART ? (int)gridDim.x : (int)gridDim.y;
   const uint8_t* x = x_;
   const uint8_t* vop = vop_;
   int64_t d = d_;
   if constexpr (PART) {
     const int nk_all = (int)((d_ + KS - 1) / KS);
-    const int kper = (nk_all + (int)gridDim.y - 1) / (int)gridDim.y;
-    const int64_t c0 = (int64_t)blockIdx.y * kper * KS;
+    const int kper = (nk_all + sg - 1) / sg;
+    const int64_t c0 = (int64_t)sb * kper * KS;
     if (c0 >= d_) return;                    // uniform; excluded by the split count
     x += c0 * EB;
     vop += c0 * EB;
@@ -535,10 +541,10 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
   }
   // data row of each X block row, advanced by (gridDim.x * WGR) mod n per
   // tile (any valid row serves the rows past the pass: they are zeroed later)
-  const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
+  const int64_t tstep = ((int64_t)tg * WGR) % n;
   int64_t xrow[XI];
 #pragma unroll
-  for (int j = 0; j < XI; ++j) xrow[j] = (rstart + (int64_t)blockIdx.x * WGR + xr[j]) % n;
+  for (int j = 0; j < XI; ++j) xrow[j] = (rstart + (int64_t)tb * WGR + xr[j]) % n;
   const uint8_t* vsrc[VI];
   int vblk[VI];
 #pragma unroll
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 #pragma unroll
     for (int q = 0; q < NBG; ++q) accg[mb][q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t tl = blockIdx.x; tl < ntile; tl += gridDim.x) {
+  for (int64_t tl = tb; tl < ntile; tl += tg) {
     const int64_t row0 = tl * WGR;
     const uint8_t* xsrc[XI];
 #pragma unroll
@@ -689,7 +695,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 
     if constexpr (PART) {
       // float32 partial of this split: ypart[split][row0 + lr][c]
-      float* yp = ypart + ((int64_t)blockIdx.y * yrows + row0) * Kp;
+      float* yp = ypart + ((int64_t)sb * yrows + row0) * Kp;
 #pragma unroll
       for (int mb = 0; mb < MW; ++mb)
 #pragma unroll
@@ -795,7 +801,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
   }
 
   if constexpr (WANT_G) {
-    float* gbase = gpart + (int64_t)blockIdx.x * Kp * Kp;
+    float* gbase = gpart + (int64_t)tb * Kp * Kp;
 #pragma unroll
     for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
@@ -1751,6 +1757,8 @@ int xv_ksplit(int32_t dtype, int Kp, int64_t d, int64_t rows_cap) {
   const bool long_rows = nk >= 2048;
   const int64_t cap = long_rows ? 32 : 16, per_cu = long_rows ? 6 : 1;
   int64_t target = std::min<int64_t>(cap, std::min<int64_t>(per_cu * kNumCU / ntile, nk));
+  // long rows: a multiple of 8 splits, so that each split's tiles share an XCD
+  if (long_rows && target >= 8) target -= target % 8;
   if (target < 2) return 1;
   const int64_t kper = cdiv(nk, target);
   return (int)cdiv(nk, kper);
@@ -1788,14 +1796,17 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
       const int srows = split_rows(p.dtype, p.d);
       const int64_t ntile = cdiv(rows, srows);
       const int64_t yrows = round_up(b.rows_cap, 64);
-      auto part = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(ntile, b.ksplit), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
-                           p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr,
+      // k_xv takes a (tile, split) grid, k_xvd a (split, tile) grid
+      auto part = [&](auto kern, bool split_major) {
+        const dim3 grid = split_major ? dim3(b.ksplit, ntile) : dim3(ntile, b.ksplit);
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, (const uint8_t*)p.x, p.n, p.d, p.ld,
+                           rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr,
                            (float*)nullptr, 0, b.ypart, yrows);
       };
-      if constexpr (DT == DT_FP8) part(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), false, false, true>);
-      else if (srows == 128) part(k_xvd<NB, DT, 2, false, false, true>);
-      else part(k_xvd<NB, DT, 1, false, false, true>);
+      if constexpr (DT == DT_FP8)
+        part(k_xv<NB, DT, 1, xv_stages(DT, NB, 1), false, false, true>, false);
+      else if (srows == 128) part(k_xvd<NB, DT, 2, false, false, true>, true);
+      else part(k_xvd<NB, DT, 1, false, false, true>, true);
       constexpr int DY = DT == DT_F32 ? DT_F32 : DT_BF16;
       hipLaunchKernelGGL((k_ysum<NB, DY>), dim3(b.ngpart), dim3(256), 0, s, b.ypart, b.ksplit,
                          yrows, rows, (uint8_t*)b.yb, b.gpart, want_y ? 1 : 0, want_g ? 1 : 0,
@@ -1811,7 +1822,7 @@ hipError_t launch_xv(const PassDesc& p, const StreamBufs& b, int64_t i0, int64_t
         const int64_t ntile = cdiv(rows, srows);
         const int64_t yrows = round_up(b.rows_cap, 64);
         auto sp = [&](auto kern) {
-          hipLaunchKernelGGL(kern, dim3(ntile, b.ksplit), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
+          hipLaunchKernelGGL(kern, dim3(b.ksplit, ntile), dim3(256), 0, s, (const uint8_t*)p.x, p.n,
                              p.d, p.ld, rstart, rows, (const uint8_t*)b.vop, b.dp, (uint8_t*)nullptr,
                              (float*)nullptr, 0, b.ypart, yrows);
         };
