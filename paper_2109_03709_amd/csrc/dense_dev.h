@@ -18,9 +18,10 @@ __device__ inline bool status_set(const int* status) {
 }
 
 // --------------------------------------------------------------------------
-// Upper Cholesky factor R (R^T R = A) and X = R^-1, K <= KM <= 128, one
-// workgroup of 256 threads, in 16 x 16 blocks (the matrix is padded with the
-// identity to a multiple of 16; the padding factors to the identity).
+// Upper Cholesky factor R (R^T R = A; written only when R is not null) and
+// X = R^-1, K <= KM <= 128, one workgroup of 256 threads, in 16 x 16 blocks
+// (the matrix is padded with the identity to a multiple of 16; the padding
+// factors to the identity).
 //
 // Factorisation, for each block row J (two barriers per block row):
 //   (1) wavefront 0 factors the diagonal block by row operations on
@@ -39,11 +40,11 @@ __device__ inline bool status_set(const int* status) {
 //       with a look-ahead: wavefront 0 updates block (J+1, J+1) first and
 //       factors it (step (1) of the next block row) while wavefronts 1-3
 //       update the other blocks.
-// Inverse, for each block row I from the bottom (two barriers per row):
-//   T_I,cb = sum_{I < kb <= cb} R_I,kb X_kb,cb, kept transposed in the unused
-//   strict lower blocks of M, then X_I,cb = -X_II T_I,cb.
-// Column blocks are dealt round-robin to the four wavefronts.  Every sum runs
-// in a fixed order.
+// Inverse, by block columns (one wavefront each, no barrier): for I from
+//   the bottom, T_I,cb = sum_{I < kb <= cb} R_I,kb X_kb,cb, then
+//   X_I,cb = -X_II T_I,cb, kept transposed in the unused lower blocks of M.
+// Column blocks of the factorisation are dealt round-robin to the four
+// wavefronts.  Every sum runs in a fixed order.
 // --------------------------------------------------------------------------
 __device__ inline double bcast_lane(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -213,44 +214,51 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
       return;
     }
   }
-  // R out (upper triangle)
-  if (cc < K) {
-#pragma unroll 4
-    for (int i = r0; i < K; i += RS) R[i * K + cc] = cc >= i ? M[i * LDM + cc] : 0.0;
-  }
-  __syncthreads();   // R is read out before the diagonal blocks are overwritten
-  // diagonal blocks -> their inverses
-  for (int e = tid; e < nbk * BS * BS; e += blockDim.x) {
-    const int J = e / (BS * BS), i = (e / BS) % BS, c = e % BS;
-    if (i <= c) M[(J * BS + i) * LDM + J * BS + c] = XD[J * BS * LDX + i * LDX + c];
+  // Inverse, one block column at a time with no barrier: wavefront w takes
+  // columns nbk-1-w and w (the work of column cb grows like cb^2).  For
+  // I = cb-1 .. 0: T = sum_{I < kb <= cb} R_I,kb X_kb,cb, X_I,cb = -X_II T
+  // (T stays in the accumulators: their layout is the B operand's).  X_I,cb
+  // goes transposed into the unused lower block (cb, I) of M, so R stays
+  // whole for the other columns.
+  auto inv_column = [&](int cb) {
+    for (int I = cb - 1; I >= 0; --I) {
+      const int i0 = I * BS;
+      f64x4_t t = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kb = I + 1; kb <= cb; ++kb) {
+        if (kb == cb)
+          t = mma16(t, [&](int i, int k) { return M[(i0 + i) * LDM + kb * BS + k]; },
+                    [&](int k, int j) { return XD[cb * BS * LDX + k * LDX + j]; });
+        else
+          t = mma16(t, [&](int i, int k) { return M[(i0 + i) * LDM + kb * BS + k]; },
+                    [&](int k, int j) { return M[(cb * BS + j) * LDM + kb * BS + k]; });
+      }
+      // B operand element (4 kc + g4, l16) of the product is t[kc]
+      f64x4_t x = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        x = __builtin_amdgcn_mfma_f64_16x16x4f64(-XD[I * BS * LDX + l16 * LDX + 4 * kc + g4],
+                                                 t[kc], x, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) M[(cb * BS + l16) * LDM + i0 + g4 + 4 * r] = x[r];
+    }
+  };
+  if (nbk - 1 - wave >= wave) {
+    inv_column(nbk - 1 - wave);
+    if (wave < nbk - 1 - wave) inv_column(wave);
   }
   __syncthreads();
-  for (int I = nbk - 2; I >= 0; --I) {
-    const int i0 = I * BS;
-    // T_I,cb, stored transposed: T[r][c] at M[c][i0 + r]
-    for (int cb = I + 1 + wave; cb < nbk; cb += 4) {
-      f64x4_t d = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      for (int kb = I + 1; kb <= cb; ++kb)
-        d = mma16(d, [&](int i, int k) { return M[(i0 + i) * LDM + kb * BS + k]; },
-                  [&](int k, int j) { return M[(kb * BS + k) * LDM + cb * BS + j]; });
-#pragma unroll
-      for (int r = 0; r < 4; ++r) M[(cb * BS + l16) * LDM + i0 + g4 + 4 * r] = d[r];
-    }
-    __syncthreads();
-    // X_I,cb = -X_II T_I,cb
-    const double* xi = XD + I * BS * LDX;
-    for (int cb = I + 1 + wave; cb < nbk; cb += 4) {
-      f64x4_t d = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      d = mma16(d, [&](int i, int k) { return -xi[i * LDX + k]; },
-                [&](int k, int j) { return M[(cb * BS + j) * LDM + i0 + k]; });
-#pragma unroll
-      for (int r = 0; r < 4; ++r) M[(i0 + g4 + 4 * r) * LDM + cb * BS + l16] = d[r];
-    }
-    __syncthreads();
-  }
+  // R (upper blocks of M) and R^-1 (diagonal blocks in XD, the others
+  // transposed in the lower blocks of M) out
   if (cc < K) {
 #pragma unroll 4
-    for (int i = r0; i < K; i += RS) Rinv[i * K + cc] = cc >= i ? M[i * LDM + cc] : 0.0;
+    for (int i = r0; i < K; i += RS) {
+      const int ib = i / BS, cb = cc / BS;
+      if (R) R[i * K + cc] = cc >= i ? M[i * LDM + cc] : 0.0;
+      Rinv[i * K + cc] = ib < cb    ? M[cc * LDM + i]
+                         : ib > cb  ? 0.0
+                         : cc >= i ? XD[ib * BS * LDX + (i % BS) * LDX + cc % BS]
+                                    : 0.0;
+    }
   }
 }
 

@@ -114,7 +114,7 @@ struct Plan {
   // offsets
   size_t ypart = 0;
   size_t status = 0, vop = 0, rotp = 0, flip = 0, yb = 0, part = 0, gpart = 0, z = 0, g = 0, b = 0, gparts = 0,
-         a = 0, r = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
+         a = 0, rinv = 0, q1 = 0, t = 0, h = 0, w = 0, ev = 0, m = 0, egs = 0,
          sums = 0, cmax = 0, mean = 0, vprev = 0, chg = 0, su = 0, sw = 0, stmp = 0, sst = 0;
   size_t total = 0;
 };
@@ -166,7 +166,6 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
     // so K bounds every k <= K; at most 1024 workgroups, whatever d)
     p.rotp = c.take((size_t)rotate_blocks(d, K) * K * sizeof(ColMax));
     p.flip = c.take((size_t)K * sizeof(int));
-    p.r = c.take(kk);
     p.rinv = c.take(kk);
     p.t = c.take(kk);
     p.h = c.take(kk);
@@ -205,7 +204,6 @@ Plan make_plan(int32_t op, int64_t n, int64_t d, int32_t dtype, int K, int64_t b
   p.b = c.take(kk);
   p.gparts = c.take((size_t)gram_parts(d, K) * K * K * sizeof(double));
   p.a = c.take(kk);
-  p.r = c.take(kk);
   p.rinv = c.take(kk);
   p.q1 = c.take((size_t)d * K * sizeof(double));
   if (fused) {
@@ -359,14 +357,13 @@ int cholqr2(const float* A, float* V, int64_t d, int K, const Plan& p, void* ws,
   int* st = at<int>(ws, p.status);
   double* gp = at<double>(ws, p.gparts);
   double* Am = at<double>(ws, p.a);
-  double* R = at<double>(ws, p.r);
   double* Ri = at<double>(ws, p.rinv);
   double* Q1 = at<double>(ws, p.q1);
   HIP_TRY(launch_gram(A, false, d, K, K, gp, Am, st, s));
-  HIP_TRY(launch_chol_inv(Am, K, R, Ri, st, s));
+  HIP_TRY(launch_chol_inv(Am, K, nullptr, Ri, st, s));
   HIP_TRY(launch_trmm(A, false, d, K, K, Ri, Q1, true, K, st, s));
   HIP_TRY(launch_gram(Q1, true, d, K, K, gp, Am, st, s));
-  HIP_TRY(launch_chol_inv(Am, K, R, Ri, st, s));
+  HIP_TRY(launch_chol_inv(Am, K, nullptr, Ri, st, s));
   HIP_TRY(launch_trmm(Q1, true, d, K, K, Ri, V, false, K, st, s));
   return PPCA_OK;
 }
@@ -409,14 +406,13 @@ int rayleigh_ritz_on(const ppca_matrix* X, int K, int k, const double* G, const 
                      hipStream_t s) {
   int* st = at<int>(ws, p.status);
   HIP_TRY(launch_zero(st, 256, s));
-  double* R = at<double>(ws, p.r);
   double* Ri = at<double>(ws, p.rinv);
   double* T = at<double>(ws, p.t);
   double* H = at<double>(ws, p.h);
   double* W = at<double>(ws, p.w);
   double* ev = at<double>(ws, p.ev);
   double* M = at<double>(ws, p.m);
-  HIP_TRY(launch_chol_inv(B, K, R, Ri, st, s));
+  HIP_TRY(launch_chol_inv(B, K, nullptr, Ri, st, s));
   HIP_TRY(launch_small_gemm(G, false, Ri, T, K, K, K, K, K, K, 1.0, st, s));
   HIP_TRY(launch_small_gemm(Ri, true, T, H, K, K, K, K, K, K, 1.0 / (double)X->n, st, s));
   HIP_TRY(launch_jacobi(H, K, W, ev, 60, st, s));
