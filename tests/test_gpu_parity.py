@@ -459,6 +459,33 @@ def test_error_not_spd():
     assert ei.value.code == -3
 
 
+def test_error_not_spd_late_block():
+    """K = 128 with a zero column 100: the zero pivot comes in the seventh
+    16-column block, which the Cholesky factors while the other wavefronts
+    still update the trailing blocks; the call reports NOT_SPD, and the next
+    call on a full-rank basis runs normally (matching the oracle)."""
+    d, K, k = 300, 128, 64
+    p = make_problem(1000, d, "exp0.9", seed=15, mode="exact")
+    data, _, _ = device_data(p.x, F32)
+    v = gaussian_block(d, K, 7, np.float32)
+    bad = v.copy()
+    bad[:, 100] = 0.0
+    with pytest.raises(P().PPCAError) as ei:
+        P().prime_power(data, k, K - k, 2, torch.from_numpy(bad).cuda())
+    assert ei.value.code == -3
+    bd = torch.from_numpy(bad).cuda()
+    G, B = P().project_gram(data, K, bd)
+    with pytest.raises(P().PPCAError) as ei:
+        P().rayleigh_ritz(data, K, k, G, B, bd)
+    assert ei.value.code == -3
+    vd = torch.from_numpy(v).cuda()
+    G, B = P().project_gram(data, K, vd)
+    ev, _ = P().rayleigh_ritz(data, K, k, G, B, vd)
+    torch.cuda.synchronize()
+    th, _, _ = O.rayleigh_ritz(G.cpu().numpy(), B.cpu().numpy(), v.astype(np.float64), data.n, k)
+    assert np.max(O.rel_eig_error(ev.cpu().numpy(), th)) < 1e-8
+
+
 def test_error_nonfinite():
     p = make_problem(1000, 64, "exp0.9", seed=13, mode="exact")
     data, _, _ = device_data(p.x, F32)
