@@ -269,6 +269,8 @@ __device__ __attribute__((always_inline)) inline void chol_inv_dev(const double*
 // eigenvector matrix W.  Each round rotates K/2 disjoint pairs at once:
 // A <- J^T A J, W <- W J, with the classical rotation that zeroes a_pq
 // (tau = (a_qq - a_pp)/(2 a_pq), t = sign(tau)/(|tau| + sqrt(1+tau^2))).
+// A rotation round updates the upper triangle of A only (one 2x2 block of
+// the pair-by-pair partition per thread, four reads and four writes).
 // Stops when off(A) <= 1e-15 ||A||_F or a sweep rotates nothing.
 // Output: evals[K] descending; Ws[i][rank] = W[i][col] sorted to match.
 constexpr int kJacRows = 16;
@@ -296,8 +298,8 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
                                   int rowblk) {
   __shared__ double A[KM * (KM + 1)];   // row stride kpad + 1: column accesses spread banks
   __shared__ double Wl[JR * KM];
-  __shared__ double cs[KM / 2], sn[KM / 2];
-  __shared__ int pp[KM / 2], qq[KM / 2];
+  __shared__ double2 rot[KM / 2];      // (c, s) of pair i
+  __shared__ int2 pq[KM / 2];          // (p, q) of pair i, p < q
   __shared__ double red[16];
   __shared__ int any_rot;
   __shared__ int rank_of[KM];
@@ -311,6 +313,9 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
   const int npair = kpad / 2;
   const int la = kpad + 1;          // LDS row stride of A
   const int row0 = rowblk * JR;
+  // rotations update the upper triangle only: element (i, j) lives at
+  // (min, max) (the load writes both triangles; the lower one goes stale)
+  auto up = [la](int i, int j) { return i < j ? i * la + j : j * la + i; };
   // H in batches of 8 elements per thread (all loads in flight before use)
   for (int e0 = tid; e0 < kpad * kpad; e0 += 8 * 1024) {
     double hv[8];
@@ -342,7 +347,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
     loc = 0.0;
     for (int e = tid; e < kpad * kpad; e += blockDim.x) {
       const int i = e / kpad, j = e % kpad;
-      if (i != j) loc += A[i * la + j] * A[i * la + j];
+      if (i != j) loc += A[up(i, j)] * A[up(i, j)];
     }
     const double off = sqrt(block_sum(loc, red));
     if (off <= 1e-15 * fro) {
@@ -366,43 +371,51 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
             any_rot = 1;
           }
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+        pq[tid] = make_int2(p, q);
+        rot[tid] = make_double2(c, s);
       }
       __syncthreads();
-      // 2x2 blocks (bi <= bj), each updated by one thread and mirrored;
-      // thread t takes bi = t/16 + 64m, bj = t%16 + 16m' (no division)
+      // 2x2 blocks (bi <= bj), each updated by one thread in the upper
+      // triangle; thread t takes bi = t/16 + 64m, bj = t%16 + 16m' (no division)
       for (int bi = tid >> 4; bi < npair; bi += 64) {
+        const int2 pqi = pq[bi];
+        const double2 ri = rot[bi];
+        const int pi = pqi.x, qi = pqi.y;
+        const double ci = ri.x, si = ri.y;
         for (int bj = tid & 15; bj < npair; bj += 16) {
           if (bi > bj) continue;
-          const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
-          const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+          const int2 pqj = pq[bj];
+          const double2 rj = rot[bj];
+          const int pj = pqj.x, qj = pqj.y;
+          const double cj = rj.x, sj = rj.y;
           if (si == 0.0 && sj == 0.0) continue;
-          const double a = A[pi * la + pj], b = A[pi * la + qj];
-          const double e0 = A[qi * la + pj], f = A[qi * la + qj];
+          const int ia = up(pi, pj), ib = up(pi, qj), ie = up(qi, pj), iff = up(qi, qj);
+          const double a = A[ia], b = A[ib];
+          const double e0 = A[ie], f = A[iff];
           const double a1 = ci * a - si * e0, b1 = ci * b - si * f;
           const double e1 = si * a + ci * e0, f1 = si * b + ci * f;
           double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
           double e2 = cj * e1 - sj * f1, f2 = sj * e1 + cj * f1;
           if (bi == bj) {
-            A[pi * la + pi] = a2;
-            A[qi * la + qi] = f2;
-            A[pi * la + qi] = 0.0;
-            A[qi * la + pi] = 0.0;
+            A[ia] = a2;
+            A[iff] = f2;
+            A[ib] = 0.0;
           } else {
-            A[pi * la + pj] = a2; A[pj * la + pi] = a2;
-            A[pi * la + qj] = b2; A[qj * la + pi] = b2;
-            A[qi * la + pj] = e2; A[pj * la + qi] = e2;
-            A[qi * la + qj] = f2; A[qj * la + qi] = f2;
+            A[ia] = a2;
+            A[ib] = b2;
+            A[ie] = e2;
+            A[iff] = f2;
           }
         }
       }
       // W rows of this workgroup: thread t takes row t/64 and pair t%64
       for (int lr = tid >> 6; lr < JR; lr += 16) {
         for (int i = tid & 63; i < npair; i += 64) {
-          const double s = sn[i];
+          const double2 r = rot[i];
+          const double s = r.y;
           if (s == 0.0) continue;
-          const double c = cs[i];
-          const int p = pp[i], q = qq[i];
+          const double c = r.x;
+          const int p = pq[i].x, q = pq[i].y;
           const double wp = Wl[lr * kpad + p], wq = Wl[lr * kpad + q];
           Wl[lr * kpad + p] = c * wp - s * wq;
           Wl[lr * kpad + q] = s * wp + c * wq;
@@ -417,7 +430,7 @@ __device__ inline void jacobi_dev(const double* __restrict__ H, int K, double* _
     loc = 0.0;
     for (int e = tid; e < kpad * kpad; e += blockDim.x) {
       const int i = e / kpad, j = e % kpad;
-      if (i != j) loc += A[i * la + j] * A[i * la + j];
+      if (i != j) loc += A[up(i, j)] * A[up(i, j)];
     }
     const double off = sqrt(block_sum(loc, red));
     if (off > 1e-15 * fro) {
