@@ -190,8 +190,11 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ A, 
 
 // --------------------------------------------------------------------------
 // out = A * Rinv for upper-triangular Rinv (K x K): tiled product, block =
-// 64 rows x 32 columns of out, k-steps of 32 that stop at the tile's last
-// column (Rinv is zero below its diagonal).
+// 64 rows x 32 columns of out.  Rinv is zero below its diagonal, so the
+// block needs the columns [0, kend) of its rows of A and the rows [0, kend)
+// of its columns of Rinv, kend = min(c0 + 32, K): all of them are loaded in
+// one batch (every load in flight before the first is used), staged in LDS,
+// and the k loop runs over them in order.
 // --------------------------------------------------------------------------
 constexpr int kTR = 64, kTC = 32;
 
@@ -199,38 +202,45 @@ template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_trmm(const TI* __restrict__ A, int64_t rows, int K,
                                               int64_t lda, const double* __restrict__ Rinv,
                                               TO* __restrict__ out, int64_t ldo, int* status) {
-  __shared__ double As[kTR][kTC + 1], Rs[kTC][kTC + 1];
+  __shared__ double As[kTR][kMaxK + 1], Rs[kMaxK][kTC + 1];
   if (status_set(status)) return;
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * kTR;
   const int c0 = blockIdx.y * kTC;
   const int kend = c0 + kTC < K ? c0 + kTC : K;
+  constexpr int NA = kTR * kMaxK / 256, NR = kMaxK * kTC / 256;
+  double va[NA], vr[NR];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = t + 256 * u, r = e / kMaxK, c = e % kMaxK;
+    const int64_t row = r0 + r;
+    va[u] = (row < rows && c < kend) ? (double)A[row * lda + c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int e = t + 256 * u, r = e / kTC, c = e % kTC;
+    vr[u] = (r < kend && c0 + c < K) ? Rinv[r * K + c0 + c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = t + 256 * u;
+    As[e / kMaxK][e % kMaxK] = va[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int e = t + 256 * u;
+    Rs[e / kTC][e % kTC] = vr[u];
+  }
+  __syncthreads();
   double acc[4][2] = {};
-  for (int p0 = 0; p0 < kend; p0 += kTC) {
+  for (int pp = 0; pp < kend; ++pp) {
+    const double b0 = Rs[pp][2 * tx], b1 = Rs[pp][2 * tx + 1];
 #pragma unroll
-    for (int e = t; e < kTR * kTC; e += 256) {   // fixed trip count: all loads issued first
-      const int r = e / kTC, c = e % kTC;
-      const int64_t row = r0 + r;
-      const int col = p0 + c;
-      As[r][c] = (row < rows && col < K) ? (double)A[row * lda + col] : 0.0;
+    for (int u = 0; u < 4; ++u) {
+      const double av = As[4 * ty + u][pp];
+      acc[u][0] = fma(av, b0, acc[u][0]);
+      acc[u][1] = fma(av, b1, acc[u][1]);
     }
-#pragma unroll
-    for (int e = t; e < kTC * kTC; e += 256) {
-      const int r = e / kTC, c = e % kTC;
-      const int pr = p0 + r, pc = c0 + c;
-      Rs[r][c] = (pr < K && pc < K) ? Rinv[pr * K + pc] : 0.0;
-    }
-    __syncthreads();
-    for (int pp = 0; pp < kTC; ++pp) {
-      const double b0 = Rs[pp][2 * tx], b1 = Rs[pp][2 * tx + 1];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double av = As[4 * ty + u][pp];
-        acc[u][0] = fma(av, b0, acc[u][0]);
-        acc[u][1] = fma(av, b1, acc[u][1]);
-      }
-    }
-    __syncthreads();
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
