@@ -427,10 +427,12 @@ static int gram_tiles(int K) {
   return nt * (nt + 1) / 2;
 }
 
-// row chunks of the Gram: about 512 blocks in all, at least 16 rows a chunk
+// row chunks of the Gram: about 512 blocks in all, at least 128 rows a chunk
+// (at d = 2048, K = 128: 16 chunks of two 64-row stages; the fixed-order sum
+// over the chunks then reads 16 partials instead of 52)
 int gram_parts(int64_t rows, int K) {
   int64_t nc = cdiv(512, gram_tiles(K));
-  const int64_t by_rows = cdiv(rows, 16);
+  const int64_t by_rows = cdiv(rows, 128);
   if (nc > by_rows) nc = by_rows;
   if (nc < 1) nc = 1;
   return (int)nc;
