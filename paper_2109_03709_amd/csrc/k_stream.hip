@@ -73,6 +73,14 @@ __device__ inline uint4 chunk_mask(int64_t col, int64_t d) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Slot of chunk c of a 128-byte LDS row r is c ^ swz(r).  A 128-bit LDS read
+// serves 16 lanes per pass from the 64 banks (16 units of 16 bytes); unit of
+// (r, slot) = 8 (r & 1) + slot.  The fragment reads take one chunk of 16
+// consecutive rows r0 .. r0 + 15 (r0 a multiple of 16), and (r >> 1) & 7
+// gives those rows 16 distinct units (r & 7 gave rows r and r + 8 the same
+// unit: a two-way conflict on every read).
+__device__ inline int swz(int r) { return (r >> 1) & 7; }
+
 __device__ inline uint4 and4(uint4 a, uint4 m) {
   return make_uint4(a.x & m.x, a.y & m.y, a.z & m.z, a.w & m.w);
 }
@@ -458,8 +466,8 @@ __global__ __launch_bounds__(256, 1) void k_xv(const uint8_t* x_, int64_t n, int
 //             -> barrier -> DMA of step kk+2 into the stage freed by step kk-1
 //             -> MFMAs on stage kk.
 // A DMA writes 64 lanes x 16 bytes to consecutive LDS slots, so the XOR
-// swizzle of a 128-byte row (chunk c at slot c ^ (row & 7), conflict-free
-// fragment reads) is produced by choosing which global chunk each lane loads.
+// swizzle of a 128-byte row (chunk c at slot c ^ swz(row)) is produced by
+// choosing which global chunk each lane loads.
 // Every wave issues the same number of DMAs per step (steps past the last one
 // and the V' blocks of a small K repeat valid loads), so a fixed vmcnt wait
 // always means "the stage I need has landed".
@@ -530,14 +538,14 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 
   // DMA sources.  X block j of wave w covers tile rows 8 (w XI + j) .. +7; lane
   // -> row 8 (w XI + j) + lane / 8, LDS slot lane % 8 holding chunk
-  // (lane % 8) ^ (row & 7).
+  // (lane % 8) ^ swz(row).
   const int p8 = lane & 7;
   int xr[XI], xc[XI];
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
     const int r = 8 * (w * XI + j) + (lane >> 3);
     xr[j] = r;
-    xc[j] = (p8 ^ (r & 7)) * (16 / EB);                // first column of the chunk in the step
+    xc[j] = (p8 ^ swz(r)) * (16 / EB);                // first column of the chunk in the step
   }
   // data row of each X block row, advanced by (gridDim.x * WGR) mod n per
   // tile (any valid row serves the rows past the pass: they are zeroed later)
@@ -552,7 +560,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
     const int blk = (w * VI + j) % VBLK;
     const int r = 8 * blk + (lane >> 3);
     vblk[j] = blk;
-    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ swz(r)) * 16;
   }
 
   f32x4_t acc[MW][NB];
@@ -616,12 +624,12 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 #pragma unroll
           for (int mb = 0; mb < MW; ++mb) {
             const int r = w * MW * 16 + mb * 16 + a;
-            af[mb] = *reinterpret_cast<const float4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+            af[mb] = *reinterpret_cast<const float4*>(xs + r * 128 + ((c ^ swz(r)) * 16));
           }
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int r = nb * 16 + a;
-            bf[nb] = *reinterpret_cast<const float4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+            bf[nb] = *reinterpret_cast<const float4*>(vs + r * 128 + ((c ^ swz(r)) * 16));
           }
 #pragma unroll
           for (int mb = 0; mb < MW; ++mb)
@@ -641,12 +649,12 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 #pragma unroll
           for (int mb = 0; mb < MW; ++mb) {
             const int r = w * MW * 16 + mb * 16 + a;
-            af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+            af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ swz(r)) * 16));
           }
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int r = nb * 16 + a;
-            bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+            bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ swz(r)) * 16));
           }
 #pragma unroll
           for (int mb = 0; mb < MW; ++mb)
@@ -659,7 +667,7 @@ __global__ __launch_bounds__(256, 1) void k_xvd(const uint8_t* x_, int64_t n, in
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
               const int r = nb * 16 + a;
-              bf[nb] = *reinterpret_cast<const uint4*>(vs + VSB + r * 128 + ((c ^ (r & 7)) * 16));
+              bf[nb] = *reinterpret_cast<const uint4*>(vs + VSB + r * 128 + ((c ^ swz(r)) * 16));
             }
 #pragma unroll
             for (int mb = 0; mb < MW; ++mb)
@@ -968,7 +976,7 @@ __global__ __launch_bounds__(256, 1) void k_xvy(const uint8_t* x, int64_t n, int
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
     const int r = 8 * (w * XI + j) + (lane >> 3);
-    xc[j] = (p8 ^ (r & 7)) * (16 / EB);
+    xc[j] = (p8 ^ swz(r)) * (16 / EB);
   }
   const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
   int64_t xrow[XI];
@@ -986,7 +994,7 @@ __global__ __launch_bounds__(256, 1) void k_xvy(const uint8_t* x, int64_t n, int
     const int blk = (w * VI + j) % VBLK;
     const int r = 8 * blk + (lane >> 3);
     vblk[j] = blk;
-    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ swz(r)) * 16;
   }
   // stage b of the ring (b is wavefront-uniform)
   auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* { return st + b * STB; };
@@ -1045,12 +1053,12 @@ __global__ __launch_bounds__(256, 1) void k_xvy(const uint8_t* x, int64_t n, int
 #pragma unroll
       for (int mb = 0; mb < M2; ++mb) {
         const int r = w * MW * 16 + mb * 32 + l32;
-        af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+        af[mb] = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ swz(r)) * 16));
       }
 #pragma unroll
       for (int nb = 0; nb < N2; ++nb) {
         const int r = nb * 32 + l32;
-        bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ (r & 7)) * 16));
+        bf[nb] = *reinterpret_cast<const uint4*>(vs + r * 128 + ((c ^ swz(r)) * 16));
       }
 #pragma unroll
       for (int mb = 0; mb < M2; ++mb)
@@ -1156,7 +1164,7 @@ __global__ __launch_bounds__(256, 1) void k_xvg(const uint8_t* x, int64_t n, int
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
     const int r = 8 * (w * XI + j) + (lane >> 3);
-    xc[j] = (p8 ^ (r & 7)) * (16 / EB);
+    xc[j] = (p8 ^ swz(r)) * (16 / EB);
   }
   const int64_t tstep = ((int64_t)gridDim.x * WGR) % n;
   int64_t xrow[XI];
@@ -1175,7 +1183,7 @@ __global__ __launch_bounds__(256, 1) void k_xvg(const uint8_t* x, int64_t n, int
     const int blk = (w * VI + j) % VBLK;
     const int r = 8 * blk + (lane >> 3);
     vblk[j] = blk;
-    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ (r & 7)) * 16;
+    vsrc[j] = vop + (int64_t)r * dp * EB + (p8 ^ swz(r)) * 16;
   }
   auto stage = [&](int b) __attribute__((always_inline)) -> uint8_t* { return st + b * STB; };
   int64_t iss = 0;
@@ -1232,13 +1240,13 @@ __global__ __launch_bounds__(256, 1) void k_xvg(const uint8_t* x, int64_t n, int
     for (int s4 = 0; s4 < 4; ++s4) {
       const int c = 2 * s4 + hl;
       const int r = w * 32 + l32;
-      const uint4 af = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ (r & 7)) * 16));
+      const uint4 af = *reinterpret_cast<const uint4*>(xs + r * 128 + ((c ^ swz(r)) * 16));
       uint4 bh[N2], bl[N2];
 #pragma unroll
       for (int nb = 0; nb < N2; ++nb) {
         const int rv = nb * 32 + l32;
-        bh[nb] = *reinterpret_cast<const uint4*>(vh + rv * 128 + ((c ^ (rv & 7)) * 16));
-        bl[nb] = *reinterpret_cast<const uint4*>(vl + rv * 128 + ((c ^ (rv & 7)) * 16));
+        bh[nb] = *reinterpret_cast<const uint4*>(vh + rv * 128 + ((c ^ swz(rv)) * 16));
+        bl[nb] = *reinterpret_cast<const uint4*>(vl + rv * 128 + ((c ^ swz(rv)) * 16));
       }
 #pragma unroll
       for (int nb = 0; nb < N2; ++nb)
