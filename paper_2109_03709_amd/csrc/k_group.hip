@@ -85,6 +85,22 @@ struct GCls {
   // the narrow classes keep as many bytes in flight as the wide ones
   static constexpr int S = 4 * 16 * 192 * 2 / XSB;               // 12, 6 or 4
   static_assert((S - 1) * DPS < 64 && S >= 4 && S % 2 == 0, "stage ring");
+  // LDS place of (row r, 16-byte chunk c) of a 16-row stage: physical row
+  // prow(r), slot pch(r, c) (both involutions, so the DMA side uses them to
+  // find the global chunk of a slot).  Two reads must be conflict-free:
+  // the Y product reads one chunk of 16 rows (128-bit reads, 16 lanes a pass
+  // over 16 units of 16 bytes), the Z product reads 8 chunks of rows r and
+  // r + 4 (32-bit reads, 64 lanes a pass: the two rows' 128-byte windows must
+  // be in different halves of the 256-byte bank window).  Rows of 128 CW
+  // bytes: odd CW puts rows in alternate halves, so r and r + 4 swap
+  // neighbours when bit 2 of r is set and the chunk swizzle takes r >> 1;
+  // even CW keeps the rows and swizzles with the 4-bit r with bits 2 and 3
+  // exchanged (bit 3 of the slot then differs between r and r + 4).
+  static constexpr bool ODD = (CW & 1) != 0;
+  __device__ static int prow(int r) { return ODD ? r ^ ((r >> 2) & 1) : r; }
+  __device__ static int pch(int r, int c) {
+    return ODD ? c ^ ((r >> 1) & 7) : c ^ ((r & 3) | ((r & 4) << 1) | ((r & 8) >> 1));
+  }
 };
 
 constexpr int kGS = 4;                    // X stages per wave at the widest class
@@ -144,14 +160,17 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
                                                     c0 + 16 * s + 8 * hl);
   }
 
-  // DMA lanes: slot q = 64 j + lane of a stage is (row q / CPR, slot q % CPR)
-  // and holds the slice's 16-byte column chunk slot ^ (row & 7); chunks past d
-  // load column 0 (their operand rows are zero).  voff: byte offset of lane's
-  // chunk j from its tile's first row.
-  auto drow = [&](int j) __attribute__((always_inline)) { return (64 * j + lane) / C::CPR; };
+  // DMA lanes: slot q = 64 j + lane of a stage is (physical row q / CPR,
+  // slot q % CPR) and holds row r = prow(q / CPR) of the tile, 16-byte column
+  // chunk pch(r, q % CPR) of the slice; chunks past d load column 0 (their
+  // operand rows are zero).  voff: byte offset of lane's chunk j from its
+  // tile's first row.
+  auto drow = [&](int j) __attribute__((always_inline)) {
+    return C::prow((64 * j + lane) / C::CPR);
+  };
   auto dcol = [&](int j) __attribute__((always_inline)) {
-    const int q = 64 * j + lane, r = q / C::CPR, sl = q % C::CPR;
-    const int64_t col = c0 + 8 * (sl ^ (r & 7));
+    const int q = 64 * j + lane, r = C::prow(q / C::CPR), sl = q % C::CPR;
+    const int64_t col = c0 + 8 * C::pch(r, sl);
     return (col < d ? col : 0) * 2;
   };
   uint32_t voff[C::DPS];
@@ -217,11 +236,10 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
     for (int nb = 0; nb < NB2; ++nb) ya[nb] = f32x16_t{};
     {
       const int rr = l32 & 15;
-      const uint8_t* xrow = ((l32 >> 4) ? xs1 : xs0) + rr * C::CPR * 16;
+      const uint8_t* xrow = ((l32 >> 4) ? xs1 : xs0) + C::prow(rr) * C::CPR * 16;
 #pragma unroll
       for (int s = 0; s < C::DW / 16; ++s) {
-        const uint4 av =
-            *reinterpret_cast<const uint4*>(xrow + (((2 * s + hl) ^ (rr & 7)) * 16));
+        const uint4 av = *reinterpret_cast<const uint4*>(xrow + C::pch(rr, 2 * s + hl) * 16);
 #pragma unroll
         for (int nb = 0; nb < NB2; ++nb)
           ya[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(vf[s][nb]),
@@ -338,7 +356,7 @@ __device__ __attribute__((always_inline)) inline void run_item(const GProb& P, c
           for (int e = 0; e < 8; ++e) {
             const int row = 8 * (e / 4) + 4 * hl + e % 4;
             in[e] = *reinterpret_cast<const uint32_t*>(
-                xs + (row * C::CPR + (ch ^ (row & 7))) * 16 + (l32 & 3) * 4);
+                xs + (C::prow(row) * C::CPR + C::pch(row, ch)) * 16 + (l32 & 3) * 4);
           }
           const uint4 a0 = make_uint4((in[0] & 0xFFFFu) | (in[1] << 16),
                                       (in[2] & 0xFFFFu) | (in[3] << 16),
