@@ -43,8 +43,9 @@ __device__ inline bool status_set(const int* status) {
 // Inverse, by block columns (one wavefront each, no barrier): for I from
 //   the bottom, T_I,cb = sum_{I < kb <= cb} R_I,kb X_kb,cb, then
 //   X_I,cb = -X_II T_I,cb, kept transposed in the unused lower blocks of M.
-// Column blocks of the factorisation are dealt round-robin to the four
-// wavefronts.  Every sum runs in a fixed order.
+// The panel's column blocks are dealt round-robin to the four wavefronts,
+// the other trailing blocks to wavefronts 1-3.  Every sum runs in a fixed
+// order.
 // --------------------------------------------------------------------------
 __device__ inline double bcast_lane(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
