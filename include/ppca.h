@@ -246,7 +246,7 @@ int ppca_rayleigh_ritz(const ppca_matrix* X, int32_t K, int32_t k,
  * fixed device array of PPCA_NOALLOC_SCRATCH_BYTES inside the library (one
  * copy per GPU, held until the process ends).  The Rayleigh-Ritz workspace
  * does not grow with n or d (the rotation reads V directly; its sign rule
- * keeps at most 1024 x K column maxima): at most about 2.8 MiB, at
+ * keeps at most 1024 x K column maxima): at most about 2.7 MiB, at
  * K = PPCA_MAX_K, so every valid call fits; a call whose workspace
  * (ppca_workspace_bytes(PPCA_OP_RR, X, K, 0)) exceeded the array would return
  * PPCA_ERR_WORKSPACE without running.  `stream` must belong to the current
