@@ -270,6 +270,7 @@ def main():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_kernels_bf16_2Mx2048_K128.txt")
 FUSED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_power_fused_bf16_2Mx2048_K128.txt")
+WIDE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eigengame_wide_bf16_6654x15116544_K8.txt")
 
 
 def _counter_file(path, src_name, key, workload):
@@ -287,6 +288,20 @@ def _counter_file(path, src_name, key, workload):
     if kv["workload"] != workload:
         return None
     return kv
+
+
+def measured_wide_traffic(n, d, K, b):
+    """HBM bytes per launch of the d >> n minibatch passes (0: Y = X_b V',
+    1: Z = X_b^T Y), from the committed counter summary, or None."""
+    try:
+        kv = _counter_file(WIDE_TRAFFIC_FILE, "k_stream.hip", "k_stream_sha1",
+                           f"n={n} d={d} K={K} b={b} bf16")
+        if kv:
+            f = lambda k: int(kv[k + ".fetch_bytes"]) + int(kv[k + ".write_bytes"])
+            return {0: f("y_pass"), 1: f("z_pass")}
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
 
 
 def measured_traffic(n, d, K, storage, iters, fused):
@@ -1207,9 +1222,15 @@ def main_wide(a):
             per[sl] = {"kernel": names[sl], "launches": nl, "avg_ms": round(tot / nl, 4),
                        "achieved_GBs": round(nl * b * d * es / (tot * 1e-3) / 1e9, 1)}
     dom = max(per, key=lambda sl: P_stats[sl][1])
+    traffic = measured_wide_traffic(n, d, k, b) or {}
+    for sl in per:
+        if sl in traffic:
+            per[sl]["traffic"] = traffic[sl]
     roofline = {"bound": "hbm", "achieved": per[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(per[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel": names[dom], "avg_ms": per[dom]["avg_ms"],
+                "traffic": traffic.get(dom),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "kernel": names[dom], "avg_ms": per[dom]["avg_ms"],
                 "alg_bytes_per_launch": b * d * es, "launches": per[dom]["launches"],
                 "other_kernels": [per[sl] for sl in per if sl != dom]}
     out = {"metric": METRIC, "value": round(xbytes / dt / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
